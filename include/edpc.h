@@ -1,0 +1,217 @@
+/*
+ * edpc.h -- C ABI of the MI355X library for the online-adaptive byte-model
+ * compressor of "EDPC: Efficient Dual-path Parallel Compression"
+ * (arXiv 2507.18969).
+ *
+ * The method (Sec. 2.1, Algorithm 1): each byte x_i of a stream is coded
+ * with the probability Pr(i) = P(x_i | x_{i-t} .. x_{i-1}) that a small
+ * network predicts from the t previous bytes (Eq. 1); after coding, the
+ * network takes one gradient step on the cross entropy of that prediction
+ * (Eq. 2), so the decoder, replaying the same steps from the same random
+ * start, reproduces every probability bit for bit.  Many streams ("batch"
+ * b, Secs. 3.1.2 and 3.2) advance in lockstep and share one model; each
+ * stream owns its slice U_s of the Feature Distribution Matrix (Eq. 15).
+ *
+ * The network (all dimensions in edpc_config):
+ *   byte embedding of the t previous bytes, concatenated oldest first
+ *   (F = context * embed) -> Latent Transformation Engine: X' = W1 X + b1
+ *   (Eq. 14), Y = bmm(X', U) (Eq. 15), X'' = W2 Y + b2 (Eq. 16) ->
+ *   `blocks` Multi-path Byte Refinement Blocks (Eqs. 9-13: LayerNorm,
+ *   `branches` parallel linear paths fused by an element-wise product,
+ *   GeLU, output linear, residual) -> linear head to 256 logits -> softmax.
+ *
+ * Everything below runs on one GPU.  Conventions for every function:
+ *   - `d_` pointers are device memory, `h_` pointers host memory; all
+ *     buffers stay owned by the caller and no pointer is retained after
+ *     the call returns, except where a session keeps its input (stated).
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *   - Functions return an edpc_status; on failure edpc_last_error() gives a
+ *     thread-local message.  Nothing aborts the process.
+ *   - Handles (edpc_model, edpc_session) are not thread-safe.
+ *   - Results are deterministic: no floating-point atomics; every reduction
+ *     has a fixed order fixed by the kernel configuration, which is written
+ *     into the container so that the decoder reproduces the encoder.
+ */
+#ifndef EDPC_H
+#define EDPC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EDPC_ABI_VERSION 1
+
+typedef enum {
+  EDPC_OK = 0,
+  EDPC_E_INVALID_ARG = -1,  /* bad argument or configuration */
+  EDPC_E_NOMEM = -2,        /* device or host allocation failed */
+  EDPC_E_CAPACITY = -3,     /* output buffer too small; required size returned */
+  EDPC_E_CORRUPT = -4,      /* container malformed or truncated */
+  EDPC_E_CHECKSUM = -5,     /* CRC mismatch (header or decoded data) */
+  EDPC_E_UNSUPPORTED = -6,  /* format version / device / kernel config mismatch */
+  EDPC_E_DEVICE = -7        /* HIP runtime error */
+} edpc_status;
+
+/* Operand type of the dense layers' matrix products.  FP32: every step in
+ * FP32.  BF16: the operands of the embedding->LTE, LTE-up, refinement-block
+ * and head products and of their adjoint products are BF16 with FP32
+ * accumulation; master weights, Adam state, LayerNorm statistics, GeLU,
+ * softmax, the FDM product and the CDF stay FP32. */
+typedef enum { EDPC_FP32 = 0, EDPC_BF16 = 1 } edpc_precision;
+
+/* edpc_config.flags */
+#define EDPC_CFG_ZERO_HEAD 0x1u /* head weights start at zero (with lr = 0 the
+                                   model predicts exactly 1/256: a test case) */
+
+typedef struct {
+  uint32_t struct_size; /* sizeof(edpc_config) */
+  uint32_t context;     /* t: bytes of history (Algorithm 1), 1..256 */
+  uint32_t embed;       /* embedding width E; F = context * embed */
+  uint32_t latent;      /* F' of the LTE (Eq. 14), multiple of 16 */
+  uint32_t blocks;      /* number of refinement blocks, 0..16 */
+  uint32_t hidden;      /* hidden width of each branch, multiple of 16 */
+  uint32_t branches;    /* k parallel paths per block (Eq. 10), 1..3 */
+  uint32_t cdf_bits;    /* CDF total 2^cdf_bits; only 16 is supported */
+  uint32_t precision;   /* edpc_precision */
+  uint32_t flags;       /* EDPC_CFG_* */
+  float lr, beta1, beta2, eps; /* Adam (Sec. 4.1: lr 1e-3) */
+  uint64_t seed;        /* counter-RNG seed of the random initialisation */
+} edpc_config;
+
+const char* edpc_status_string(int status);
+const char* edpc_last_error(void);
+int edpc_abi_version(void);
+
+/* Default configuration: context 16, embed 16, latent 64, 2 blocks of hidden
+ * 128, 2 branches, 16-bit CDF, FP32, Adam(1e-3, 0.9, 0.999, 1e-8), seed 0. */
+edpc_status edpc_config_default(edpc_config* cfg);
+/* EDPC_OK if the library can run `cfg`; EDPC_E_INVALID_ARG otherwise. */
+edpc_status edpc_config_validate(const edpc_config* cfg);
+
+/* ------------------------------------------------------------------------
+ * Whole-input codec.  Input: n_streams byte streams concatenated in d_in,
+ * lengths in h_lens.  Output: one container (header + per-stream payloads)
+ * in d_out.  These calls synchronise `stream` before returning.
+ * ---------------------------------------------------------------------- */
+
+/* Upper bound of the container size for these lengths (bytes). */
+edpc_status edpc_encode_bound(const edpc_config* cfg, const uint64_t* h_lens,
+                              size_t n_streams, size_t* bound);
+
+/* Compress.  n_streams >= 1; zero-length streams are allowed.  If out_cap is
+ * too small returns EDPC_E_CAPACITY with the required size in *out_len. */
+edpc_status edpc_encode(const edpc_config* cfg, const uint8_t* d_in,
+                        const uint64_t* h_lens, size_t n_streams,
+                        uint8_t* d_out, size_t out_cap, size_t* out_len,
+                        void* stream);
+
+/* Parse a container header held in host memory (at least the header bytes;
+ * *header_len receives its size, or the size needed if in_len is short, in
+ * which case EDPC_E_CORRUPT is returned).  cfg/n_streams/h_lens may be NULL;
+ * h_lens needs lens_cap >= n_streams entries. */
+edpc_status edpc_decode_info(const uint8_t* h_in, size_t in_len, edpc_config* cfg,
+                             size_t* n_streams, uint64_t* h_lens, size_t lens_cap,
+                             size_t* header_len, size_t* decoded_len);
+
+/* Decompress a container held in device memory into d_out (streams
+ * concatenated).  Verifies the per-stream CRC32 of the decoded bytes. */
+edpc_status edpc_decode(const uint8_t* d_in, size_t in_len, uint8_t* d_out,
+                        size_t out_cap, size_t* out_len, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Step-granular sessions: the same codec, advanced a number of model steps
+ * at a time (for streaming callers and for timing).  A session keeps
+ * reading d_in (encoder) or d_in/d_out (decoder) until it is destroyed.
+ * ---------------------------------------------------------------------- */
+typedef struct edpc_session edpc_session;
+
+edpc_status edpc_encoder_begin(const edpc_config* cfg, const uint8_t* d_in,
+                               const uint64_t* h_lens, size_t n_streams,
+                               void* stream, edpc_session** out);
+edpc_status edpc_decoder_begin(const uint8_t* d_in, size_t in_len, uint8_t* d_out,
+                               size_t out_cap, void* stream, edpc_session** out);
+/* Enqueue up to n_steps more steps (asynchronous); *done = steps taken. */
+edpc_status edpc_session_run(edpc_session* s, uint64_t n_steps, uint64_t* done);
+/* Current step and total steps (= longest stream). */
+edpc_status edpc_session_progress(const edpc_session* s, uint64_t* step,
+                                  uint64_t* total);
+/* Encoder: finish all remaining steps, flush, write the container. */
+edpc_status edpc_encoder_finish(edpc_session* s, uint8_t* d_out, size_t out_cap,
+                                size_t* out_len);
+/* Decoder: finish all remaining steps, check CRCs; *out_len = bytes decoded. */
+edpc_status edpc_decoder_finish(edpc_session* s, size_t* out_len);
+void edpc_session_destroy(edpc_session* s);
+
+/* ------------------------------------------------------------------------
+ * Model-level access: one step of the network on explicit contexts.
+ * ---------------------------------------------------------------------- */
+typedef struct edpc_model edpc_model;
+
+/* edpc_model_step flags */
+#define EDPC_STEP_BACKWARD 0x1u /* compute gradients of the mean cross entropy */
+#define EDPC_STEP_UPDATE 0x2u   /* ... and apply one Adam step (implies BACKWARD) */
+#define EDPC_STEP_KEEP_FDM_GRAD 0x4u /* store dL/dU of each row's slot (no update) */
+
+/* A model with n_slots FDM slices (one per stream) accepting up to max_rows
+ * rows per step.  Parameters are initialised from cfg->seed. */
+edpc_status edpc_model_create(const edpc_config* cfg, size_t n_slots,
+                              size_t max_rows, edpc_model** out);
+void edpc_model_destroy(edpc_model* m);
+
+/* One step on `rows` rows.  d_ctx: [rows, context] bytes, oldest first.
+ * d_target: [rows] bytes (required with BACKWARD/UPDATE, else may be NULL).
+ * h_slot: [rows] distinct FDM slot indices < n_slots (host memory).
+ * Optional outputs: d_probs [rows, 256] FP32 softmax, d_cum [rows, 257]
+ * integer CDF (the coder's table), d_loss [1] FP32 mean cross entropy.
+ * Asynchronous on `stream`. */
+edpc_status edpc_model_step(edpc_model* m, const uint8_t* d_ctx,
+                            const uint8_t* d_target, const uint32_t* h_slot,
+                            size_t rows, float* d_probs, uint32_t* d_cum,
+                            float* d_loss, uint32_t flags, void* stream);
+
+/* Tensor access (synchronous).  Tensors are numbered 0..count-1 in storage
+ * order; the last one is the FDM "U" with n_slots*latent*latent entries. */
+#define EDPC_KIND_PARAM 0u
+#define EDPC_KIND_GRAD 1u
+#define EDPC_KIND_ADAM_M 2u
+#define EDPC_KIND_ADAM_V 3u
+edpc_status edpc_model_tensor_count(const edpc_model* m, size_t* n);
+edpc_status edpc_model_tensor_info(const edpc_model* m, size_t idx, char* name,
+                                   size_t name_cap, size_t* numel);
+edpc_status edpc_model_read(const edpc_model* m, uint32_t kind, size_t idx,
+                            float* h_dst, size_t numel);
+edpc_status edpc_model_write(edpc_model* m, uint32_t kind, size_t idx,
+                             const float* h_src, size_t numel);
+/* Adam step counter (number of updates taken). */
+edpc_status edpc_model_get_step(const edpc_model* m, uint64_t* tau);
+edpc_status edpc_model_set_step(edpc_model* m, uint64_t tau);
+
+/* ------------------------------------------------------------------------
+ * Range coder alone (the "Arithmetic Coding" step of Sec. 2.1): codes
+ * symbols with caller-supplied 16-bit CDF tables, one coder per stream.
+ * d_cum: [n_steps, n_streams, 257] u32, cum[0] = 0, cum[256] = 65536,
+ * strictly increasing.  d_sym: [n_steps, n_streams] bytes.  Stream s writes
+ * its payload at d_out + s*cap_per_stream (cap_per_stream >= 2*n_steps + 2)
+ * and its length to h_out_lens[s].  Decoding reverses it.  Synchronous.
+ * ---------------------------------------------------------------------- */
+edpc_status edpc_rc_encode(const uint32_t* d_cum, const uint8_t* d_sym,
+                           size_t n_steps, size_t n_streams, uint8_t* d_out,
+                           size_t cap_per_stream, uint32_t* h_out_lens, void* stream);
+edpc_status edpc_rc_decode(const uint32_t* d_cum, const uint8_t* d_in,
+                           const uint32_t* h_in_lens, size_t cap_per_stream,
+                           size_t n_steps, size_t n_streams, uint8_t* d_sym,
+                           void* stream);
+/* The same coder compiled for the host (reference and CPU tests). */
+edpc_status edpc_rc_encode_host(const uint32_t* h_cum, const uint8_t* h_sym,
+                                size_t n_steps, uint8_t* h_out, size_t cap,
+                                size_t* out_len);
+edpc_status edpc_rc_decode_host(const uint32_t* h_cum, const uint8_t* h_in,
+                                size_t in_len, size_t n_steps, uint8_t* h_sym);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EDPC_H */

@@ -1,0 +1,374 @@
+"""Python binding of libedpc (MI355X / gfx950 HIP library).
+
+Thin argument marshalling over the C ABI declared in include/edpc.h: every
+function here has the name of the C entry point it calls; PyTorch tensors
+provide device memory and the current HIP stream.  All computation happens
+in the library's HIP kernels; if the built library is missing, loading fails
+loudly (there is no fallback).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libedpc.so")
+
+EDPC_OK = 0
+STATUS = {0: "EDPC_OK", -1: "EDPC_E_INVALID_ARG", -2: "EDPC_E_NOMEM", -3: "EDPC_E_CAPACITY",
+          -4: "EDPC_E_CORRUPT", -5: "EDPC_E_CHECKSUM", -6: "EDPC_E_UNSUPPORTED",
+          -7: "EDPC_E_DEVICE"}
+EDPC_FP32, EDPC_BF16 = 0, 1
+EDPC_CFG_ZERO_HEAD = 0x1
+EDPC_STEP_BACKWARD, EDPC_STEP_UPDATE, EDPC_STEP_KEEP_FDM_GRAD = 0x1, 0x2, 0x4
+EDPC_KIND_PARAM, EDPC_KIND_GRAD, EDPC_KIND_ADAM_M, EDPC_KIND_ADAM_V = 0, 1, 2, 3
+
+#: every symbol include/edpc.h declares
+EXPORTS = [
+    "edpc_status_string", "edpc_last_error", "edpc_abi_version", "edpc_config_default",
+    "edpc_config_validate", "edpc_encode_bound", "edpc_encode", "edpc_decode_info",
+    "edpc_decode", "edpc_encoder_begin", "edpc_decoder_begin", "edpc_session_run",
+    "edpc_session_progress", "edpc_encoder_finish", "edpc_decoder_finish",
+    "edpc_session_destroy", "edpc_model_create", "edpc_model_destroy", "edpc_model_step",
+    "edpc_model_tensor_count", "edpc_model_tensor_info", "edpc_model_read", "edpc_model_write",
+    "edpc_model_get_step", "edpc_model_set_step", "edpc_rc_encode", "edpc_rc_decode",
+    "edpc_rc_encode_host", "edpc_rc_decode_host",
+]
+
+
+class EdpcError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class edpc_config(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("context", ctypes.c_uint32),
+                ("embed", ctypes.c_uint32), ("latent", ctypes.c_uint32),
+                ("blocks", ctypes.c_uint32), ("hidden", ctypes.c_uint32),
+                ("branches", ctypes.c_uint32), ("cdf_bits", ctypes.c_uint32),
+                ("precision", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float), ("seed", ctypes.c_uint64)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+_P = ctypes.c_void_p
+_SZ = ctypes.c_size_t
+_U64P = ctypes.POINTER(ctypes.c_uint64)
+_U32P = ctypes.POINTER(ctypes.c_uint32)
+_SZP = ctypes.POINTER(ctypes.c_size_t)
+
+
+def lib() -> ctypes.CDLL:
+    """Load libedpc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_2507_18969_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    cfgp = ctypes.POINTER(edpc_config)
+    sig = {
+        "edpc_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+        "edpc_last_error": (ctypes.c_char_p, []),
+        "edpc_abi_version": (ctypes.c_int, []),
+        "edpc_config_default": (ctypes.c_int, [cfgp]),
+        "edpc_config_validate": (ctypes.c_int, [cfgp]),
+        "edpc_encode_bound": (ctypes.c_int, [cfgp, _U64P, _SZ, _SZP]),
+        "edpc_encode": (ctypes.c_int, [cfgp, _P, _U64P, _SZ, _P, _SZ, _SZP, _P]),
+        "edpc_decode_info": (ctypes.c_int, [_P, _SZ, cfgp, _SZP, _U64P, _SZ, _SZP, _SZP]),
+        "edpc_decode": (ctypes.c_int, [_P, _SZ, _P, _SZ, _SZP, _P]),
+        "edpc_encoder_begin": (ctypes.c_int, [cfgp, _P, _U64P, _SZ, _P, ctypes.POINTER(_P)]),
+        "edpc_decoder_begin": (ctypes.c_int, [_P, _SZ, _P, _SZ, _P, ctypes.POINTER(_P)]),
+        "edpc_session_run": (ctypes.c_int, [_P, ctypes.c_uint64, _U64P]),
+        "edpc_session_progress": (ctypes.c_int, [_P, _U64P, _U64P]),
+        "edpc_encoder_finish": (ctypes.c_int, [_P, _P, _SZ, _SZP]),
+        "edpc_decoder_finish": (ctypes.c_int, [_P, _SZP]),
+        "edpc_session_destroy": (None, [_P]),
+        "edpc_model_create": (ctypes.c_int, [cfgp, _SZ, _SZ, ctypes.POINTER(_P)]),
+        "edpc_model_destroy": (None, [_P]),
+        "edpc_model_step": (ctypes.c_int, [_P, _P, _P, _U32P, _SZ, _P, _P, _P, ctypes.c_uint32, _P]),
+        "edpc_model_tensor_count": (ctypes.c_int, [_P, _SZP]),
+        "edpc_model_tensor_info": (ctypes.c_int, [_P, _SZ, ctypes.c_char_p, _SZ, _SZP]),
+        "edpc_model_read": (ctypes.c_int, [_P, ctypes.c_uint32, _SZ, _P, _SZ]),
+        "edpc_model_write": (ctypes.c_int, [_P, ctypes.c_uint32, _SZ, _P, _SZ]),
+        "edpc_model_get_step": (ctypes.c_int, [_P, _U64P]),
+        "edpc_model_set_step": (ctypes.c_int, [_P, ctypes.c_uint64]),
+        "edpc_rc_encode": (ctypes.c_int, [_P, _P, _SZ, _SZ, _P, _SZ, _U32P, _P]),
+        "edpc_rc_decode": (ctypes.c_int, [_P, _P, _U32P, _SZ, _SZ, _SZ, _P, _P]),
+        "edpc_rc_encode_host": (ctypes.c_int, [_P, _P, _SZ, _P, _SZ, _SZP]),
+        "edpc_rc_decode_host": (ctypes.c_int, [_P, _P, _SZ, _SZ, _P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(st: int):
+    if st != EDPC_OK:
+        raise EdpcError(st, lib().edpc_last_error().decode())
+
+
+def _stream(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _np_ptr(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def edpc_config_default(**overrides) -> edpc_config:
+    c = edpc_config()
+    _check(lib().edpc_config_default(ctypes.byref(c)))
+    for k, v in overrides.items():
+        if k == "precision" and isinstance(v, str):
+            v = {"fp32": EDPC_FP32, "bf16": EDPC_BF16}[v]
+        if k == "zero_head":
+            c.flags = (c.flags | EDPC_CFG_ZERO_HEAD) if v else (c.flags & ~EDPC_CFG_ZERO_HEAD)
+            continue
+        setattr(c, k, v)
+    return c
+
+
+def edpc_config_validate(cfg: edpc_config):
+    _check(lib().edpc_config_validate(ctypes.byref(cfg)))
+
+
+def _lens(lens) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(lens, dtype=np.uint64))
+
+
+def edpc_encode_bound(cfg: edpc_config, lens) -> int:
+    ln = _lens(lens)
+    out = ctypes.c_size_t()
+    _check(lib().edpc_encode_bound(ctypes.byref(cfg), ln.ctypes.data_as(_U64P), len(ln),
+                                   ctypes.byref(out)))
+    return out.value
+
+
+def edpc_encode(cfg: edpc_config, d_in, lens, stream=None):
+    """Compress device bytes ``d_in`` (uint8 tensor, streams concatenated);
+    returns the container as a uint8 device tensor."""
+    import torch
+    ln = _lens(lens)
+    cap = edpc_encode_bound(cfg, ln)
+    out = torch.empty(cap, dtype=torch.uint8, device=d_in.device)
+    n = ctypes.c_size_t()
+    _check(lib().edpc_encode(ctypes.byref(cfg), _dptr(d_in), ln.ctypes.data_as(_U64P), len(ln),
+                             _dptr(out), cap, ctypes.byref(n), _stream(stream)))
+    return out[: n.value]
+
+
+def edpc_decode_info(h_in: bytes):
+    """(config, lens, header_len, decoded_len) from container bytes in host memory."""
+    buf = np.frombuffer(bytes(h_in), dtype=np.uint8)
+    cfg = edpc_config()
+    n = ctypes.c_size_t()
+    hl = ctypes.c_size_t()
+    dl = ctypes.c_size_t()
+    _check(lib().edpc_decode_info(_np_ptr(buf), len(buf), ctypes.byref(cfg), ctypes.byref(n),
+                                  None, 0, ctypes.byref(hl), ctypes.byref(dl)))
+    lens = np.zeros(n.value, dtype=np.uint64)
+    _check(lib().edpc_decode_info(_np_ptr(buf), len(buf), None, None,
+                                  lens.ctypes.data_as(_U64P), len(lens), None, None))
+    return cfg, lens.astype(np.int64), hl.value, dl.value
+
+
+def _header_bytes(container) -> bytes:
+    head = container[:16].cpu().numpy().tobytes()
+    hl = int.from_bytes(head[8:12], "little")
+    return container[: min(hl, container.numel())].cpu().numpy().tobytes()
+
+
+def edpc_decode(container, stream=None):
+    """Decompress a container held in a uint8 device tensor."""
+    import torch
+    _, lens, _, total = edpc_decode_info(_header_bytes(container))
+    out = torch.empty(max(total, 1), dtype=torch.uint8, device=container.device)
+    n = ctypes.c_size_t()
+    _check(lib().edpc_decode(_dptr(container), container.numel(), _dptr(out), out.numel(),
+                             ctypes.byref(n), _stream(stream)))
+    return out[: n.value], lens
+
+
+class Session:
+    """edpc_encoder_begin / edpc_decoder_begin ... edpc_session_destroy."""
+
+    def __init__(self, handle, keep):
+        self.h = handle
+        self._keep = keep  # tensors the session reads until destroyed
+
+    def edpc_session_run(self, n_steps: int) -> int:
+        done = ctypes.c_uint64()
+        _check(lib().edpc_session_run(self.h, n_steps, ctypes.byref(done)))
+        return done.value
+
+    def edpc_session_progress(self):
+        a, b = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().edpc_session_progress(self.h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def edpc_encoder_finish(self, bound: int):
+        import torch
+        dev = self._keep[0].device
+        out = torch.empty(bound, dtype=torch.uint8, device=dev)
+        n = ctypes.c_size_t()
+        _check(lib().edpc_encoder_finish(self.h, _dptr(out), bound, ctypes.byref(n)))
+        return out[: n.value]
+
+    def edpc_decoder_finish(self) -> int:
+        n = ctypes.c_size_t()
+        _check(lib().edpc_decoder_finish(self.h, ctypes.byref(n)))
+        return n.value
+
+    def edpc_session_destroy(self):
+        if self.h:
+            lib().edpc_session_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.edpc_session_destroy()
+        except Exception:
+            pass
+
+
+def edpc_encoder_begin(cfg: edpc_config, d_in, lens, stream=None) -> Session:
+    ln = _lens(lens)
+    h = ctypes.c_void_p()
+    _check(lib().edpc_encoder_begin(ctypes.byref(cfg), _dptr(d_in), ln.ctypes.data_as(_U64P),
+                                    len(ln), _stream(stream), ctypes.byref(h)))
+    return Session(h, (d_in,))
+
+
+def edpc_decoder_begin(container, d_out, stream=None) -> Session:
+    h = ctypes.c_void_p()
+    _check(lib().edpc_decoder_begin(_dptr(container), container.numel(), _dptr(d_out),
+                                    d_out.numel(), _stream(stream), ctypes.byref(h)))
+    return Session(h, (container, d_out))
+
+
+class Model:
+    """edpc_model_create ... edpc_model_destroy, with tensor access by name."""
+
+    def __init__(self, cfg: edpc_config, n_slots: int, max_rows: int):
+        self.cfg = cfg
+        h = ctypes.c_void_p()
+        _check(lib().edpc_model_create(ctypes.byref(cfg), n_slots, max_rows, ctypes.byref(h)))
+        self.h = h
+        self.n_slots = n_slots
+        n = ctypes.c_size_t()
+        _check(lib().edpc_model_tensor_count(self.h, ctypes.byref(n)))
+        self.names, self.numel = [], []
+        buf = ctypes.create_string_buffer(64)
+        for i in range(n.value):
+            ne = ctypes.c_size_t()
+            _check(lib().edpc_model_tensor_info(self.h, i, buf, 64, ctypes.byref(ne)))
+            self.names.append(buf.value.decode())
+            self.numel.append(ne.value)
+
+    def edpc_model_destroy(self):
+        if self.h:
+            lib().edpc_model_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.edpc_model_destroy()
+        except Exception:
+            pass
+
+    def edpc_model_step(self, ctx, target, slots, probs=None, cum=None, loss=None, flags=0,
+                        stream=None):
+        sl = np.ascontiguousarray(np.asarray(slots, dtype=np.uint32))
+        _check(lib().edpc_model_step(
+            self.h, _dptr(ctx), _dptr(target) if target is not None else None,
+            sl.ctypes.data_as(_U32P), len(sl),
+            _dptr(probs) if probs is not None else None,
+            _dptr(cum) if cum is not None else None,
+            _dptr(loss) if loss is not None else None, flags, _stream(stream)))
+
+    def index(self, name: str) -> int:
+        return self.names.index(name)
+
+    def edpc_model_read(self, name: str, kind: int = EDPC_KIND_PARAM) -> np.ndarray:
+        i = self.index(name)
+        out = np.empty(self.numel[i], dtype=np.float32)
+        _check(lib().edpc_model_read(self.h, kind, i, _np_ptr(out), out.size))
+        return out
+
+    def edpc_model_write(self, name: str, values, kind: int = EDPC_KIND_PARAM):
+        i = self.index(name)
+        a = np.ascontiguousarray(np.asarray(values, dtype=np.float32).reshape(-1))
+        _check(lib().edpc_model_write(self.h, kind, i, _np_ptr(a), a.size))
+
+    def edpc_model_get_step(self) -> int:
+        t = ctypes.c_uint64()
+        _check(lib().edpc_model_get_step(self.h, ctypes.byref(t)))
+        return t.value
+
+    def edpc_model_set_step(self, tau: int):
+        _check(lib().edpc_model_set_step(self.h, tau))
+
+
+def edpc_model_create(cfg: edpc_config, n_slots: int, max_rows: int) -> Model:
+    return Model(cfg, n_slots, max_rows)
+
+
+def edpc_rc_encode(d_cum, d_sym, cap_per_stream: int, stream=None):
+    """Range-code [n_steps, n_streams] symbols with [n_steps, n_streams, 257]
+    u32 CDFs; returns (payload tensor [n_streams, cap], lengths)."""
+    import torch
+    n_steps, n_streams = d_sym.shape
+    out = torch.zeros((n_streams, cap_per_stream), dtype=torch.uint8, device=d_sym.device)
+    lens = np.zeros(n_streams, dtype=np.uint32)
+    _check(lib().edpc_rc_encode(_dptr(d_cum), _dptr(d_sym), n_steps, n_streams, _dptr(out),
+                                cap_per_stream, lens.ctypes.data_as(_U32P), _stream(stream)))
+    return out, lens
+
+
+def edpc_rc_decode(d_cum, d_payload, lens, stream=None):
+    import torch
+    n_steps, n_streams = d_cum.shape[0], d_cum.shape[1]
+    sym = torch.empty((n_steps, n_streams), dtype=torch.uint8, device=d_cum.device)
+    ln = np.ascontiguousarray(np.asarray(lens, dtype=np.uint32))
+    _check(lib().edpc_rc_decode(_dptr(d_cum), _dptr(d_payload), ln.ctypes.data_as(_U32P),
+                                d_payload.shape[1], n_steps, n_streams, _dptr(sym),
+                                _stream(stream)))
+    return sym
+
+
+def edpc_rc_encode_host(cum: np.ndarray, sym: np.ndarray) -> bytes:
+    cum = np.ascontiguousarray(cum, dtype=np.uint32)
+    sym = np.ascontiguousarray(sym, dtype=np.uint8)
+    cap = 2 * len(sym) + 2
+    out = np.zeros(cap, dtype=np.uint8)
+    n = ctypes.c_size_t()
+    _check(lib().edpc_rc_encode_host(_np_ptr(cum), _np_ptr(sym), len(sym), _np_ptr(out), cap,
+                                     ctypes.byref(n)))
+    return out[: n.value].tobytes()
+
+
+def edpc_rc_decode_host(cum: np.ndarray, payload: bytes, n_steps: int) -> np.ndarray:
+    cum = np.ascontiguousarray(cum, dtype=np.uint32)
+    buf = np.frombuffer(bytes(payload) + b"\0", dtype=np.uint8)
+    sym = np.zeros(max(n_steps, 1), dtype=np.uint8)
+    _check(lib().edpc_rc_decode_host(_np_ptr(cum), _np_ptr(buf), len(payload), n_steps,
+                                     _np_ptr(sym)))
+    return sym[:n_steps]

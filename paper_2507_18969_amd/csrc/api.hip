@@ -1,0 +1,463 @@
+// extern "C" boundary: argument checks, error translation, handles.
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "codec.h"
+
+using namespace edpc;
+
+struct edpc_model {
+  std::unique_ptr<Model> m;
+};
+struct edpc_session {
+  std::unique_ptr<Session> s;
+};
+
+namespace {
+thread_local std::string g_last_error;
+
+edpc_status set_err(edpc_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+template <class F>
+edpc_status guarded(F&& f) {
+  try {
+    g_last_error.clear();
+    return f();
+  } catch (const Error& e) {
+    return set_err(e.status, e.msg);
+  } catch (const std::bad_alloc&) {
+    return set_err(EDPC_E_NOMEM, "host allocation failed");
+  } catch (...) {
+    return set_err(EDPC_E_DEVICE, "unexpected internal error");
+  }
+}
+
+hipStream_t S(void* p) { return (hipStream_t)p; }
+}  // namespace
+
+extern "C" {
+
+const char* edpc_status_string(int st) {
+  switch (st) {
+    case EDPC_OK: return "ok";
+    case EDPC_E_INVALID_ARG: return "invalid argument";
+    case EDPC_E_NOMEM: return "out of memory";
+    case EDPC_E_CAPACITY: return "output buffer too small";
+    case EDPC_E_CORRUPT: return "corrupt or truncated container";
+    case EDPC_E_CHECKSUM: return "checksum mismatch";
+    case EDPC_E_UNSUPPORTED: return "unsupported format, device or kernel configuration";
+    case EDPC_E_DEVICE: return "device error";
+  }
+  return "unknown status";
+}
+
+const char* edpc_last_error(void) { return g_last_error.c_str(); }
+int edpc_abi_version(void) { return EDPC_ABI_VERSION; }
+
+edpc_status edpc_config_default(edpc_config* cfg) {
+  if (!cfg) return set_err(EDPC_E_INVALID_ARG, "cfg is NULL");
+  std::memset(cfg, 0, sizeof(*cfg));
+  cfg->struct_size = sizeof(edpc_config);
+  cfg->context = 16;
+  cfg->embed = 16;
+  cfg->latent = 64;
+  cfg->blocks = 2;
+  cfg->hidden = 128;
+  cfg->branches = 2;
+  cfg->cdf_bits = 16;
+  cfg->precision = EDPC_FP32;
+  cfg->flags = 0;
+  cfg->lr = 1e-3f;
+  cfg->beta1 = 0.9f;
+  cfg->beta2 = 0.999f;
+  cfg->eps = 1e-8f;
+  cfg->seed = 0;
+  return EDPC_OK;
+}
+
+edpc_status edpc_config_validate(const edpc_config* cfg) {
+  return guarded([&] {
+    if (!cfg) fail(EDPC_E_INVALID_ARG, "cfg is NULL");
+    Model::validate(*cfg);
+    return EDPC_OK;
+  });
+}
+
+edpc_status edpc_encode_bound(const edpc_config* cfg, const uint64_t* h_lens, size_t n,
+                              size_t* bound) {
+  return guarded([&] {
+    if (!cfg || !bound || (n && !h_lens)) fail(EDPC_E_INVALID_ARG, "NULL argument");
+    Model::validate(*cfg);
+    if (n == 0) fail(EDPC_E_INVALID_ARG, "n_streams must be >= 1");
+    *bound = encode_bound(*cfg, h_lens, n);
+    return EDPC_OK;
+  });
+}
+
+edpc_status edpc_encoder_begin(const edpc_config* cfg, const uint8_t* d_in, const uint64_t* h_lens,
+                               size_t n, void* stream, edpc_session** out) {
+  return guarded([&] {
+    if (!cfg || !out || !h_lens) fail(EDPC_E_INVALID_ARG, "NULL argument");
+    *out = nullptr;
+    uint64_t total = 0;
+    for (size_t i = 0; i < n; ++i) total += h_lens[i];
+    if (total && !d_in) fail(EDPC_E_INVALID_ARG, "d_in is NULL");
+    std::unique_ptr<edpc_session> h(new edpc_session());
+    h->s = encoder_begin(*cfg, d_in, h_lens, n, S(stream), nullptr);
+    *out = h.release();
+    return EDPC_OK;
+  });
+}
+
+edpc_status edpc_decoder_begin(const uint8_t* d_in, size_t in_len, uint8_t* d_out, size_t out_cap,
+                               void* stream, edpc_session** out) {
+  return guarded([&] {
+    if (!d_in || !out) fail(EDPC_E_INVALID_ARG, "NULL argument");
+    *out = nullptr;
+    std::unique_ptr<edpc_session> h(new edpc_session());
+    h->s = decoder_begin(d_in, in_len, d_out, out_cap, S(stream));
+    *out = h.release();
+    return EDPC_OK;
+  });
+}
+
+edpc_status edpc_session_run(edpc_session* s, uint64_t n_steps, uint64_t* done) {
+  return guarded([&] {
+    if (!s || !s->s) fail(EDPC_E_INVALID_ARG, "NULL session");
+    const uint64_t before = s->s->next;
+    s->s->run(n_steps);
+    if (done) *done = s->s->next - before;
+    return EDPC_OK;
+  });
+}
+
+edpc_status edpc_session_progress(const edpc_session* s, uint64_t* step, uint64_t* total) {
+  if (!s || !s->s) return set_err(EDPC_E_INVALID_ARG, "NULL session");
+  if (step) *step = s->s->next;
+  if (total) *total = s->s->maxlen;
+  return EDPC_OK;
+}
+
+edpc_status edpc_encoder_finish(edpc_session* s, uint8_t* d_out, size_t out_cap, size_t* out_len) {
+  return guarded([&] {
+    if (!s || !s->s || s->s->decoding) fail(EDPC_E_INVALID_ARG, "not an encoder session");
+    if (!out_len) fail(EDPC_E_INVALID_ARG, "out_len is NULL");
+    try {
+      *out_len = encoder_finish(*s->s, d_out, out_cap);
+    } catch (const Error& e) {
+      if (e.status == EDPC_E_CAPACITY) *out_len = s->s->out_cap;
+      throw;
+    }
+    return EDPC_OK;
+  });
+}
+
+edpc_status edpc_decoder_finish(edpc_session* s, size_t* out_len) {
+  return guarded([&] {
+    if (!s || !s->s || !s->s->decoding) fail(EDPC_E_INVALID_ARG, "not a decoder session");
+    const size_t n = decoder_finish(*s->s);
+    if (out_len) *out_len = n;
+    return EDPC_OK;
+  });
+}
+
+void edpc_session_destroy(edpc_session* s) { delete s; }
+
+edpc_status edpc_encode(const edpc_config* cfg, const uint8_t* d_in, const uint64_t* h_lens,
+                        size_t n, uint8_t* d_out, size_t out_cap, size_t* out_len, void* stream) {
+  edpc_session* s = nullptr;
+  edpc_status st = edpc_encoder_begin(cfg, d_in, h_lens, n, stream, &s);
+  if (st != EDPC_OK) return st;
+  st = edpc_encoder_finish(s, d_out, out_cap, out_len);
+  std::string keep = g_last_error;
+  edpc_session_destroy(s);
+  g_last_error = keep;
+  return st;
+}
+
+edpc_status edpc_decode(const uint8_t* d_in, size_t in_len, uint8_t* d_out, size_t out_cap,
+                        size_t* out_len, void* stream) {
+  edpc_session* s = nullptr;
+  edpc_status st = edpc_decoder_begin(d_in, in_len, d_out, out_cap, stream, &s);
+  if (st != EDPC_OK) return st;
+  st = edpc_decoder_finish(s, out_len);
+  std::string keep = g_last_error;
+  edpc_session_destroy(s);
+  g_last_error = keep;
+  return st;
+}
+
+edpc_status edpc_decode_info(const uint8_t* h_in, size_t in_len, edpc_config* cfg,
+                             size_t* n_streams, uint64_t* h_lens, size_t lens_cap,
+                             size_t* header_len, size_t* decoded_len) {
+  return guarded([&] {
+    if (!h_in) fail(EDPC_E_INVALID_ARG, "h_in is NULL");
+    Header h;
+    size_t need = 0;
+    std::string err;
+    const edpc_status st = parse_header(h_in, in_len, &h, &need, &err);
+    if (header_len) *header_len = need;
+    if (st != EDPC_OK) fail(st, err);
+    if (cfg) *cfg = h.cfg;
+    if (n_streams) *n_streams = h.lens.size();
+    if (h_lens) {
+      if (lens_cap < h.lens.size()) fail(EDPC_E_CAPACITY, "lens_cap smaller than n_streams");
+      std::memcpy(h_lens, h.lens.data(), h.lens.size() * 8);
+    }
+    if (decoded_len) {
+      size_t t = 0;
+      for (uint64_t l : h.lens) t += l;
+      *decoded_len = t;
+    }
+    return EDPC_OK;
+  });
+}
+
+// ---------------------------------------------------------------- model
+
+edpc_status edpc_model_create(const edpc_config* cfg, size_t n_slots, size_t max_rows,
+                              edpc_model** out) {
+  return guarded([&] {
+    if (!cfg || !out) fail(EDPC_E_INVALID_ARG, "NULL argument");
+    *out = nullptr;
+    std::unique_ptr<edpc_model> h(new edpc_model());
+    h->m.reset(new Model(*cfg, n_slots, max_rows, nullptr));
+    h->m->init_params(nullptr);
+    h->m->build_tables(nullptr);
+    hip_check(hipDeviceSynchronize(), "model create");
+    *out = h.release();
+    return EDPC_OK;
+  });
+}
+
+void edpc_model_destroy(edpc_model* m) {
+  if (m) (void)hipDeviceSynchronize();
+  delete m;
+}
+
+edpc_status edpc_model_step(edpc_model* mh, const uint8_t* d_ctx, const uint8_t* d_target,
+                            const uint32_t* h_slot, size_t rows, float* d_probs, uint32_t* d_cum,
+                            float* d_loss, uint32_t flags, void* stream) {
+  return guarded([&] {
+    if (!mh || !mh->m) fail(EDPC_E_INVALID_ARG, "NULL model");
+    Model& m = *mh->m;
+    if (flags & ~(EDPC_STEP_BACKWARD | EDPC_STEP_UPDATE | EDPC_STEP_KEEP_FDM_GRAD))
+      fail(EDPC_E_INVALID_ARG, "unknown step flags");
+    if (rows == 0 || rows > m.max_rows) fail(EDPC_E_INVALID_ARG, "rows must be in 1..max_rows");
+    if (!d_ctx || !h_slot) fail(EDPC_E_INVALID_ARG, "d_ctx and h_slot are required");
+    const bool bwd = flags != 0;
+    if ((bwd || d_loss) && !d_target) fail(EDPC_E_INVALID_ARG, "d_target is required for the loss and gradients");
+    std::vector<char> seen(m.n_slots, 0);
+    for (size_t r = 0; r < rows; ++r) {
+      if (h_slot[r] >= m.n_slots) fail(EDPC_E_INVALID_ARG, "slot index out of range");
+      if (seen[h_slot[r]]) fail(EDPC_E_INVALID_ARG, "slot indices must be distinct");
+      seen[h_slot[r]] = 1;
+    }
+    hipStream_t s = S(stream);
+    hip_check(hipMemcpyAsync(m.ctx, d_ctx, rows * m.C, hipMemcpyDeviceToDevice, s), "copy");
+    if (d_target) hip_check(hipMemcpyAsync(m.tgt, d_target, rows, hipMemcpyDeviceToDevice, s), "copy");
+    hip_check(hipMemcpyAsync(m.slot, h_slot, rows * sizeof(uint32_t), hipMemcpyHostToDevice, s), "copy");
+    StepOutputs out;
+    out.probs = d_probs;
+    out.cum = d_cum;
+    out.loss = d_loss;
+    out.update = (flags & EDPC_STEP_UPDATE) != 0;
+    out.backward = bwd;
+    out.keep_fdm_grad = (flags & EDPC_STEP_KEEP_FDM_GRAD) != 0 && !out.update;
+    if (out.keep_fdm_grad && !m.dUkeep) {
+      void* p = nullptr;
+      hip_check(hipMalloc(&p, m.n_slots * (size_t)m.L * m.L * sizeof(float)), "hipMalloc");
+      m.allocs.push_back(p);
+      m.dUkeep = (float*)p;
+      hip_check(hipMemsetAsync(m.dUkeep, 0, m.n_slots * (size_t)m.L * m.L * sizeof(float), s), "memset");
+    }
+    const uint32_t tau = out.update ? (uint32_t)(m.tau + 1) : (uint32_t)(m.tau > 0 ? m.tau : 1);
+    k_step_explicit(m.st, (int)rows, tau, m.cfg.beta1, m.cfg.beta2, s);
+    StreamIO io;
+    std::memset(&io, 0, sizeof(io));
+    io.slot = m.slot;
+    out.has_target = d_target != nullptr;
+    m.step(MODE_PLAIN, io, out, (int)rows, s);
+    if (out.update) m.tau += 1;
+    return EDPC_OK;
+  });
+}
+
+edpc_status edpc_model_tensor_count(const edpc_model* mh, size_t* n) {
+  if (!mh || !n) return set_err(EDPC_E_INVALID_ARG, "NULL argument");
+  *n = mh->m->tens.size() + 1;
+  return EDPC_OK;
+}
+
+edpc_status edpc_model_tensor_info(const edpc_model* mh, size_t idx, char* name, size_t cap,
+                                   size_t* numel) {
+  if (!mh) return set_err(EDPC_E_INVALID_ARG, "NULL model");
+  const Model& m = *mh->m;
+  std::string nm;
+  size_t ne;
+  if (idx < m.tens.size()) {
+    nm = m.tens[idx].name;
+    ne = m.tens[idx].numel;
+  } else if (idx == m.tens.size()) {
+    nm = "U";
+    ne = m.n_slots * (size_t)m.L * m.L;
+  } else {
+    return set_err(EDPC_E_INVALID_ARG, "tensor index out of range");
+  }
+  if (name && cap) {
+    std::strncpy(name, nm.c_str(), cap - 1);
+    name[cap - 1] = 0;
+  }
+  if (numel) *numel = ne;
+  return EDPC_OK;
+}
+
+static float* tensor_ptr(Model& m, uint32_t kind, size_t idx, size_t* numel, bool for_write) {
+  if (idx < m.tens.size()) {
+    const TensorInfo& t = m.tens[idx];
+    *numel = t.numel;
+    float* base = kind == EDPC_KIND_PARAM ? m.param : kind == EDPC_KIND_GRAD ? m.grad
+                  : kind == EDPC_KIND_ADAM_M ? m.m : kind == EDPC_KIND_ADAM_V ? m.v : nullptr;
+    if (!base) fail(EDPC_E_INVALID_ARG, "unknown tensor kind");
+    return base + t.off;
+  }
+  if (idx == m.tens.size()) {
+    *numel = m.n_slots * (size_t)m.L * m.L;
+    if (kind == EDPC_KIND_PARAM) return m.U;
+    if (kind == EDPC_KIND_ADAM_M) return m.mU;
+    if (kind == EDPC_KIND_ADAM_V) return m.vU;
+    if (kind == EDPC_KIND_GRAD) {
+      if (!m.dUkeep) fail(EDPC_E_INVALID_ARG, "no FDM gradient kept (use EDPC_STEP_KEEP_FDM_GRAD)");
+      if (for_write) fail(EDPC_E_INVALID_ARG, "the FDM gradient is read-only");
+      return m.dUkeep;
+    }
+    fail(EDPC_E_INVALID_ARG, "unknown tensor kind");
+  }
+  fail(EDPC_E_INVALID_ARG, "tensor index out of range");
+}
+
+edpc_status edpc_model_read(const edpc_model* mh, uint32_t kind, size_t idx, float* h_dst,
+                            size_t numel) {
+  return guarded([&] {
+    if (!mh || !h_dst) fail(EDPC_E_INVALID_ARG, "NULL argument");
+    size_t ne = 0;
+    float* p = tensor_ptr(*mh->m, kind, idx, &ne, false);
+    if (numel != ne) fail(EDPC_E_INVALID_ARG, "numel mismatch");
+    hip_check(hipDeviceSynchronize(), "sync");
+    hip_check(hipMemcpy(h_dst, p, ne * sizeof(float), hipMemcpyDeviceToHost), "copy");
+    return EDPC_OK;
+  });
+}
+
+edpc_status edpc_model_write(edpc_model* mh, uint32_t kind, size_t idx, const float* h_src,
+                             size_t numel) {
+  return guarded([&] {
+    if (!mh || !h_src) fail(EDPC_E_INVALID_ARG, "NULL argument");
+    Model& m = *mh->m;
+    size_t ne = 0;
+    float* p = tensor_ptr(m, kind, idx, &ne, true);
+    if (numel != ne) fail(EDPC_E_INVALID_ARG, "numel mismatch");
+    hip_check(hipDeviceSynchronize(), "sync");
+    hip_check(hipMemcpy(p, h_src, ne * sizeof(float), hipMemcpyHostToDevice), "copy");
+    if (kind == EDPC_KIND_PARAM && m.bf16 && idx < m.tens.size()) {
+      const TensorInfo& t = m.tens[idx];
+      k_to_bf16(m.param + t.off, m.p16 + t.off, t.numel, nullptr);
+      hip_check(hipDeviceSynchronize(), "sync");
+    }
+    return EDPC_OK;
+  });
+}
+
+edpc_status edpc_model_get_step(const edpc_model* mh, uint64_t* tau) {
+  if (!mh || !tau) return set_err(EDPC_E_INVALID_ARG, "NULL argument");
+  *tau = mh->m->tau;
+  return EDPC_OK;
+}
+
+edpc_status edpc_model_set_step(edpc_model* mh, uint64_t tau) {
+  if (!mh) return set_err(EDPC_E_INVALID_ARG, "NULL model");
+  mh->m->tau = tau;
+  return EDPC_OK;
+}
+
+// ---------------------------------------------------------------- coder only
+
+edpc_status edpc_rc_encode(const uint32_t* d_cum, const uint8_t* d_sym, size_t n_steps,
+                           size_t n_streams, uint8_t* d_out, size_t cap, uint32_t* h_out_lens,
+                           void* stream) {
+  return guarded([&] {
+    if (!d_cum || !d_sym || !d_out || !h_out_lens) fail(EDPC_E_INVALID_ARG, "NULL argument");
+    if (n_streams == 0) fail(EDPC_E_INVALID_ARG, "n_streams must be >= 1");
+    if (cap < 2 * n_steps + 2) fail(EDPC_E_INVALID_ARG, "cap_per_stream < 2 * n_steps + 2");
+    hipStream_t s = S(stream);
+    uint64_t* d_len = nullptr;
+    hip_check(hipMalloc(&d_len, n_streams * 8), "hipMalloc");
+    k_rc_table_encode(d_cum, d_sym, n_steps, n_streams, d_out, cap, d_len, s);
+    std::vector<uint64_t> l(n_streams);
+    hipError_t e = hipMemcpyAsync(l.data(), d_len, n_streams * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(d_len);
+    hip_check(e, "rc encode");
+    for (size_t i = 0; i < n_streams; ++i) h_out_lens[i] = (uint32_t)l[i];
+    return EDPC_OK;
+  });
+}
+
+edpc_status edpc_rc_decode(const uint32_t* d_cum, const uint8_t* d_in, const uint32_t* h_in_lens,
+                           size_t cap, size_t n_steps, size_t n_streams, uint8_t* d_sym,
+                           void* stream) {
+  return guarded([&] {
+    if (!d_cum || !d_in || !h_in_lens || !d_sym) fail(EDPC_E_INVALID_ARG, "NULL argument");
+    if (n_streams == 0) fail(EDPC_E_INVALID_ARG, "n_streams must be >= 1");
+    hipStream_t s = S(stream);
+    std::vector<uint64_t> l(h_in_lens, h_in_lens + n_streams);
+    uint64_t* d_len = nullptr;
+    hip_check(hipMalloc(&d_len, n_streams * 8), "hipMalloc");
+    hipError_t e = hipMemcpyAsync(d_len, l.data(), n_streams * 8, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+      k_rc_table_decode(d_cum, d_in, d_len, cap, n_steps, n_streams, d_sym, s);
+      e = hipStreamSynchronize(s);
+    }
+    (void)hipFree(d_len);
+    hip_check(e, "rc decode");
+    return EDPC_OK;
+  });
+}
+
+edpc_status edpc_rc_encode_host(const uint32_t* h_cum, const uint8_t* h_sym, size_t n_steps,
+                                uint8_t* h_out, size_t cap, size_t* out_len) {
+  if (!h_cum || (n_steps && !h_sym) || !h_out || !out_len)
+    return set_err(EDPC_E_INVALID_ARG, "NULL argument");
+  if (cap < 2 * n_steps + 2) return set_err(EDPC_E_INVALID_ARG, "cap < 2 * n_steps + 2");
+  RcEnc e;
+  rc_enc_init(e);
+  for (size_t t = 0; t < n_steps; ++t) {
+    const uint32_t* c = h_cum + t * 257;
+    const uint32_t x = h_sym[t];
+    rc_encode(e, h_out, cap, c[x], c[x + 1] - c[x]);
+  }
+  rc_finish(e, h_out, cap);
+  *out_len = e.pos;
+  return EDPC_OK;
+}
+
+edpc_status edpc_rc_decode_host(const uint32_t* h_cum, const uint8_t* h_in, size_t in_len,
+                                size_t n_steps, uint8_t* h_sym) {
+  if (!h_cum || (in_len && !h_in) || (n_steps && !h_sym))
+    return set_err(EDPC_E_INVALID_ARG, "NULL argument");
+  RcDec d;
+  rc_dec_init(d, h_in, in_len);
+  for (size_t t = 0; t < n_steps; ++t) {
+    const uint32_t* c = h_cum + t * 257;
+    const uint32_t x = rc_find(d, c);
+    rc_consume(d, h_in, in_len, c[x], c[x + 1]);
+    h_sym[t] = (uint8_t)x;
+  }
+  return EDPC_OK;
+}
+
+}  // extern "C"

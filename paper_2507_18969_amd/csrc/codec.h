@@ -1,0 +1,86 @@
+// Multi-stream codec sessions (Algorithm 1 over b streams in lockstep) and
+// the container format.
+#pragma once
+#include <memory>
+#include <vector>
+
+#include "model.h"
+
+namespace edpc {
+
+// Container layout (little-endian):
+//   0   "EDPC"                      magic
+//   4   u16 format version (1)
+//   6   u16 reserved (0)
+//   8   u32 header length           96 + 20 * n_streams
+//   12  u32 n_streams
+//   16  u32 context, embed, latent, blocks, hidden, branches, cdf_bits,
+//           precision, flags
+//   52  f32 lr, beta1, beta2, eps
+//   68  u64 seed
+//   76  u64 kernel configuration id (tile choices + numerics revision)
+//   84  u32 device architecture (950 for gfx950)
+//   88  u32 reserved (0)
+//   92  per stream: u64 length, u64 payload length, u32 CRC-32 of the bytes
+//   ... u32 CRC-32 of every header byte before it
+//   payloads, stream order
+constexpr uint16_t kFormatVersion = 1;
+constexpr uint32_t kArch = 950;
+constexpr size_t kHeaderFixed = 92;
+constexpr size_t kPerStream = 20;
+
+struct Header {
+  edpc_config cfg;
+  uint64_t kernel_id;
+  uint32_t arch;
+  std::vector<uint64_t> lens, pay_lens;
+  std::vector<uint32_t> crcs;
+  size_t header_len;
+};
+
+uint32_t crc32_host(const uint8_t* p, size_t n, uint32_t c = 0);
+std::vector<uint8_t> write_header(const Header& h);
+// Parses and validates; returns the status and fills `h` (lengths may be
+// partial when the buffer is short: then *need is the header length).
+edpc_status parse_header(const uint8_t* buf, size_t len, Header* h, size_t* need, std::string* err);
+
+struct Session {
+  bool decoding = false;
+  hipStream_t s = nullptr;
+  edpc_config cfg;
+  size_t n = 0;
+  std::vector<uint64_t> lens;
+  std::vector<int64_t> lens_sorted;
+  std::vector<uint32_t> perm;
+  uint64_t maxlen = 0, next = 0;
+  std::unique_ptr<Model> model;
+  std::vector<void*> allocs;
+  uint64_t *d_off = nullptr, *d_lens = nullptr, *d_pay_off = nullptr, *d_pay_cap = nullptr;
+  int64_t* d_lens_sorted = nullptr;
+  uint32_t* d_crc = nullptr;
+  RcEnc* d_enc = nullptr;
+  RcDec* d_dec = nullptr;
+  uint8_t* d_pay = nullptr;
+  uint8_t* d_dst = nullptr;
+  size_t out_cap = 0;
+  Header hdr;  // decoder
+  StreamIO io;
+  Schedule sched;
+
+  ~Session();
+  int rows_at(uint64_t i) const;
+  void run(uint64_t k);
+  template <class T>
+  T* dalloc(size_t n);
+};
+
+std::unique_ptr<Session> encoder_begin(const edpc_config& cfg, const uint8_t* d_in,
+                                       const uint64_t* lens, size_t n, hipStream_t s,
+                                       const KernelConfig* kc);
+size_t encoder_finish(Session& ss, uint8_t* d_out, size_t out_cap);
+std::unique_ptr<Session> decoder_begin(const uint8_t* d_in, size_t in_len, uint8_t* d_out,
+                                       size_t out_cap, hipStream_t s);
+size_t decoder_finish(Session& ss);
+size_t encode_bound(const edpc_config& cfg, const uint64_t* lens, size_t n);
+
+}  // namespace edpc

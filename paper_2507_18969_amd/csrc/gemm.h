@@ -1,0 +1,87 @@
+// Tiled matrix products on the gfx950 matrix cores (MFMA).
+//
+// C[M, N] = A[M, K] * B[K, N] with either operand stored K-contiguous
+// ("K-major") or M/N-contiguous, FP32 accumulation, and fused epilogues:
+//   forward dense layers  Out = In W^T + b (+ residual)       A K-major, B K-major
+//   adjoint of the input  dIn = dOut W                         A K-major, B N-major
+//   weight gradients      dW = dOut^T In (sum over rows)      A M-major, B N-major
+// The refinement block's branch product (Eqs. 10-12) is one product with
+// several B matrices sharing the A tile; its epilogue forms
+// GeLU(X_1 * ... * X_k), and the adjoint epilogue forms dX_i.
+//
+// Summation order is fixed by the tile configuration: K is walked in BK
+// chunks in increasing order, each chunk by the MFMA's own fixed order.  No
+// atomics: results are identical run to run for a given configuration.
+#pragma once
+#include "common.h"
+
+namespace edpc {
+
+enum EpiKind : int {
+  EPI_STORE = 0,     // out = acc (+ bias[n]) (+ resid[m, n])
+  EPI_GATE_FWD = 1,  // a_i = acc_i + bias_i[n]; aux[m, i*H+n] = a_i; out = gelu(prod a_i)
+  EPI_GATE_BWD = 2,  // dP = acc * gelu'(prod a_i); out[m, i*H+n] = dP * prod_{k!=i} a_k
+};
+
+struct GemmArgs {
+  const void* A;
+  const void* B;
+  int M, N, K;
+  int lda, ldb;
+  long long b_branch_stride;  // elements between the B matrices of a multi-B product
+  const StepState* st;        // rows from the step state: M (m_rows) or K (k_rows)
+  int m_rows, k_rows;
+  // epilogue
+  const float* bias;
+  int bias_branch_stride;
+  const float* resid;
+  int ld_resid;
+  float* out32;
+  int ld_out32;
+  bf16_t* out16;
+  int ld_out16;
+  float* aux;       // GATE_FWD: branch values written; GATE_BWD: read
+  int ld_aux;
+  int aux_branch;   // column offset between branches in aux / gate-bwd outputs
+};
+
+// Grouped weight-gradient products: one launch over many (dOut, In) pairs.
+struct WgradProblem {
+  const void* dout;  // [rows, M] (M = out features)
+  const void* in;    // [rows, N] (N = in features)
+  float* dw;         // [M, N]
+  int M, N;
+  int tiles_n, tile_begin;  // tiles of this problem start at tile_begin
+};
+
+// Tile configurations (the autotuner picks one per product; the choice is
+// recorded in the container so the decoder uses the same summation order).
+enum TileId : int {
+  TILE_32x32 = 0,
+  TILE_64x32 = 1,
+  TILE_32x64 = 2,
+  TILE_64x64 = 3,
+  TILE_128x64 = 4,
+  TILE_64x128 = 5,
+  TILE_128x128 = 6,
+  TILE_COUNT = 7
+};
+
+struct TileShape {
+  int bm, bn;
+};
+inline TileShape tile_shape(int id) {
+  static const TileShape t[TILE_COUNT] = {{32, 32}, {64, 32}, {32, 64}, {64, 64},
+                                          {128, 64}, {64, 128}, {128, 128}};
+  return t[id];
+}
+
+// Launchers (gemm.hip).  `bf16` selects BF16 operands (A, B hold bf16_t).
+// `a_kmajor` / `b_kmajor` select the operand layouts; nb = number of B
+// matrices (1..3) for the gated products.
+hipError_t launch_gemm(int tile, bool bf16, bool a_kmajor, bool b_kmajor, EpiKind epi, int nb,
+                       const GemmArgs& g, int grid_m_max, hipStream_t s);
+hipError_t launch_wgrad(int tile, bool bf16, const WgradProblem* d_probs, int n_probs,
+                        int total_tiles, const StepState* st, hipStream_t s);
+
+}  // namespace edpc

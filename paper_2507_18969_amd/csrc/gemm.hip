@@ -1,0 +1,415 @@
+// MFMA matrix products for gfx950; see gemm.h for the contract.
+#include "gemm.h"
+
+namespace edpc {
+
+constexpr int kThreads = 256;  // 4 waves of 64, arranged 2 x 2 over the tile
+
+template <bool BF, int MB>
+struct Mfma;
+
+template <>
+struct Mfma<false, 32> {  // v_mfma_f32_32x32x2_f32
+  static constexpr int KSTEP = 2;
+  static constexpr int NACC = 16;
+  typedef f32x16 Acc;
+  typedef float Frag;
+  __device__ static Acc mma(Frag a, Frag b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Mfma<false, 16> {  // v_mfma_f32_16x16x4_f32
+  static constexpr int KSTEP = 4;
+  static constexpr int NACC = 4;
+  typedef f32x4 Acc;
+  typedef float Frag;
+  __device__ static Acc mma(Frag a, Frag b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Mfma<true, 32> {  // v_mfma_f32_32x32x16_bf16
+  static constexpr int KSTEP = 16;
+  static constexpr int NACC = 16;
+  typedef f32x16 Acc;
+  typedef bf16x8 Frag;
+  __device__ static Acc mma(Frag a, Frag b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Mfma<true, 16> {  // v_mfma_f32_16x16x32_bf16
+  static constexpr int KSTEP = 32;
+  static constexpr int NACC = 4;
+  typedef f32x4 Acc;
+  typedef bf16x8 Frag;
+  __device__ static Acc mma(Frag a, Frag b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+};
+
+// Row / column of accumulator register r of this lane inside an MB x MB block.
+template <int MB>
+__device__ __forceinline__ int acc_row(int r, int lane) {
+  if constexpr (MB == 32) return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+  else return 4 * (lane >> 4) + r;
+}
+template <int MB>
+__device__ __forceinline__ int acc_col(int lane) {
+  return lane & (MB - 1);
+}
+
+// ---------------------------------------------------------------------------
+// Operand tile staging.  LDS layout: FP32 tiles are stored k-major
+// [BK][ROWS + 4]; BF16 tiles row-major [ROWS][BK + 8] so that one lane reads
+// its 8 consecutive k values with a single 16-byte access.
+// ---------------------------------------------------------------------------
+template <bool BF, int ROWS, int BK>
+struct Stage {
+  static constexpr int VEC = BF ? 8 : 4;                 // elements per 16-byte vector
+  static constexpr int NVEC = ROWS * BK / VEC;           // vectors per tile
+  static constexpr int PER_THREAD = (NVEC + kThreads - 1) / kThreads;
+  static constexpr int STRIDE = BF ? (BK + 8) : (ROWS + 4);  // LDS row stride (elements)
+  static constexpr int LDS_ELEMS = BF ? ROWS * (BK + 8) : BK * (ROWS + 4);
+  uint4 reg[PER_THREAD];
+
+  // Global -> registers.  kmajor: src[row * ld + k]; else src[k * ld + row].
+  template <bool KMAJOR>
+  __device__ __forceinline__ void load(const void* srcv, int ld, int row0, int rows_valid,
+                                       int k0, int K) {
+    const char* src = (const char*)srcv;
+    const int esz = BF ? 2 : 4;
+#pragma unroll
+    for (int p = 0; p < PER_THREAD; ++p) {
+      const int v = threadIdx.x + p * kThreads;
+      uint4 val = make_uint4(0, 0, 0, 0);
+      if (v < NVEC) {
+        if constexpr (KMAJOR) {
+          const int row = v / (BK / VEC), kq = v % (BK / VEC);
+          const int gr = row0 + row, gk = k0 + kq * VEC;
+          if (gr < rows_valid && gk < K)
+            val = *(const uint4*)(src + ((long long)gr * ld + gk) * esz);
+        } else {
+          const int k = v / (ROWS / VEC), rq = v % (ROWS / VEC);
+          const int gr = row0 + rq * VEC, gk = k0 + k;
+          if (gr < rows_valid && gk < K)
+            val = *(const uint4*)(src + ((long long)gk * ld + gr) * esz);
+        }
+      }
+      reg[p] = val;
+    }
+  }
+
+  template <bool KMAJOR>
+  __device__ __forceinline__ void store(void* ldsv) {
+#pragma unroll
+    for (int p = 0; p < PER_THREAD; ++p) {
+      const int v = threadIdx.x + p * kThreads;
+      if (v >= NVEC) continue;
+      if constexpr (!BF) {
+        float* lds = (float*)ldsv;
+        const float* f = (const float*)&reg[p];
+        if constexpr (KMAJOR) {
+          const int row = v / (BK / VEC), kq = v % (BK / VEC);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) lds[(kq * 4 + j) * STRIDE + row] = f[j];
+        } else {
+          const int k = v / (ROWS / VEC), rq = v % (ROWS / VEC);
+          *(uint4*)(lds + k * STRIDE + rq * 4) = reg[p];
+        }
+      } else {
+        bf16_t* lds = (bf16_t*)ldsv;
+        if constexpr (KMAJOR) {
+          const int row = v / (BK / VEC), kq = v % (BK / VEC);
+          *(uint4*)(lds + row * STRIDE + kq * 8) = reg[p];
+        } else {
+          const int k = v / (ROWS / VEC), rq = v % (ROWS / VEC);
+          const bf16_t* h = (const bf16_t*)&reg[p];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) lds[(rq * 8 + j) * STRIDE + k] = h[j];
+        }
+      }
+    }
+  }
+};
+
+template <bool BF, int MB, int BK>
+__device__ __forceinline__ typename Mfma<BF, MB>::Frag frag_read(const void* ldsv, int stride,
+                                                                 int row_base, int kk, int lane) {
+  if constexpr (!BF) {
+    const float* lds = (const float*)ldsv;
+    const int r = lane % MB, k = lane / MB;
+    return lds[(kk + k) * stride + row_base + r];
+  } else {
+    const bf16_t* lds = (const bf16_t*)ldsv;
+    const int r = lane % MB, kg = lane / MB;
+    uint4 u = *(const uint4*)(lds + (row_base + r) * stride + kk + 8 * kg);
+    return __builtin_bit_cast(bf16x8, u);
+  }
+}
+
+template <int BM_, int BN_, int MB_, int TM_, int TN_>
+struct TileCfg {
+  static constexpr int BM = BM_, BN = BN_, MB = MB_, TM = TM_, TN = TN_;
+};
+
+// One output tile (m0, n0) of C = A * B_i for i < NB.
+template <bool BF, class T, bool AK, bool BKM, int NB>
+struct TileCompute {
+  static constexpr int BK = 32;
+  static constexpr int MB = T::MB, TM = T::TM, TN = T::TN;
+  typedef Mfma<BF, MB> Op;
+  typedef Stage<BF, T::BM, BK> SA;
+  typedef Stage<BF, T::BN, BK> SB;
+  typename Op::Acc acc[NB][TM][TN];
+
+  __device__ __forceinline__ void run(const void* A, int lda, const void* B, int ldb,
+                                      long long bstride, int M, int N, int K, int m0, int n0,
+                                      char* smem) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    void* lds_a = smem;
+    char* lds_b = smem + SA::LDS_ELEMS * (BF ? 2 : 4);
+    const int esz = BF ? 2 : 4;
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+          for (int r = 0; r < Op::NACC; ++r) acc[b][i][j][r] = 0.0f;
+
+    SA sa;
+    SB sb[NB];
+    sa.template load<AK>(A, lda, m0, M, 0, K);
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+      sb[b].template load<BKM>((const char*)B + b * bstride * esz, ldb, n0, N, 0, K);
+
+    for (int k0 = 0; k0 < K; k0 += BK) {
+      __syncthreads();
+      sa.template store<AK>(lds_a);
+#pragma unroll
+      for (int b = 0; b < NB; ++b) sb[b].template store<BKM>(lds_b + b * SB::LDS_ELEMS * esz);
+      __syncthreads();
+      if (k0 + BK < K) {
+        sa.template load<AK>(A, lda, m0, M, k0 + BK, K);
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+          sb[b].template load<BKM>((const char*)B + b * bstride * esz, ldb, n0, N, k0 + BK, K);
+      }
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += Op::KSTEP) {
+        typename Op::Frag fa[TM];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+          fa[i] = frag_read<BF, MB, BK>(lds_a, SA::STRIDE, (wm * TM + i) * MB, kk, lane);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+#pragma unroll
+          for (int j = 0; j < TN; ++j) {
+            typename Op::Frag fb = frag_read<BF, MB, BK>(lds_b + b * SB::LDS_ELEMS * esz,
+                                                         SB::STRIDE, (wn * TN + j) * MB, kk, lane);
+#pragma unroll
+            for (int i = 0; i < TM; ++i) acc[b][i][j] = Op::mma(fa[i], fb, acc[b][i][j]);
+          }
+        }
+      }
+    }
+  }
+
+  static constexpr int smem_bytes() {
+    return (SA::LDS_ELEMS + NB * SB::LDS_ELEMS) * (BF ? 2 : 4);
+  }
+};
+
+template <bool BF, class T, bool AK, bool BKM, int EPI, int NB>
+__global__ void __launch_bounds__(kThreads) gemm_kernel(GemmArgs g) {
+  typedef TileCompute<BF, T, AK, BKM, NB> TC;
+  extern __shared__ __align__(16) char smem[];
+  const int M = g.m_rows ? g.st->rows : g.M;
+  const int K = g.k_rows ? g.st->rows : g.K;
+  const int N = g.N;
+  const int m0 = blockIdx.y * T::BM, n0 = blockIdx.x * T::BN;
+  if (m0 >= M) return;
+  TC tc;
+  tc.run(g.A, g.lda, g.B, g.ldb, g.b_branch_stride, M, N, K, m0, n0, smem);
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+#pragma unroll
+  for (int i = 0; i < T::TM; ++i)
+#pragma unroll
+    for (int j = 0; j < T::TN; ++j)
+#pragma unroll
+      for (int r = 0; r < TC::Op::NACC; ++r) {
+        const int m = m0 + (wm * T::TM + i) * T::MB + acc_row<T::MB>(r, lane);
+        const int n = n0 + (wn * T::TN + j) * T::MB + acc_col<T::MB>(lane);
+        if (m >= M || n >= N) continue;
+        if constexpr (EPI == EPI_STORE) {
+          float v = tc.acc[0][i][j][r];
+          if (g.bias) v += g.bias[n];
+          if (g.resid) v += g.resid[(long long)m * g.ld_resid + n];
+          if (g.out32) g.out32[(long long)m * g.ld_out32 + n] = v;
+          if (g.out16) g.out16[(long long)m * g.ld_out16 + n] = f2bf(v);
+        } else if constexpr (EPI == EPI_GATE_FWD) {
+          float prod = 1.0f;
+#pragma unroll
+          for (int b = 0; b < NB; ++b) {
+            const float a = tc.acc[b][i][j][r] + g.bias[b * g.bias_branch_stride + n];
+            g.aux[(long long)m * g.ld_aux + b * g.aux_branch + n] = a;
+            prod = (b == 0) ? a : prod * a;
+          }
+          const float v = gelu_f(prod);
+          if (g.out32) g.out32[(long long)m * g.ld_out32 + n] = v;
+          if (g.out16) g.out16[(long long)m * g.ld_out16 + n] = f2bf(v);
+        } else {  // EPI_GATE_BWD: branch count in bias_branch_stride
+          const int nbr = g.bias_branch_stride;
+          float a[3];
+          float prod = 1.0f;
+          for (int b = 0; b < nbr; ++b) {
+            a[b] = g.aux[(long long)m * g.ld_aux + b * g.aux_branch + n];
+            prod = (b == 0) ? a[b] : prod * a[b];
+          }
+          const float dp = tc.acc[0][i][j][r] * gelu_grad_f(prod);
+          for (int b = 0; b < nbr; ++b) {
+            float o = dp;
+            for (int c = 0; c < nbr; ++c)
+              if (c != b) o *= a[c];
+            if (g.out32) g.out32[(long long)m * g.ld_out32 + b * g.aux_branch + n] = o;
+            if (g.out16) g.out16[(long long)m * g.ld_out16 + b * g.aux_branch + n] = f2bf(o);
+          }
+        }
+      }
+}
+
+template <bool BF, class T>
+__global__ void __launch_bounds__(kThreads) wgrad_kernel(const WgradProblem* __restrict__ probs,
+                                                         int n_probs, const StepState* st) {
+  typedef TileCompute<BF, T, false, false, 1> TC;
+  extern __shared__ __align__(16) char smem[];
+  int p = 0;
+  while (p + 1 < n_probs && (int)blockIdx.x >= probs[p + 1].tile_begin) ++p;
+  const WgradProblem pr = probs[p];
+  const int t = blockIdx.x - pr.tile_begin;
+  const int m0 = (t / pr.tiles_n) * T::BM, n0 = (t % pr.tiles_n) * T::BN;
+  const int K = st->rows;
+  TC tc;
+  tc.run(pr.dout, pr.M, pr.in, pr.N, 0, pr.M, pr.N, K, m0, n0, smem);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+#pragma unroll
+  for (int i = 0; i < T::TM; ++i)
+#pragma unroll
+    for (int j = 0; j < T::TN; ++j)
+#pragma unroll
+      for (int r = 0; r < TC::Op::NACC; ++r) {
+        const int m = m0 + (wm * T::TM + i) * T::MB + acc_row<T::MB>(r, lane);
+        const int n = n0 + (wn * T::TN + j) * T::MB + acc_col<T::MB>(lane);
+        if (m < pr.M && n < pr.N) pr.dw[(long long)m * pr.N + n] = tc.acc[0][i][j][r];
+      }
+}
+
+// ---------------------------------------------------------------------------
+// Dispatch
+// ---------------------------------------------------------------------------
+typedef TileCfg<32, 32, 16, 1, 1> T32x32;
+typedef TileCfg<64, 32, 16, 2, 1> T64x32;
+typedef TileCfg<32, 64, 16, 1, 2> T32x64;
+typedef TileCfg<64, 64, 32, 1, 1> T64x64;
+typedef TileCfg<128, 64, 32, 2, 1> T128x64;
+typedef TileCfg<64, 128, 32, 1, 2> T64x128;
+typedef TileCfg<128, 128, 32, 2, 2> T128x128;
+
+template <bool BF, class T, bool AK, bool BKM, int EPI, int NB>
+static hipError_t launch_one(const GemmArgs& g, int grid_m_max, hipStream_t s) {
+  typedef TileCompute<BF, T, AK, BKM, NB> TC;
+  dim3 grid((g.N + T::BN - 1) / T::BN, (grid_m_max + T::BM - 1) / T::BM);
+  if (grid.x == 0 || grid.y == 0) return hipSuccess;
+  constexpr int smem = TC::smem_bytes();
+  static_assert(smem <= 160 * 1024, "tile does not fit in LDS");
+  if constexpr (smem > 64 * 1024) {
+    static bool done = false;
+    if (!done) {
+      hipError_t e = hipFuncSetAttribute((const void*)gemm_kernel<BF, T, AK, BKM, EPI, NB>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, smem);
+      if (e != hipSuccess) return e;
+      done = true;
+    }
+  }
+  hipLaunchKernelGGL((gemm_kernel<BF, T, AK, BKM, EPI, NB>), grid, dim3(kThreads), smem, s, g);
+  return hipGetLastError();
+}
+
+template <bool BF, class T>
+static hipError_t launch_t(bool ak, bool bk, EpiKind epi, int nb, const GemmArgs& g, int gm,
+                           hipStream_t s) {
+  if (ak && bk) {  // forward dense layers
+    if (epi == EPI_STORE) return launch_one<BF, T, true, true, EPI_STORE, 1>(g, gm, s);
+    if (epi == EPI_GATE_FWD) {
+      if (nb == 1) return launch_one<BF, T, true, true, EPI_GATE_FWD, 1>(g, gm, s);
+      if (nb == 2) return launch_one<BF, T, true, true, EPI_GATE_FWD, 2>(g, gm, s);
+      if (nb == 3) return launch_one<BF, T, true, true, EPI_GATE_FWD, 3>(g, gm, s);
+    }
+  } else if (ak && !bk) {  // adjoint of the input
+    if (epi == EPI_STORE) return launch_one<BF, T, true, false, EPI_STORE, 1>(g, gm, s);
+    if (epi == EPI_GATE_BWD) return launch_one<BF, T, true, false, EPI_GATE_BWD, 1>(g, gm, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <bool BF>
+static hipError_t launch_p(int tile, bool ak, bool bk, EpiKind epi, int nb, const GemmArgs& g,
+                           int gm, hipStream_t s) {
+  switch (tile) {
+    case TILE_32x32: return launch_t<BF, T32x32>(ak, bk, epi, nb, g, gm, s);
+    case TILE_64x32: return launch_t<BF, T64x32>(ak, bk, epi, nb, g, gm, s);
+    case TILE_32x64: return launch_t<BF, T32x64>(ak, bk, epi, nb, g, gm, s);
+    case TILE_64x64: return launch_t<BF, T64x64>(ak, bk, epi, nb, g, gm, s);
+    case TILE_128x64: return launch_t<BF, T128x64>(ak, bk, epi, nb, g, gm, s);
+    case TILE_64x128: return launch_t<BF, T64x128>(ak, bk, epi, nb, g, gm, s);
+    case TILE_128x128: return launch_t<BF, T128x128>(ak, bk, epi, nb, g, gm, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_gemm(int tile, bool bf16, bool a_kmajor, bool b_kmajor, EpiKind epi, int nb,
+                       const GemmArgs& g, int grid_m_max, hipStream_t s) {
+  return bf16 ? launch_p<true>(tile, a_kmajor, b_kmajor, epi, nb, g, grid_m_max, s)
+              : launch_p<false>(tile, a_kmajor, b_kmajor, epi, nb, g, grid_m_max, s);
+}
+
+template <bool BF, class T>
+static hipError_t launch_w(const WgradProblem* d_probs, int n_probs, int total_tiles,
+                           const StepState* st, hipStream_t s) {
+  typedef TileCompute<BF, T, false, false, 1> TC;
+  if (total_tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL((wgrad_kernel<BF, T>), dim3(total_tiles), dim3(kThreads), TC::smem_bytes(), s,
+                     d_probs, n_probs, st);
+  return hipGetLastError();
+}
+
+template <bool BF>
+static hipError_t launch_wp(int tile, const WgradProblem* p, int n, int tt, const StepState* st,
+                            hipStream_t s) {
+  switch (tile) {
+    case TILE_32x32: return launch_w<BF, T32x32>(p, n, tt, st, s);
+    case TILE_64x32: return launch_w<BF, T64x32>(p, n, tt, st, s);
+    case TILE_32x64: return launch_w<BF, T32x64>(p, n, tt, st, s);
+    case TILE_64x64: return launch_w<BF, T64x64>(p, n, tt, st, s);
+    case TILE_128x64: return launch_w<BF, T128x64>(p, n, tt, st, s);
+    case TILE_64x128: return launch_w<BF, T64x128>(p, n, tt, st, s);
+    case TILE_128x128: return launch_w<BF, T128x128>(p, n, tt, st, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_wgrad(int tile, bool bf16, const WgradProblem* d_probs, int n_probs,
+                        int total_tiles, const StepState* st, hipStream_t s) {
+  return bf16 ? launch_wp<true>(tile, d_probs, n_probs, total_tiles, st, s)
+              : launch_wp<false>(tile, d_probs, n_probs, total_tiles, st, s);
+}
+
+}  // namespace edpc

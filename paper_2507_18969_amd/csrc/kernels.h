@@ -1,0 +1,102 @@
+// Row-wise and element-wise kernels of one model step, and the coder lanes.
+#pragma once
+#include "common.h"
+#include "rangecoder.h"
+
+namespace edpc {
+
+// Schedule of a multi-stream run: streams sorted by decreasing length so
+// that the active streams at step i are rows 0 .. rows(i)-1.
+struct Schedule {
+  const int64_t* lens_sorted;  // [n] decreasing
+  int n;
+  int context;
+  float beta1, beta2;
+};
+
+// Where each row's bytes live in a multi-stream run.
+struct StreamIO {
+  const uint32_t* slot;       // row -> stream index (original order)
+  const uint8_t* src;         // encoder input (concatenated streams)
+  uint8_t* dst;               // decoder output (concatenated streams)
+  const uint64_t* off;        // stream -> offset in src / dst
+  const uint64_t* lens;       // stream -> length
+  uint8_t* pay;               // encoder payload region base
+  const uint8_t* pay_in;      // decoder payload base
+  const uint64_t* pay_off;    // stream -> payload offset
+  const uint64_t* pay_cap;    // stream -> payload capacity (encoder) / length (decoder)
+  RcEnc* enc;                 // [n_streams]
+  RcDec* dec;                 // [n_streams]
+};
+
+struct HeadArgs {
+  const float* logits;  // [rows, 256]
+  const uint8_t* target;  // [rows] (encode / plain step)
+  uint8_t* target_out;    // decoded symbol per row (decode)
+  float* dz32;            // [rows, 256]
+  bf16_t* dz16;
+  float* loss_rows;       // [rows]
+  float* probs;           // optional [rows, 256]
+  uint32_t* cum_out;      // optional [rows, 257]
+  int mode;               // 0 plain step, 1 encode, 2 decode
+  int want_grad;
+};
+
+void k_step_schedule(StepState* st, Schedule sc, int step, hipStream_t s);
+void k_step_explicit(StepState* st, int rows, uint32_t tau, float beta1, float beta2, hipStream_t s);
+
+void k_gather(const StepState* st, StreamIO io, int C, uint8_t* ctx, uint8_t* tgt, int max_rows,
+              bool decoding, hipStream_t s);
+void k_embed(const StepState* st, const uint8_t* ctx, const float* emb, int C, int E, float* x32,
+             bf16_t* x16, int max_rows, hipStream_t s);
+void k_fdm_fwd(const StepState* st, const float* x1, const float* U, const uint32_t* slot, int L,
+               float* y32, bf16_t* y16, int max_rows, hipStream_t s);
+void k_fdm_bwd(const StepState* st, const float* x1, const float* dy, float* U, float* mU,
+               float* vU, float* dU_keep, const uint32_t* slot, int L, AdamCfg ac, bool update,
+               float* dx1_32, bf16_t* dx1_16, int max_rows, hipStream_t s);
+void k_ln_fwd(const StepState* st, const float* h, const float* gamma, const float* beta, int F,
+              float* z32, bf16_t* z16, float* mean, float* rstd, int max_rows, hipStream_t s);
+void k_ln_bwd(const StepState* st, const float* h, const float* mean, const float* rstd,
+              const float* gamma, const float* dz, const float* dh_next, int F, float* dh32,
+              bf16_t* dh16, int max_rows, hipStream_t s);
+void k_head(const StepState* st, HeadArgs a, StreamIO io, int max_rows, hipStream_t s);
+
+// Column sums over the active rows (bias and LayerNorm gradients, loss).
+struct ColsumJob {
+  const float* src;    // [rows, cols] with leading dimension ld
+  const float* h;      // LN gamma jobs: the block input; xhat = (h - mean) * rstd
+  const float* mean;
+  const float* rstd;
+  float* dst;          // [cols]
+  int cols, ld;
+  int col_block_begin; // first block of this job
+  float scale;
+};
+void k_colsum(const StepState* st, const ColsumJob* jobs, int n_jobs, int total_blocks,
+              hipStream_t s);
+
+void k_emb_grad(const StepState* st, const uint8_t* ctx, const float* dx, int C, int E,
+                float* partial, int chunk_rows, int max_rows, float* demb, hipStream_t s);
+void k_adam(const StepState* st, float* p, const float* g, float* m, float* v, bf16_t* p16,
+            size_t n, AdamCfg ac, hipStream_t s);
+
+// Counter-based initialisation: dst[j] = fl32(a_j * bound), a_j from
+// SplitMix64(seed + (tid << 40) + start + j).
+void k_init_uniform(float* dst, size_t n, uint64_t seed, uint32_t tid, uint64_t start, float bound,
+                    hipStream_t s);
+void k_fill(float* dst, size_t n, float v, hipStream_t s);
+void k_to_bf16(const float* src, bf16_t* dst, size_t n, hipStream_t s);
+
+// Coder lanes.
+void k_uniform_prefix(StreamIO io, int n_streams, int C, bool decoding, hipStream_t s);
+void k_rc_finish(StreamIO io, int n_streams, hipStream_t s);
+void k_rc_table_encode(const uint32_t* cum, const uint8_t* sym, size_t n_steps, size_t n_streams,
+                       uint8_t* out, size_t cap, uint64_t* out_lens, hipStream_t s);
+void k_rc_table_decode(const uint32_t* cum, const uint8_t* in, const uint64_t* in_lens, size_t cap,
+                       size_t n_steps, size_t n_streams, uint8_t* sym, hipStream_t s);
+void k_crc32(const uint8_t* data, const uint64_t* off, const uint64_t* lens, int n, uint32_t* crc,
+             hipStream_t s);
+void k_gather_payloads(const uint8_t* pay, const uint64_t* pay_off, const uint64_t* len,
+                       const uint64_t* dst_off, uint8_t* dst, int n, hipStream_t s);
+
+}  // namespace edpc

@@ -1,0 +1,732 @@
+// Row-wise / element-wise kernels of one model step and the coder lanes.
+#include "kernels.h"
+
+namespace edpc {
+
+static inline unsigned blocks_for(size_t n, unsigned per) { return (unsigned)((n + per - 1) / per); }
+
+// ---------------------------------------------------------------------------
+// Step state
+// ---------------------------------------------------------------------------
+__global__ void step_schedule_kernel(StepState* st, Schedule sc, int step) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (step < 0) step = st->step + 1;
+  // rows = number of streams with length > step (lens sorted decreasing)
+  int lo = 0, hi = sc.n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (sc.lens_sorted[mid] > (int64_t)step) lo = mid + 1; else hi = mid;
+  }
+  st->step = step;
+  st->rows = lo;
+  st->inv_rows = lo > 0 ? 1.0f / (float)lo : 0.0f;
+  st->model = step >= sc.context ? 1 : 0;
+  const uint32_t tau = step >= sc.context ? (uint32_t)(step - sc.context + 1) : 0u;
+  st->tau = tau;
+  st->bc1 = 1.0f - powf(sc.beta1, (float)tau);
+  st->bc2 = 1.0f - powf(sc.beta2, (float)tau);
+}
+
+void k_step_schedule(StepState* st, Schedule sc, int step, hipStream_t s) {
+  hipLaunchKernelGGL(step_schedule_kernel, dim3(1), dim3(64), 0, s, st, sc, step);
+}
+
+__global__ void step_explicit_kernel(StepState* st, int rows, uint32_t tau, float beta1,
+                                     float beta2) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  st->step = -1;
+  st->rows = rows;
+  st->inv_rows = rows > 0 ? 1.0f / (float)rows : 0.0f;
+  st->model = 1;
+  st->tau = tau;
+  st->bc1 = 1.0f - powf(beta1, (float)tau);
+  st->bc2 = 1.0f - powf(beta2, (float)tau);
+}
+
+void k_step_explicit(StepState* st, int rows, uint32_t tau, float beta1, float beta2,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(step_explicit_kernel, dim3(1), dim3(64), 0, s, st, rows, tau, beta1, beta2);
+}
+
+// ---------------------------------------------------------------------------
+// Context window gather and byte embedding
+// ---------------------------------------------------------------------------
+__global__ void gather_kernel(const StepState* __restrict__ st, StreamIO io, int C,
+                              uint8_t* __restrict__ ctx, uint8_t* __restrict__ tgt,
+                              bool decoding) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = idx / C, c = idx % C;
+  if (r >= st->rows) return;
+  const int i = st->step;
+  const uint32_t s = io.slot[r];
+  const uint8_t* base = decoding ? io.dst : io.src;
+  const uint64_t o = io.off[s];
+  ctx[idx] = base[o + (uint64_t)(i - C + c)];
+  if (!decoding && c == 0) tgt[r] = io.src[o + (uint64_t)i];
+}
+
+void k_gather(const StepState* st, StreamIO io, int C, uint8_t* ctx, uint8_t* tgt, int max_rows,
+              bool decoding, hipStream_t s) {
+  const size_t n = (size_t)max_rows * C;
+  hipLaunchKernelGGL(gather_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, st, io, C, ctx, tgt,
+                     decoding);
+}
+
+__global__ void embed_kernel(const StepState* __restrict__ st, const uint8_t* __restrict__ ctx,
+                             const float* __restrict__ emb, int C, int E, float* __restrict__ x32,
+                             bf16_t* __restrict__ x16) {
+  const int F = C * E;
+  const int q4 = F >> 2;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = idx / q4, f = (idx % q4) * 4;
+  if (r >= st->rows) return;
+  const int c = f / E, e = f % E;
+  const int v = ctx[r * C + c];
+  const float4 val = *(const float4*)(emb + v * E + e);
+  if (x32) *(float4*)(x32 + (size_t)r * F + f) = val;
+  if (x16) {
+    ushort4 h = make_ushort4(f2bf(val.x), f2bf(val.y), f2bf(val.z), f2bf(val.w));
+    *(ushort4*)(x16 + (size_t)r * F + f) = h;
+  }
+}
+
+void k_embed(const StepState* st, const uint8_t* ctx, const float* emb, int C, int E, float* x32,
+             bf16_t* x16, int max_rows, hipStream_t s) {
+  const size_t n = (size_t)max_rows * C * E / 4;
+  hipLaunchKernelGGL(embed_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, st, ctx, emb, C, E,
+                     x32, x16);
+}
+
+// ---------------------------------------------------------------------------
+// Feature Distribution Matrix (Eq. 15): y_s = x'_s U_s, one workgroup per row.
+// Thread (g, t): t covers columns 4t..4t+3, group g rows l = g, g+G, ...
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) fdm_fwd_kernel(const StepState* __restrict__ st,
+                                                      const float* __restrict__ x1,
+                                                      const float* __restrict__ U,
+                                                      const uint32_t* __restrict__ slot, int L,
+                                                      float* __restrict__ y32,
+                                                      bf16_t* __restrict__ y16) {
+  const int r = blockIdx.x;
+  if (r >= st->rows) return;
+  __shared__ float xs[256];
+  __shared__ float part[1024];
+  const int tpr = L >> 2, G = 256 / tpr;
+  const int t = threadIdx.x % tpr, g = threadIdx.x / tpr;
+  for (int l = threadIdx.x; l < L; l += 256) xs[l] = x1[(size_t)r * L + l];
+  __syncthreads();
+  const float* Us = U + (size_t)slot[r] * L * L;
+  float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (g < G) {
+    for (int l = g; l < L; l += G) {
+      const float4 u = *(const float4*)(Us + (size_t)l * L + 4 * t);
+      const float xv = xs[l];
+      acc.x += xv * u.x;
+      acc.y += xv * u.y;
+      acc.z += xv * u.z;
+      acc.w += xv * u.w;
+    }
+    *(float4*)(part + g * L + 4 * t) = acc;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < L; k += 256) {
+    float y = 0.f;
+    for (int gg = 0; gg < G; ++gg) y += part[gg * L + k];
+    if (y32) y32[(size_t)r * L + k] = y;
+    if (y16) y16[(size_t)r * L + k] = f2bf(y);
+  }
+}
+
+void k_fdm_fwd(const StepState* st, const float* x1, const float* U, const uint32_t* slot, int L,
+               float* y32, bf16_t* y16, int max_rows, hipStream_t s) {
+  hipLaunchKernelGGL(fdm_fwd_kernel, dim3(max_rows), dim3(256), 0, s, st, x1, U, slot, L, y32, y16);
+}
+
+// Adjoint of Eq. 15 fused with the Adam step on U_s:
+//   dx'_s = U_s dy_s (with U before the update), dU_s = x'_s (x) dy_s.
+__global__ void __launch_bounds__(256) fdm_bwd_kernel(
+    const StepState* __restrict__ st, const float* __restrict__ x1, const float* __restrict__ dy,
+    float* __restrict__ U, float* __restrict__ mU, float* __restrict__ vU,
+    float* __restrict__ dU_keep, const uint32_t* __restrict__ slot, int L, AdamCfg ac, bool update,
+    float* __restrict__ dx1_32, bf16_t* __restrict__ dx1_16) {
+  const int r = blockIdx.x;
+  if (r >= st->rows) return;
+  __shared__ float xs[256];
+  __shared__ float ds[256];
+  const int tpr = L >> 2, G = 256 / tpr;
+  const int t = threadIdx.x % tpr, g = threadIdx.x / tpr;
+  for (int l = threadIdx.x; l < L; l += 256) {
+    xs[l] = x1[(size_t)r * L + l];
+    ds[l] = dy[(size_t)r * L + l];
+  }
+  __syncthreads();
+  if (g >= G) return;
+  const size_t base_s = (size_t)slot[r] * L * L;
+  const float4 d4 = *(const float4*)(ds + 4 * t);
+  const float b1 = ac.beta1, b2 = ac.beta2;
+  const float lr_bc = ac.lr / st->bc1;
+  const float inv_bc2 = 1.0f / st->bc2;
+  for (int l = g; l < L; l += G) {
+    const size_t idx = base_s + (size_t)l * L + 4 * t;
+    float4 u = *(const float4*)(U + idx);
+    float part = u.x * d4.x + u.y * d4.y + u.z * d4.z + u.w * d4.w;
+    for (int o = tpr >> 1; o >= 1; o >>= 1) part += __shfl_xor(part, o, 64);
+    if (t == 0) {
+      if (dx1_32) dx1_32[(size_t)r * L + l] = part;
+      if (dx1_16) dx1_16[(size_t)r * L + l] = f2bf(part);
+    }
+    const float xv = xs[l];
+    const float gr[4] = {xv * d4.x, xv * d4.y, xv * d4.z, xv * d4.w};
+    if (dU_keep) *(float4*)(dU_keep + idx) = make_float4(gr[0], gr[1], gr[2], gr[3]);
+    if (update) {
+      float4 m = *(const float4*)(mU + idx);
+      float4 v = *(const float4*)(vU + idx);
+      float* up = (float*)&u;
+      float* mp = (float*)&m;
+      float* vp = (float*)&v;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        mp[j] = b1 * mp[j] + (1.0f - b1) * gr[j];
+        vp[j] = b2 * vp[j] + (1.0f - b2) * gr[j] * gr[j];
+        up[j] -= lr_bc * mp[j] / (sqrtf(vp[j] * inv_bc2) + ac.eps);
+      }
+      *(float4*)(U + idx) = u;
+      *(float4*)(mU + idx) = m;
+      *(float4*)(vU + idx) = v;
+    }
+  }
+}
+
+void k_fdm_bwd(const StepState* st, const float* x1, const float* dy, float* U, float* mU,
+               float* vU, float* dU_keep, const uint32_t* slot, int L, AdamCfg ac, bool update,
+               float* dx1_32, bf16_t* dx1_16, int max_rows, hipStream_t s) {
+  hipLaunchKernelGGL(fdm_bwd_kernel, dim3(max_rows), dim3(256), 0, s, st, x1, dy, U, mU, vU,
+                     dU_keep, slot, L, ac, update, dx1_32, dx1_16);
+}
+
+// ---------------------------------------------------------------------------
+// LayerNorm (Eq. 9): one wave per row, biased variance, eps 1e-5.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) ln_fwd_kernel(const StepState* __restrict__ st,
+                                                     const float* __restrict__ h,
+                                                     const float* __restrict__ gamma,
+                                                     const float* __restrict__ beta, int F,
+                                                     float* __restrict__ z32,
+                                                     bf16_t* __restrict__ z16,
+                                                     float* __restrict__ mean,
+                                                     float* __restrict__ rstd) {
+  const int lane = threadIdx.x & 63;
+  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= st->rows) return;
+  const float* hr = h + (size_t)r * F;
+  float s = 0.f;
+  for (int f = 4 * lane; f < F; f += 256) {
+    const float4 x = *(const float4*)(hr + f);
+    s += (x.x + x.y) + (x.z + x.w);
+  }
+  const float mu = wave_sum(s) / (float)F;
+  float q = 0.f;
+  for (int f = 4 * lane; f < F; f += 256) {
+    const float4 x = *(const float4*)(hr + f);
+    const float a = x.x - mu, b = x.y - mu, c = x.z - mu, d = x.w - mu;
+    q += (a * a + b * b) + (c * c + d * d);
+  }
+  const float var = wave_sum(q) / (float)F;
+  const float rs = 1.0f / sqrtf(var + 1e-5f);
+  if (lane == 0) {
+    mean[r] = mu;
+    rstd[r] = rs;
+  }
+  for (int f = 4 * lane; f < F; f += 256) {
+    const float4 x = *(const float4*)(hr + f);
+    const float4 gm = *(const float4*)(gamma + f);
+    const float4 bt = *(const float4*)(beta + f);
+    float4 z;
+    z.x = (x.x - mu) * rs * gm.x + bt.x;
+    z.y = (x.y - mu) * rs * gm.y + bt.y;
+    z.z = (x.z - mu) * rs * gm.z + bt.z;
+    z.w = (x.w - mu) * rs * gm.w + bt.w;
+    if (z32) *(float4*)(z32 + (size_t)r * F + f) = z;
+    if (z16)
+      *(ushort4*)(z16 + (size_t)r * F + f) = make_ushort4(f2bf(z.x), f2bf(z.y), f2bf(z.z), f2bf(z.w));
+  }
+}
+
+void k_ln_fwd(const StepState* st, const float* h, const float* gamma, const float* beta, int F,
+              float* z32, bf16_t* z16, float* mean, float* rstd, int max_rows, hipStream_t s) {
+  hipLaunchKernelGGL(ln_fwd_kernel, dim3(blocks_for(max_rows, 4)), dim3(256), 0, s, st, h, gamma,
+                     beta, F, z32, z16, mean, rstd);
+}
+
+// dh = dh_next + rstd * (dxhat - mean(dxhat) - xhat * mean(dxhat * xhat)),
+// dxhat = dz * gamma, xhat = (h - mean) * rstd.
+__global__ void __launch_bounds__(256) ln_bwd_kernel(
+    const StepState* __restrict__ st, const float* __restrict__ h, const float* __restrict__ mean,
+    const float* __restrict__ rstd, const float* __restrict__ gamma, const float* __restrict__ dz,
+    const float* __restrict__ dh_next, int F, float* __restrict__ dh32,
+    bf16_t* __restrict__ dh16) {
+  const int lane = threadIdx.x & 63;
+  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= st->rows) return;
+  const float mu = mean[r], rs = rstd[r];
+  const float* hr = h + (size_t)r * F;
+  const float* dzr = dz + (size_t)r * F;
+  float s1 = 0.f, s2 = 0.f;
+  for (int f = 4 * lane; f < F; f += 256) {
+    const float4 x = *(const float4*)(hr + f);
+    const float4 d = *(const float4*)(dzr + f);
+    const float4 gm = *(const float4*)(gamma + f);
+    const float dx0 = d.x * gm.x, dx1 = d.y * gm.y, dx2 = d.z * gm.z, dx3 = d.w * gm.w;
+    s1 += (dx0 + dx1) + (dx2 + dx3);
+    s2 += (dx0 * ((x.x - mu) * rs) + dx1 * ((x.y - mu) * rs)) +
+          (dx2 * ((x.z - mu) * rs) + dx3 * ((x.w - mu) * rs));
+  }
+  const float m1 = wave_sum(s1) / (float)F;
+  const float m2 = wave_sum(s2) / (float)F;
+  for (int f = 4 * lane; f < F; f += 256) {
+    const float4 x = *(const float4*)(hr + f);
+    const float4 d = *(const float4*)(dzr + f);
+    const float4 gm = *(const float4*)(gamma + f);
+    const float4 dn = *(const float4*)(dh_next + (size_t)r * F + f);
+    float4 o;
+    o.x = dn.x + rs * (d.x * gm.x - m1 - ((x.x - mu) * rs) * m2);
+    o.y = dn.y + rs * (d.y * gm.y - m1 - ((x.y - mu) * rs) * m2);
+    o.z = dn.z + rs * (d.z * gm.z - m1 - ((x.z - mu) * rs) * m2);
+    o.w = dn.w + rs * (d.w * gm.w - m1 - ((x.w - mu) * rs) * m2);
+    *(float4*)(dh32 + (size_t)r * F + f) = o;
+    if (dh16)
+      *(ushort4*)(dh16 + (size_t)r * F + f) = make_ushort4(f2bf(o.x), f2bf(o.y), f2bf(o.z), f2bf(o.w));
+  }
+}
+
+void k_ln_bwd(const StepState* st, const float* h, const float* mean, const float* rstd,
+              const float* gamma, const float* dz, const float* dh_next, int F, float* dh32,
+              bf16_t* dh16, int max_rows, hipStream_t s) {
+  hipLaunchKernelGGL(ln_bwd_kernel, dim3(blocks_for(max_rows, 4)), dim3(256), 0, s, st, h, mean,
+                     rstd, gamma, dz, dh_next, F, dh32, dh16);
+}
+
+// ---------------------------------------------------------------------------
+// Head: softmax (Eq. 1) -> 16-bit integer CDF -> range-coder lane ->
+// cross-entropy adjoint (Eq. 2).  One wave per row; lane l holds symbols
+// 4l .. 4l+3.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) head_kernel(const StepState* __restrict__ st, HeadArgs a,
+                                                   StreamIO io) {
+  const int lane = threadIdx.x & 63;
+  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= st->rows) return;
+  const float4 z4 = *(const float4*)(a.logits + (size_t)r * 256 + 4 * lane);
+  const float z[4] = {z4.x, z4.y, z4.z, z4.w};
+  const float m = wave_max(fmaxf(fmaxf(z[0], z[1]), fmaxf(z[2], z[3])));
+  float e[4], p[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) e[j] = expf(z[j] - m);
+  const float S = wave_sum((e[0] + e[1]) + (e[2] + e[3]));
+#pragma unroll
+  for (int j = 0; j < 4; ++j) p[j] = e[j] / S;
+
+  // quantise: q = 1 + floor(p * (2^16 - 256)) in FP32; remainder to the
+  // largest bin (lowest symbol on ties)
+  int q[4];
+  uint32_t key = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    q[j] = 1 + (int)floorf(p[j] * 65280.0f);
+    const uint32_t k = ((uint32_t)q[j] << 8) | (uint32_t)(255 - (4 * lane + j));
+    key = k > key ? k : key;
+  }
+  key = wave_max_u(key);
+  const int am = 255 - (int)(key & 255u);
+  const int qsum = wave_sum_i((q[0] + q[1]) + (q[2] + q[3]));
+  if ((am >> 2) == lane) q[am & 3] += 65536 - qsum;
+
+  // exclusive prefix sums
+  const int ls = (q[0] + q[1]) + (q[2] + q[3]);
+  int incl = ls;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += t;
+  }
+  int cum[4];
+  cum[0] = incl - ls;
+  cum[1] = cum[0] + q[0];
+  cum[2] = cum[1] + q[1];
+  cum[3] = cum[2] + q[2];
+
+  const uint32_t s = io.slot ? io.slot[r] : 0u;
+  int x = 0;
+  if (a.mode == 2) {
+    // decode: symbol x = #{v : (range * cum[v]) >> 16 <= d} - 1
+    uint64_t d = 0, rng = 0;
+    if (lane == 0) {
+      d = io.dec[s].d;
+      rng = io.dec[s].range;
+    }
+    d = __shfl(d, 0, 64);
+    rng = __shfl(rng, 0, 64);
+    int cnt = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) cnt += (((rng * (uint64_t)cum[j]) >> 16) <= d) ? 1 : 0;
+    x = wave_sum_i(cnt) - 1;
+  } else if (a.target) {
+    x = a.target[r];
+  }
+  const int jx = x & 3;
+  const int cx = __shfl(jx == 0 ? cum[0] : jx == 1 ? cum[1] : jx == 2 ? cum[2] : cum[3], x >> 2, 64);
+  const int qx = __shfl(jx == 0 ? q[0] : jx == 1 ? q[1] : jx == 2 ? q[2] : q[3], x >> 2, 64);
+  const float zx = __shfl(jx == 0 ? z[0] : jx == 1 ? z[1] : jx == 2 ? z[2] : z[3], x >> 2, 64);
+
+  if (lane == 0) {
+    if (a.mode == 1) {
+      RcEnc en = io.enc[s];
+      rc_encode(en, io.pay + io.pay_off[s], io.pay_cap[s], (uint32_t)cx, (uint32_t)qx);
+      io.enc[s] = en;
+    } else if (a.mode == 2) {
+      RcDec de = io.dec[s];
+      rc_consume(de, io.pay_in + io.pay_off[s], io.pay_cap[s], (uint32_t)cx, (uint32_t)(cx + qx));
+      io.dec[s] = de;
+      io.dst[io.off[s] + (uint64_t)st->step] = (uint8_t)x;
+      if (a.target_out) a.target_out[r] = (uint8_t)x;
+    }
+  }
+  const bool have_target = a.mode != 0 || a.target != nullptr;
+  if (have_target && lane == 0 && a.loss_rows) a.loss_rows[r] = logf(S) - (zx - m);
+  if (have_target && a.want_grad) {
+    const float ir = st->inv_rows;
+    float4 d4;
+    d4.x = (p[0] - (4 * lane + 0 == x ? 1.0f : 0.0f)) * ir;
+    d4.y = (p[1] - (4 * lane + 1 == x ? 1.0f : 0.0f)) * ir;
+    d4.z = (p[2] - (4 * lane + 2 == x ? 1.0f : 0.0f)) * ir;
+    d4.w = (p[3] - (4 * lane + 3 == x ? 1.0f : 0.0f)) * ir;
+    if (a.dz32) *(float4*)(a.dz32 + (size_t)r * 256 + 4 * lane) = d4;
+    if (a.dz16)
+      *(ushort4*)(a.dz16 + (size_t)r * 256 + 4 * lane) =
+          make_ushort4(f2bf(d4.x), f2bf(d4.y), f2bf(d4.z), f2bf(d4.w));
+  }
+  if (a.probs) *(float4*)(a.probs + (size_t)r * 256 + 4 * lane) = make_float4(p[0], p[1], p[2], p[3]);
+  if (a.cum_out) {
+    uint32_t* co = a.cum_out + (size_t)r * 257;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) co[4 * lane + j] = (uint32_t)cum[j];
+    if (lane == 63) co[256] = 65536u;
+  }
+}
+
+void k_head(const StepState* st, HeadArgs a, StreamIO io, int max_rows, hipStream_t s) {
+  hipLaunchKernelGGL(head_kernel, dim3(blocks_for(max_rows, 4)), dim3(256), 0, s, st, a, io);
+}
+
+// ---------------------------------------------------------------------------
+// Column sums over the active rows, fixed order: 4 row slices per column
+// combined in slice order.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) colsum_kernel(const StepState* __restrict__ st,
+                                                     const ColsumJob* __restrict__ jobs,
+                                                     int n_jobs) {
+  int j = 0;
+  while (j + 1 < n_jobs && (int)blockIdx.x >= jobs[j + 1].col_block_begin) ++j;
+  const ColsumJob jb = jobs[j];
+  const int col = ((int)blockIdx.x - jb.col_block_begin) * 64 + (threadIdx.x & 63);
+  const int slice = threadIdx.x >> 6;
+  const int rows = st->rows;
+  float acc = 0.f;
+  if (col < jb.cols) {
+    if (jb.h) {
+      for (int r = slice; r < rows; r += 4) {
+        const float xh = (jb.h[(size_t)r * jb.ld + col] - jb.mean[r]) * jb.rstd[r];
+        acc += jb.src[(size_t)r * jb.ld + col] * xh;
+      }
+    } else {
+      for (int r = slice; r < rows; r += 4) acc += jb.src[(size_t)r * jb.ld + col];
+    }
+  }
+  __shared__ float part[4][64];
+  part[slice][threadIdx.x & 63] = acc;
+  __syncthreads();
+  if (slice == 0 && col < jb.cols) {
+    const float tot = (part[0][threadIdx.x] + part[1][threadIdx.x]) +
+                      (part[2][threadIdx.x] + part[3][threadIdx.x]);
+    jb.dst[col] = tot * (jb.scale == 0.0f ? st->inv_rows : jb.scale);
+  }
+}
+
+void k_colsum(const StepState* st, const ColsumJob* jobs, int n_jobs, int total_blocks,
+              hipStream_t s) {
+  if (total_blocks == 0) return;
+  hipLaunchKernelGGL(colsum_kernel, dim3(total_blocks), dim3(256), 0, s, st, jobs, n_jobs);
+}
+
+// ---------------------------------------------------------------------------
+// Embedding gradient: dEmb[v] = sum over (row, position) with ctx = v of the
+// matching E-slice of dX.  Chunks of rows accumulate in LDS, cell (v, e)
+// owned by one thread so the additions happen in row-major pair order; the
+// chunk partials are then summed in chunk order.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) emb_grad_partial_kernel(
+    const StepState* __restrict__ st, const uint8_t* __restrict__ ctx, const float* __restrict__ dx,
+    int C, int E, int chunk_rows, float* __restrict__ partial) {
+  extern __shared__ float acc[];  // [256][E]
+  const int rows = st->rows;
+  const int r0 = blockIdx.x * chunk_rows;
+  const int G = 256 / E;
+  const int g = threadIdx.x / E, e = threadIdx.x % E;
+  float* out = partial + (size_t)blockIdx.x * 256 * E;
+  if (g < G)
+    for (int v = g; v < 256; v += G) acc[v * E + e] = 0.f;
+  if (r0 < rows && g < G) {
+    const int r1 = min(rows, r0 + chunk_rows);
+    const int F = C * E;
+    for (int r = r0; r < r1; ++r) {
+      for (int c = 0; c < C; ++c) {
+        const int v = ctx[r * C + c];
+        if (v % G == g) acc[v * E + e] += dx[(size_t)r * F + c * E + e];
+      }
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < 256 * E; k += 256) out[k] = acc[k];
+}
+
+__global__ void emb_grad_reduce_kernel(const StepState* __restrict__ st,
+                                       const float* __restrict__ partial, int chunk_rows, int n,
+                                       float* __restrict__ demb) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int nb = (st->rows + chunk_rows - 1) / chunk_rows;
+  float s = 0.f;
+  for (int b = 0; b < nb; ++b) s += partial[(size_t)b * n + k];
+  demb[k] = s;
+}
+
+void k_emb_grad(const StepState* st, const uint8_t* ctx, const float* dx, int C, int E,
+                float* partial, int chunk_rows, int max_rows, float* demb, hipStream_t s) {
+  const int nb = (max_rows + chunk_rows - 1) / chunk_rows;
+  hipLaunchKernelGGL(emb_grad_partial_kernel, dim3(nb), dim3(256), 256 * E * sizeof(float), s, st,
+                     ctx, dx, C, E, chunk_rows, partial);
+  const int n = 256 * E;
+  hipLaunchKernelGGL(emb_grad_reduce_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, st, partial,
+                     chunk_rows, n, demb);
+}
+
+// ---------------------------------------------------------------------------
+// Adam on the shared parameters (FP32 master, optional BF16 shadow).
+// ---------------------------------------------------------------------------
+__global__ void adam_kernel(const StepState* __restrict__ st, float* __restrict__ p,
+                            const float* __restrict__ g, float* __restrict__ m,
+                            float* __restrict__ v, bf16_t* __restrict__ p16, size_t n,
+                            AdamCfg ac) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float lr_bc = ac.lr / st->bc1;
+  const float inv_bc2 = 1.0f / st->bc2;
+  const float gr = g[i];
+  const float mm = ac.beta1 * m[i] + (1.0f - ac.beta1) * gr;
+  const float vv = ac.beta2 * v[i] + (1.0f - ac.beta2) * gr * gr;
+  const float pp = p[i] - lr_bc * mm / (sqrtf(vv * inv_bc2) + ac.eps);
+  m[i] = mm;
+  v[i] = vv;
+  p[i] = pp;
+  if (p16) p16[i] = f2bf(pp);
+}
+
+void k_adam(const StepState* st, float* p, const float* g, float* m, float* v, bf16_t* p16,
+            size_t n, AdamCfg ac, hipStream_t s) {
+  hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, st, p, g, m, v, p16, n,
+                     ac);
+}
+
+// ---------------------------------------------------------------------------
+// Initialisation (SplitMix64, Steele, Lea & Flood 2014)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ void init_uniform_kernel(float* __restrict__ dst, size_t n, uint64_t seed, uint32_t tid,
+                                    uint64_t start, float bound) {
+  const size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const uint64_t r = splitmix64(seed + ((uint64_t)tid << 40) + start + j);
+  const int k = (int)(r >> 40) - (1 << 23);
+  const float a = (float)k * (1.0f / 8388608.0f);
+  dst[j] = a * bound;
+}
+
+void k_init_uniform(float* dst, size_t n, uint64_t seed, uint32_t tid, uint64_t start, float bound,
+                    hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(init_uniform_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, dst, n, seed,
+                     tid, start, bound);
+}
+
+__global__ void fill_kernel(float* dst, size_t n, float v) {
+  const size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n) dst[j] = v;
+}
+void k_fill(float* dst, size_t n, float v, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(fill_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, dst, n, v);
+}
+
+__global__ void to_bf16_kernel(const float* src, bf16_t* dst, size_t n) {
+  const size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n) dst[j] = f2bf(src[j]);
+}
+void k_to_bf16(const float* src, bf16_t* dst, size_t n, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(to_bf16_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, src, dst, n);
+}
+
+// ---------------------------------------------------------------------------
+// Coder lanes (one thread per stream)
+// ---------------------------------------------------------------------------
+// The first t bytes of each stream: frequency 256 each (Algorithm 1, "with
+// equal probability"); also initialises the coder state.
+__global__ void uniform_prefix_kernel(StreamIO io, int n_streams, int C, bool decoding) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_streams) return;
+  const uint64_t len = io.lens[s];
+  const uint64_t n = len < (uint64_t)C ? len : (uint64_t)C;
+  if (!decoding) {
+    RcEnc e;
+    rc_enc_init(e);
+    uint8_t* out = io.pay + io.pay_off[s];
+    const uint64_t cap = io.pay_cap[s];
+    const uint8_t* in = io.src + io.off[s];
+    for (uint64_t i = 0; i < n; ++i) rc_encode(e, out, cap, 256u * in[i], 256u);
+    io.enc[s] = e;
+  } else {
+    RcDec d;
+    const uint8_t* in = io.pay_in + io.pay_off[s];
+    const uint64_t plen = io.pay_cap[s];
+    rc_dec_init(d, in, plen);
+    uint8_t* out = io.dst + io.off[s];
+    for (uint64_t i = 0; i < n; ++i) {
+      // largest x with (range * 256x) >> 16 <= d
+      uint32_t lo = 0, hi = 256;
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (((d.range * (uint64_t)(256u * mid)) >> 16) <= d.d) lo = mid; else hi = mid;
+      }
+      out[i] = (uint8_t)lo;
+      rc_consume(d, in, plen, 256u * lo, 256u * lo + 256u);
+    }
+    io.dec[s] = d;
+  }
+}
+
+void k_uniform_prefix(StreamIO io, int n_streams, int C, bool decoding, hipStream_t s) {
+  hipLaunchKernelGGL(uniform_prefix_kernel, dim3(blocks_for(n_streams, 64)), dim3(64), 0, s, io,
+                     n_streams, C, decoding);
+}
+
+__global__ void rc_finish_kernel(StreamIO io, int n_streams) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_streams) return;
+  RcEnc e = io.enc[s];
+  rc_finish(e, io.pay + io.pay_off[s], io.pay_cap[s]);
+  io.enc[s] = e;
+}
+
+void k_rc_finish(StreamIO io, int n_streams, hipStream_t s) {
+  hipLaunchKernelGGL(rc_finish_kernel, dim3(blocks_for(n_streams, 64)), dim3(64), 0, s, io,
+                     n_streams);
+}
+
+__global__ void rc_table_encode_kernel(const uint32_t* __restrict__ cum,
+                                       const uint8_t* __restrict__ sym, size_t n_steps,
+                                       size_t n_streams, uint8_t* __restrict__ out, size_t cap,
+                                       uint64_t* __restrict__ out_lens) {
+  const size_t s = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_streams) return;
+  RcEnc e;
+  rc_enc_init(e);
+  uint8_t* o = out + s * cap;
+  for (size_t t = 0; t < n_steps; ++t) {
+    const uint32_t* c = cum + (t * n_streams + s) * 257;
+    const uint32_t x = sym[t * n_streams + s];
+    rc_encode(e, o, cap, c[x], c[x + 1] - c[x]);
+  }
+  rc_finish(e, o, cap);
+  out_lens[s] = e.pos;
+}
+
+void k_rc_table_encode(const uint32_t* cum, const uint8_t* sym, size_t n_steps, size_t n_streams,
+                       uint8_t* out, size_t cap, uint64_t* out_lens, hipStream_t s) {
+  hipLaunchKernelGGL(rc_table_encode_kernel, dim3(blocks_for(n_streams, 64)), dim3(64), 0, s, cum,
+                     sym, n_steps, n_streams, out, cap, out_lens);
+}
+
+__global__ void rc_table_decode_kernel(const uint32_t* __restrict__ cum,
+                                       const uint8_t* __restrict__ in,
+                                       const uint64_t* __restrict__ in_lens, size_t cap,
+                                       size_t n_steps, size_t n_streams, uint8_t* __restrict__ sym) {
+  const size_t s = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_streams) return;
+  const uint8_t* p = in + s * cap;
+  const uint64_t len = in_lens[s] < cap ? in_lens[s] : cap;
+  RcDec d;
+  rc_dec_init(d, p, len);
+  for (size_t t = 0; t < n_steps; ++t) {
+    const uint32_t* c = cum + (t * n_streams + s) * 257;
+    const uint32_t x = rc_find(d, c);
+    rc_consume(d, p, len, c[x], c[x + 1]);
+    sym[t * n_streams + s] = (uint8_t)x;
+  }
+}
+
+void k_rc_table_decode(const uint32_t* cum, const uint8_t* in, const uint64_t* in_lens, size_t cap,
+                       size_t n_steps, size_t n_streams, uint8_t* sym, hipStream_t s) {
+  hipLaunchKernelGGL(rc_table_decode_kernel, dim3(blocks_for(n_streams, 64)), dim3(64), 0, s, cum,
+                     in, in_lens, cap, n_steps, n_streams, sym);
+}
+
+// CRC-32 (IEEE 802.3, reflected polynomial 0xEDB88320), one thread per stream.
+__global__ void crc32_kernel(const uint8_t* __restrict__ data, const uint64_t* __restrict__ off,
+                             const uint64_t* __restrict__ lens, int n, uint32_t* __restrict__ crc) {
+  __shared__ uint32_t table[256];
+  for (int i = threadIdx.x; i < 256; i += blockDim.x) {
+    uint32_t c = (uint32_t)i;
+    for (int k = 0; k < 8; ++k) c = (c & 1u) ? (0xEDB88320u ^ (c >> 1)) : (c >> 1);
+    table[i] = c;
+  }
+  __syncthreads();
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const uint8_t* p = data + off[s];
+  const uint64_t len = lens[s];
+  uint32_t c = 0xFFFFFFFFu;
+  for (uint64_t i = 0; i < len; ++i) c = table[(c ^ p[i]) & 0xFFu] ^ (c >> 8);
+  crc[s] = c ^ 0xFFFFFFFFu;
+}
+
+void k_crc32(const uint8_t* data, const uint64_t* off, const uint64_t* lens, int n, uint32_t* crc,
+             hipStream_t s) {
+  hipLaunchKernelGGL(crc32_kernel, dim3(blocks_for(n, 64)), dim3(64), 0, s, data, off, lens, n, crc);
+}
+
+__global__ void gather_payloads_kernel(const uint8_t* __restrict__ pay,
+                                       const uint64_t* __restrict__ pay_off,
+                                       const uint64_t* __restrict__ len,
+                                       const uint64_t* __restrict__ dst_off,
+                                       uint8_t* __restrict__ dst) {
+  const int s = blockIdx.x;
+  const uint8_t* src = pay + pay_off[s];
+  uint8_t* d = dst + dst_off[s];
+  const uint64_t n = len[s];
+  for (uint64_t i = threadIdx.x; i < n; i += blockDim.x) d[i] = src[i];
+}
+
+void k_gather_payloads(const uint8_t* pay, const uint64_t* pay_off, const uint64_t* len,
+                       const uint64_t* dst_off, uint8_t* dst, int n, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(gather_payloads_kernel, dim3(n), dim3(256), 0, s, pay, pay_off, len, dst_off,
+                     dst);
+}
+
+}  // namespace edpc

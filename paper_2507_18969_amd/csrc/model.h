@@ -1,0 +1,133 @@
+// The model object: parameters, Adam state, per-stream FDM slices,
+// activation workspace, and the launch sequence of one step.
+#pragma once
+#include <string>
+#include <vector>
+
+#include "../../include/edpc.h"
+#include "gemm.h"
+#include "kernels.h"
+
+namespace edpc {
+
+// Thrown inside the library, turned into an edpc_status at the C boundary.
+struct Error {
+  edpc_status status;
+  std::string msg;
+};
+[[noreturn]] void fail(edpc_status st, const std::string& msg);
+void hip_check(hipError_t e, const char* what);
+
+// Product slots that carry their own tile configuration.
+enum ProductSlot : int {
+  PS_LTE_DOWN = 0,
+  PS_LTE_UP,
+  PS_GATE,
+  PS_OUT,
+  PS_HEAD,
+  PS_HEAD_BWD,
+  PS_GATE_BWD,
+  PS_DZ,
+  PS_LTE_UP_BWD,
+  PS_LTE_DOWN_BWD,
+  PS_WGRAD,
+  PS_COUNT
+};
+
+// Kernel configuration: one tile id per product slot, plus the numerics
+// revision of the kernels.  Encoded into 64 bits for the container.
+constexpr uint32_t kNumericsRevision = 1;
+struct KernelConfig {
+  int tile[PS_COUNT];
+  uint64_t encode() const;
+  static bool decode(uint64_t id, KernelConfig* out);
+};
+
+struct TensorInfo {
+  std::string name;
+  size_t off;    // element offset in the flat shared buffers
+  size_t numel;
+  uint32_t tid;  // counter-RNG tensor id (0: constant)
+  float bound;   // RNG bound or constant value
+};
+
+enum StepMode : int { MODE_PLAIN = 0, MODE_ENCODE = 1, MODE_DECODE = 2 };
+
+struct StepOutputs {
+  float* probs = nullptr;
+  uint32_t* cum = nullptr;
+  float* loss = nullptr;
+  bool backward = false;
+  bool update = false;
+  bool keep_fdm_grad = false;
+  bool has_target = true;  // plain steps: targets staged in tgt
+};
+
+struct Model {
+  edpc_config cfg;
+  int C, E, F, L, N, H, K;
+  bool bf16;
+  size_t n_slots, max_rows;
+  KernelConfig kc;
+  std::vector<TensorInfo> tens;
+  size_t P = 0;  // shared parameter count (with alignment padding)
+  uint64_t tau = 0;
+
+  // device state
+  float *param = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr;
+  bf16_t* p16 = nullptr;
+  float *U = nullptr, *mU = nullptr, *vU = nullptr, *dUkeep = nullptr;
+  StepState* st = nullptr;
+
+  // workspace
+  uint8_t *ctx = nullptr, *tgt = nullptr;
+  uint32_t* slot = nullptr;
+  float* X32 = nullptr;
+  bf16_t* X16 = nullptr;
+  float* X1 = nullptr;
+  float* Y32 = nullptr;
+  bf16_t* Y16 = nullptr;
+  std::vector<float*> Hs;
+  bf16_t* HN16 = nullptr;
+  std::vector<float*> Z32, mean, rstd, Abr, G32, dA32, dZ, dH32;
+  std::vector<bf16_t*> Z16, G16, dA16, dH16;
+  float *logits = nullptr, *dz32 = nullptr, *loss_rows = nullptr, *loss_out = nullptr;
+  bf16_t* dz16 = nullptr;
+  float *dY = nullptr, *dX1_32 = nullptr, *dX = nullptr, *emb_partial = nullptr;
+  bf16_t* dX1_16 = nullptr;
+  WgradProblem* d_wg = nullptr;
+  int n_wg = 0, wg_tiles = 0;
+  ColsumJob* d_cs = nullptr;
+  int n_cs = 0, cs_blocks = 0;
+  ColsumJob* d_loss_job = nullptr;
+  int emb_chunk = 16;
+  std::vector<void*> allocs;
+
+  Model(const edpc_config& c, size_t n_slots, size_t max_rows, const KernelConfig* kc);
+  ~Model();
+  Model(const Model&) = delete;
+  Model& operator=(const Model&) = delete;
+
+  const TensorInfo& tensor(const std::string& name) const;
+  float* P_(const std::string& name) { return param + tensor(name).off; }
+  float* G_(const std::string& name) { return grad + tensor(name).off; }
+  const void* W_(const std::string& name) const;  // weight operand (fp32 or bf16 shadow)
+
+  void init_params(hipStream_t s);
+  void build_tables(hipStream_t s);
+  // One step on rows already staged in ctx/tgt/slot with st set; grid_rows
+  // bounds the launch grids (>= st->rows).
+  void step(StepMode mode, const StreamIO& io, const StepOutputs& out, int grid_rows,
+            hipStream_t s);
+
+  static KernelConfig default_config(const edpc_config& c, size_t rows);
+  static void validate(const edpc_config& c);
+
+ private:
+  template <class T>
+  T* dalloc(size_t n);
+  void gemm(int slot, bool ak, bool bk, EpiKind epi, int nb, GemmArgs g, int grid_rows,
+            hipStream_t s);
+};
+
+}  // namespace edpc

@@ -1,0 +1,429 @@
+// Model object and the launch sequence of one step (Algorithm 1, lines
+// "Model", "Encode/Decode", "loss", "backward", "update").
+#include "model.h"
+
+#include <cmath>
+#include <cstring>
+
+namespace edpc {
+
+[[noreturn]] void fail(edpc_status st, const std::string& msg) { throw Error{st, msg}; }
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) {
+    if (e == hipErrorOutOfMemory) fail(EDPC_E_NOMEM, std::string(what) + ": out of device memory");
+    fail(EDPC_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  }
+}
+
+uint64_t KernelConfig::encode() const {
+  uint64_t id = (uint64_t)kNumericsRevision << 48;
+  for (int i = 0; i < PS_COUNT; ++i) id |= (uint64_t)(tile[i] & 7) << (3 * i);
+  return id;
+}
+
+bool KernelConfig::decode(uint64_t id, KernelConfig* out) {
+  if ((id >> 48) != kNumericsRevision) return false;
+  if ((id >> (3 * PS_COUNT)) & ((1ull << (48 - 3 * PS_COUNT)) - 1)) return false;
+  for (int i = 0; i < PS_COUNT; ++i) {
+    const int t = (int)((id >> (3 * i)) & 7);
+    if (t >= TILE_COUNT) return false;
+    out->tile[i] = t;
+  }
+  return true;
+}
+
+static bool pow2(uint32_t x) { return x && !(x & (x - 1)); }
+
+void Model::validate(const edpc_config& c) {
+  if (c.struct_size != sizeof(edpc_config)) fail(EDPC_E_INVALID_ARG, "edpc_config.struct_size mismatch");
+  if (c.context < 1 || c.context > 256) fail(EDPC_E_INVALID_ARG, "context must be in 1..256");
+  if (!pow2(c.embed) || c.embed < 4 || c.embed > 64) fail(EDPC_E_INVALID_ARG, "embed must be a power of two in 4..64");
+  if (!pow2(c.latent) || c.latent < 16 || c.latent > 256) fail(EDPC_E_INVALID_ARG, "latent must be a power of two in 16..256");
+  if (c.blocks > 16) fail(EDPC_E_INVALID_ARG, "blocks must be <= 16");
+  if (c.hidden < 16 || c.hidden % 16 || c.hidden > 8192) fail(EDPC_E_INVALID_ARG, "hidden must be a multiple of 16 in 16..8192");
+  if (c.branches < 1 || c.branches > 3) fail(EDPC_E_INVALID_ARG, "branches must be 1..3");
+  if (c.cdf_bits != 16) fail(EDPC_E_INVALID_ARG, "only 16-bit CDFs are supported");
+  if (c.precision != EDPC_FP32 && c.precision != EDPC_BF16) fail(EDPC_E_INVALID_ARG, "unknown precision");
+  if (c.flags & ~EDPC_CFG_ZERO_HEAD) fail(EDPC_E_INVALID_ARG, "unknown config flags");
+  if ((c.context * c.embed) % 8) fail(EDPC_E_INVALID_ARG, "context * embed must be a multiple of 8");
+  if ((uint64_t)c.context * c.embed > 16384) fail(EDPC_E_INVALID_ARG, "context * embed must be <= 16384");
+  if (!(c.lr >= 0.f) || !(c.beta1 >= 0.f && c.beta1 < 1.f) || !(c.beta2 >= 0.f && c.beta2 < 1.f) || !(c.eps > 0.f))
+    fail(EDPC_E_INVALID_ARG, "invalid Adam constants");
+}
+
+KernelConfig Model::default_config(const edpc_config& c, size_t rows) {
+  KernelConfig k;
+  const int big = rows >= 4096 ? TILE_128x128 : rows >= 1024 ? TILE_64x64 : TILE_32x32;
+  for (int i = 0; i < PS_COUNT; ++i) k.tile[i] = big;
+  const int mid = rows >= 4096 ? TILE_128x64 : rows >= 1024 ? TILE_64x32 : TILE_32x32;
+  k.tile[PS_LTE_DOWN] = mid;
+  k.tile[PS_LTE_UP_BWD] = mid;
+  k.tile[PS_WGRAD] = rows >= 1024 ? TILE_64x64 : TILE_32x32;
+  (void)c;
+  return k;
+}
+
+template <class T>
+T* Model::dalloc(size_t n) {
+  void* p = nullptr;
+  if (n == 0) n = 1;
+  hip_check(hipMalloc(&p, n * sizeof(T)), "hipMalloc");
+  allocs.push_back(p);
+  return (T*)p;
+}
+
+static size_t align64(size_t x) { return (x + 63) & ~(size_t)63; }
+
+Model::Model(const edpc_config& c, size_t nslots, size_t rows, const KernelConfig* kcfg)
+    : cfg(c), n_slots(nslots), max_rows(rows) {
+  validate(c);
+  if (nslots == 0 || rows == 0) fail(EDPC_E_INVALID_ARG, "n_slots and max_rows must be >= 1");
+  if (rows > (1u << 24)) fail(EDPC_E_INVALID_ARG, "max_rows too large");
+  C = c.context;
+  E = c.embed;
+  F = C * E;
+  L = c.latent;
+  N = c.blocks;
+  H = c.hidden;
+  K = c.branches;
+  bf16 = c.precision == EDPC_BF16;
+  kc = kcfg ? *kcfg : default_config(c, rows);
+
+  // Flat layout of the shared parameters; each tensor starts 64-aligned.
+  auto add = [&](const std::string& n, size_t numel, uint32_t tid, double bound) {
+    tens.push_back(TensorInfo{n, P, numel, tid, (float)bound});
+    P = align64(P + numel);
+  };
+  const double bF = 1.0 / std::sqrt((double)F), bL = 1.0 / std::sqrt((double)L),
+               bH = 1.0 / std::sqrt((double)H);
+  add("emb", 256 * (size_t)E, 1, std::sqrt(3.0));
+  add("w1", (size_t)L * F, 2, bF);
+  add("b1", L, 3, bF);
+  add("w2", (size_t)F * L, 5, bL);
+  add("b2", F, 6, bL);
+  for (int j = 0; j < N; ++j) {
+    add("ln" + std::to_string(j) + ".gamma", F, 0, 1.0);
+    add("ln" + std::to_string(j) + ".beta", F, 0, 0.0);
+    // branch weights contiguous ([K*H, F]) so one product covers all paths
+    const size_t wbase = P;
+    for (int i = 0; i < K; ++i) {
+      tens.push_back(TensorInfo{"blk" + std::to_string(j) + ".w" + std::to_string(i),
+                                wbase + (size_t)i * H * F, (size_t)H * F, 16u + 16u * j + 2u * i,
+                                (float)bF});
+    }
+    P = align64(wbase + (size_t)K * H * F);
+    const size_t bbase = P;
+    for (int i = 0; i < K; ++i) {
+      tens.push_back(TensorInfo{"blk" + std::to_string(j) + ".b" + std::to_string(i),
+                                bbase + (size_t)i * H, (size_t)H, 17u + 16u * j + 2u * i,
+                                (float)bF});
+    }
+    P = align64(bbase + (size_t)K * H);
+    add("blk" + std::to_string(j) + ".wo", (size_t)F * H, 16u + 16u * j + 14u, bH);
+    add("blk" + std::to_string(j) + ".bo", F, 16u + 16u * j + 15u, bH);
+  }
+  const bool zh = (c.flags & EDPC_CFG_ZERO_HEAD) != 0;
+  add("wh", 256 * (size_t)F, zh ? 0 : 7, zh ? 0.0 : bF);
+  add("bh", 256, zh ? 0 : 8, zh ? 0.0 : bF);
+
+  param = dalloc<float>(P);
+  grad = dalloc<float>(P);
+  m = dalloc<float>(P);
+  v = dalloc<float>(P);
+  if (bf16) p16 = dalloc<bf16_t>(P);
+  const size_t fdm = n_slots * (size_t)L * L;
+  U = dalloc<float>(fdm);
+  mU = dalloc<float>(fdm);
+  vU = dalloc<float>(fdm);
+  st = dalloc<StepState>(1);
+
+  const size_t R = max_rows;
+  ctx = dalloc<uint8_t>(R * C);
+  tgt = dalloc<uint8_t>(R);
+  slot = dalloc<uint32_t>(R);
+  if (bf16) X16 = dalloc<bf16_t>(R * F); else X32 = dalloc<float>(R * F);
+  X1 = dalloc<float>(R * L);
+  if (bf16) Y16 = dalloc<bf16_t>(R * L); else Y32 = dalloc<float>(R * L);
+  for (int j = 0; j <= N; ++j) Hs.push_back(dalloc<float>(R * F));
+  if (bf16) HN16 = dalloc<bf16_t>(R * F);
+  for (int j = 0; j < N; ++j) {
+    if (bf16) Z16.push_back(dalloc<bf16_t>(R * F)); else Z32.push_back(dalloc<float>(R * F));
+    mean.push_back(dalloc<float>(R));
+    rstd.push_back(dalloc<float>(R));
+    Abr.push_back(dalloc<float>(R * K * H));
+    if (bf16) G16.push_back(dalloc<bf16_t>(R * H)); else G32.push_back(dalloc<float>(R * H));
+    dA32.push_back(dalloc<float>(R * K * H));
+    if (bf16) dA16.push_back(dalloc<bf16_t>(R * K * H));
+    dZ.push_back(dalloc<float>(R * F));
+  }
+  for (int j = 0; j <= N; ++j) {
+    dH32.push_back(dalloc<float>(R * F));
+    if (bf16) dH16.push_back(dalloc<bf16_t>(R * F));
+  }
+  logits = dalloc<float>(R * 256);
+  dz32 = dalloc<float>(R * 256);
+  if (bf16) dz16 = dalloc<bf16_t>(R * 256);
+  loss_rows = dalloc<float>(R);
+  loss_out = dalloc<float>(1);
+  dY = dalloc<float>(R * L);
+  dX1_32 = dalloc<float>(R * L);
+  if (bf16) dX1_16 = dalloc<bf16_t>(R * L);
+  dX = dalloc<float>(R * F);
+  emb_partial = dalloc<float>(((R + emb_chunk - 1) / emb_chunk) * 256 * (size_t)E);
+}
+
+Model::~Model() {
+  for (void* p : allocs) (void)hipFree(p);
+}
+
+const TensorInfo& Model::tensor(const std::string& name) const {
+  for (const auto& t : tens)
+    if (t.name == name) return t;
+  fail(EDPC_E_INVALID_ARG, "no tensor " + name);
+}
+
+const void* Model::W_(const std::string& name) const {
+  const TensorInfo& t = tensor(name);
+  return bf16 ? (const void*)(p16 + t.off) : (const void*)(param + t.off);
+}
+
+void Model::init_params(hipStream_t s) {
+  hip_check(hipMemsetAsync(param, 0, P * sizeof(float), s), "memset");
+  for (const auto& t : tens) {
+    if (t.tid) k_init_uniform(param + t.off, t.numel, cfg.seed, t.tid, 0, t.bound, s);
+    else k_fill(param + t.off, t.numel, t.bound, s);
+  }
+  k_init_uniform(U, n_slots * (size_t)L * L, cfg.seed, 4, 0,
+                 (float)(1.0 / std::sqrt((double)L)), s);
+  hip_check(hipMemsetAsync(m, 0, P * sizeof(float), s), "memset");
+  hip_check(hipMemsetAsync(v, 0, P * sizeof(float), s), "memset");
+  hip_check(hipMemsetAsync(grad, 0, P * sizeof(float), s), "memset");
+  hip_check(hipMemsetAsync(mU, 0, n_slots * (size_t)L * L * sizeof(float), s), "memset");
+  hip_check(hipMemsetAsync(vU, 0, n_slots * (size_t)L * L * sizeof(float), s), "memset");
+  if (bf16) k_to_bf16(param, p16, P, s);
+  hip_check(hipGetLastError(), "init");
+  tau = 0;
+}
+
+void Model::build_tables(hipStream_t s) {
+  // weight-gradient products (sum over rows)
+  std::vector<WgradProblem> wg;
+  const TileShape ts = tile_shape(kc.tile[PS_WGRAD]);
+  auto addw = [&](const void* dout, const void* in, float* dw, int Mo, int Ni) {
+    WgradProblem p;
+    p.dout = dout;
+    p.in = in;
+    p.dw = dw;
+    p.M = Mo;
+    p.N = Ni;
+    p.tiles_n = (Ni + ts.bn - 1) / ts.bn;
+    p.tile_begin = wg_tiles;
+    wg_tiles += p.tiles_n * ((Mo + ts.bm - 1) / ts.bm);
+    wg.push_back(p);
+  };
+  const void* dz_op = bf16 ? (const void*)dz16 : (const void*)dz32;
+  const void* hN_op = bf16 ? (const void*)HN16 : (const void*)Hs[N];
+  addw(dz_op, hN_op, G_("wh"), 256, F);
+  for (int j = 0; j < N; ++j) {
+    const std::string b = "blk" + std::to_string(j);
+    addw(bf16 ? (const void*)dH16[j + 1] : (const void*)dH32[j + 1],
+         bf16 ? (const void*)G16[j] : (const void*)G32[j], G_(b + ".wo"), F, H);
+    addw(bf16 ? (const void*)dA16[j] : (const void*)dA32[j],
+         bf16 ? (const void*)Z16[j] : (const void*)Z32[j], G_(b + ".w0"), K * H, F);
+  }
+  addw(bf16 ? (const void*)dH16[0] : (const void*)dH32[0], bf16 ? (const void*)Y16 : (const void*)Y32,
+       G_("w2"), F, L);
+  addw(bf16 ? (const void*)dX1_16 : (const void*)dX1_32, bf16 ? (const void*)X16 : (const void*)X32,
+       G_("w1"), L, F);
+  n_wg = (int)wg.size();
+  d_wg = dalloc<WgradProblem>(wg.size());
+  hip_check(hipMemcpyAsync(d_wg, wg.data(), wg.size() * sizeof(WgradProblem), hipMemcpyHostToDevice, s),
+            "copy");
+
+  // column sums: bias gradients, LayerNorm affine gradients
+  std::vector<ColsumJob> cs;
+  auto addc = [&](const float* src, int cols, int ld, float* dst, const float* h,
+                  const float* mu, const float* rs) {
+    ColsumJob j;
+    j.src = src;
+    j.h = h;
+    j.mean = mu;
+    j.rstd = rs;
+    j.dst = dst;
+    j.cols = cols;
+    j.ld = ld;
+    j.col_block_begin = cs_blocks;
+    j.scale = 1.0f;
+    cs_blocks += (cols + 63) / 64;
+    cs.push_back(j);
+  };
+  addc(dz32, 256, 256, G_("bh"), nullptr, nullptr, nullptr);
+  for (int j = 0; j < N; ++j) {
+    const std::string b = "blk" + std::to_string(j);
+    addc(dH32[j + 1], F, F, G_(b + ".bo"), nullptr, nullptr, nullptr);
+    addc(dA32[j], K * H, K * H, G_(b + ".b0"), nullptr, nullptr, nullptr);
+    addc(dZ[j], F, F, G_("ln" + std::to_string(j) + ".beta"), nullptr, nullptr, nullptr);
+    addc(dZ[j], F, F, G_("ln" + std::to_string(j) + ".gamma"), Hs[j], mean[j], rstd[j]);
+  }
+  addc(dH32[0], F, F, G_("b2"), nullptr, nullptr, nullptr);
+  addc(dX1_32, L, L, G_("b1"), nullptr, nullptr, nullptr);
+  n_cs = (int)cs.size();
+  d_cs = dalloc<ColsumJob>(cs.size());
+  hip_check(hipMemcpyAsync(d_cs, cs.data(), cs.size() * sizeof(ColsumJob), hipMemcpyHostToDevice, s),
+            "copy");
+  ColsumJob lj;
+  lj.src = loss_rows;
+  lj.h = nullptr;
+  lj.mean = lj.rstd = nullptr;
+  lj.dst = loss_out;
+  lj.cols = 1;
+  lj.ld = 1;
+  lj.col_block_begin = 0;
+  lj.scale = 0.0f;  // scale by 1/rows
+  d_loss_job = dalloc<ColsumJob>(1);
+  hip_check(hipMemcpyAsync(d_loss_job, &lj, sizeof(lj), hipMemcpyHostToDevice, s), "copy");
+  hip_check(hipStreamSynchronize(s), "sync");
+}
+
+void Model::gemm(int ps, bool ak, bool bk, EpiKind epi, int nb, GemmArgs g, int grid_rows,
+                 hipStream_t s) {
+  g.st = st;
+  hip_check(launch_gemm(kc.tile[ps], bf16, ak, bk, epi, nb, g, grid_rows, s), "gemm launch");
+}
+
+static GemmArgs ga() {
+  GemmArgs g;
+  std::memset(&g, 0, sizeof(g));
+  return g;
+}
+
+void Model::step(StepMode mode, const StreamIO& io, const StepOutputs& out, int grid_rows,
+                 hipStream_t s) {
+  const int R = grid_rows;
+  const void* X_op = bf16 ? (const void*)X16 : (const void*)X32;
+  // ---- forward -----------------------------------------------------------
+  k_embed(st, ctx, P_("emb"), C, E, X32, X16, R, s);
+  {  // LTE down-projection (Eq. 14)
+    GemmArgs g = ga();
+    g.A = X_op; g.lda = F; g.B = W_("w1"); g.ldb = F;
+    g.M = R; g.m_rows = 1; g.N = L; g.K = F;
+    g.bias = P_("b1"); g.out32 = X1; g.ld_out32 = L;
+    gemm(PS_LTE_DOWN, true, true, EPI_STORE, 1, g, R, s);
+  }
+  k_fdm_fwd(st, X1, U, slot, L, Y32, Y16, R, s);  // Eq. 15
+  {  // LTE up-projection (Eq. 16)
+    GemmArgs g = ga();
+    g.A = bf16 ? (const void*)Y16 : (const void*)Y32; g.lda = L; g.B = W_("w2"); g.ldb = L;
+    g.M = R; g.m_rows = 1; g.N = F; g.K = L;
+    g.bias = P_("b2"); g.out32 = Hs[0]; g.ld_out32 = F;
+    if (N == 0 && bf16) { g.out16 = HN16; g.ld_out16 = F; }
+    gemm(PS_LTE_UP, true, true, EPI_STORE, 1, g, R, s);
+  }
+  for (int j = 0; j < N; ++j) {  // refinement blocks (Eqs. 9-13)
+    const std::string b = "blk" + std::to_string(j), ln = "ln" + std::to_string(j);
+    k_ln_fwd(st, Hs[j], P_(ln + ".gamma"), P_(ln + ".beta"), F, bf16 ? nullptr : Z32[j],
+             bf16 ? Z16[j] : nullptr, mean[j], rstd[j], R, s);
+    GemmArgs g = ga();
+    g.A = bf16 ? (const void*)Z16[j] : (const void*)Z32[j]; g.lda = F;
+    g.B = W_(b + ".w0"); g.ldb = F; g.b_branch_stride = (long long)H * F;
+    g.M = R; g.m_rows = 1; g.N = H; g.K = F;
+    g.bias = P_(b + ".b0"); g.bias_branch_stride = H;
+    g.aux = Abr[j]; g.ld_aux = K * H; g.aux_branch = H;
+    if (bf16) { g.out16 = G16[j]; g.ld_out16 = H; } else { g.out32 = G32[j]; g.ld_out32 = H; }
+    gemm(PS_GATE, true, true, EPI_GATE_FWD, K, g, R, s);
+    GemmArgs o = ga();
+    o.A = bf16 ? (const void*)G16[j] : (const void*)G32[j]; o.lda = H;
+    o.B = W_(b + ".wo"); o.ldb = H;
+    o.M = R; o.m_rows = 1; o.N = F; o.K = H;
+    o.bias = P_(b + ".bo"); o.resid = Hs[j]; o.ld_resid = F;
+    o.out32 = Hs[j + 1]; o.ld_out32 = F;
+    if (j == N - 1 && bf16) { o.out16 = HN16; o.ld_out16 = F; }
+    gemm(PS_OUT, true, true, EPI_STORE, 1, o, R, s);
+  }
+  const void* HN_op = bf16 ? (const void*)HN16 : (const void*)Hs[N];
+  {  // head logits
+    GemmArgs g = ga();
+    g.A = HN_op; g.lda = F; g.B = W_("wh"); g.ldb = F;
+    g.M = R; g.m_rows = 1; g.N = 256; g.K = F;
+    g.bias = P_("bh"); g.out32 = logits; g.ld_out32 = 256;
+    gemm(PS_HEAD, true, true, EPI_STORE, 1, g, R, s);
+  }
+  const bool backward = out.backward || out.update || out.keep_fdm_grad;
+  HeadArgs ha;
+  std::memset(&ha, 0, sizeof(ha));
+  ha.logits = logits;
+  ha.target = (mode == MODE_DECODE || (mode == MODE_PLAIN && !out.has_target)) ? nullptr : tgt;
+  ha.target_out = mode == MODE_DECODE ? tgt : nullptr;
+  ha.dz32 = dz32;
+  ha.dz16 = dz16;
+  ha.loss_rows = loss_rows;
+  ha.probs = out.probs;
+  ha.cum_out = out.cum;
+  ha.mode = mode;
+  ha.want_grad = backward ? 1 : 0;
+  StreamIO hio = io;
+  if (mode == MODE_PLAIN) hio.slot = nullptr;
+  k_head(st, ha, hio, R, s);
+  if (out.loss) {
+    k_colsum(st, d_loss_job, 1, 1, s);
+    hip_check(hipMemcpyAsync(out.loss, loss_out, sizeof(float), hipMemcpyDeviceToDevice, s), "copy");
+  }
+  if (!backward) return;
+
+  // ---- adjoint of the mean cross entropy ---------------------------------
+  {
+    GemmArgs g = ga();
+    g.A = bf16 ? (const void*)dz16 : (const void*)dz32; g.lda = 256; g.B = W_("wh"); g.ldb = F;
+    g.M = R; g.m_rows = 1; g.N = F; g.K = 256;
+    g.out32 = dH32[N]; g.ld_out32 = F;
+    if (bf16) { g.out16 = dH16[N]; g.ld_out16 = F; }
+    gemm(PS_HEAD_BWD, true, false, EPI_STORE, 1, g, R, s);
+  }
+  for (int j = N - 1; j >= 0; --j) {
+    const std::string b = "blk" + std::to_string(j), ln = "ln" + std::to_string(j);
+    GemmArgs g = ga();  // dX_ff = dH Wo, then dX_i through GeLU and the product
+    g.A = bf16 ? (const void*)dH16[j + 1] : (const void*)dH32[j + 1]; g.lda = F;
+    g.B = W_(b + ".wo"); g.ldb = H;
+    g.M = R; g.m_rows = 1; g.N = H; g.K = F;
+    g.aux = Abr[j]; g.ld_aux = K * H; g.aux_branch = H; g.bias_branch_stride = K;
+    g.out32 = dA32[j]; g.ld_out32 = K * H;
+    if (bf16) { g.out16 = dA16[j]; g.ld_out16 = K * H; }
+    gemm(PS_GATE_BWD, true, false, EPI_GATE_BWD, 1, g, R, s);
+    GemmArgs z = ga();  // dX0 = sum_i dX_i W_i
+    z.A = bf16 ? (const void*)dA16[j] : (const void*)dA32[j]; z.lda = K * H;
+    z.B = W_(b + ".w0"); z.ldb = F;
+    z.M = R; z.m_rows = 1; z.N = F; z.K = K * H;
+    z.out32 = dZ[j]; z.ld_out32 = F;
+    gemm(PS_DZ, true, false, EPI_STORE, 1, z, R, s);
+    k_ln_bwd(st, Hs[j], mean[j], rstd[j], P_(ln + ".gamma"), dZ[j], dH32[j + 1], F, dH32[j],
+             bf16 ? dH16[j] : nullptr, R, s);
+  }
+  {  // adjoint of Eq. 16
+    GemmArgs g = ga();
+    g.A = bf16 ? (const void*)dH16[0] : (const void*)dH32[0]; g.lda = F;
+    g.B = W_("w2"); g.ldb = L;
+    g.M = R; g.m_rows = 1; g.N = L; g.K = F;
+    g.out32 = dY; g.ld_out32 = L;
+    gemm(PS_LTE_UP_BWD, true, false, EPI_STORE, 1, g, R, s);
+  }
+  AdamCfg ac{cfg.lr, cfg.beta1, cfg.beta2, cfg.eps};
+  // adjoint of Eq. 15 (+ Adam on U_s)
+  k_fdm_bwd(st, X1, dY, U, mU, vU, out.keep_fdm_grad ? dUkeep : nullptr, slot, L, ac, out.update,
+            dX1_32, dX1_16, R, s);
+  {  // adjoint of Eq. 14 down to the embedding
+    GemmArgs g = ga();
+    g.A = bf16 ? (const void*)dX1_16 : (const void*)dX1_32; g.lda = L;
+    g.B = W_("w1"); g.ldb = F;
+    g.M = R; g.m_rows = 1; g.N = F; g.K = L;
+    g.out32 = dX; g.ld_out32 = F;
+    gemm(PS_LTE_DOWN_BWD, true, false, EPI_STORE, 1, g, R, s);
+  }
+  k_emb_grad(st, ctx, dX, C, E, emb_partial, emb_chunk, R, G_("emb"), s);
+  hip_check(launch_wgrad(kc.tile[PS_WGRAD], bf16, d_wg, n_wg, wg_tiles, st, s), "wgrad launch");
+  k_colsum(st, d_cs, n_cs, cs_blocks, s);
+  if (out.update) k_adam(st, param, grad, m, v, p16, P, ac, s);
+  hip_check(hipGetLastError(), "step launch");
+}
+
+}  // namespace edpc

@@ -1,0 +1,75 @@
+"""Write the oracle's expected payload sizes for the GPU parity tests.
+
+Calls only the CPU oracle (oracle/) on the seeded synthetic inputs (gen/);
+nothing here touches the GPU library.  Output: tests/golden/oracle_sizes.json
+
+    python tests/golden/make_oracle_golden.py [--only NAME]
+
+Cases:
+  small_full      the 8-stream x 8 KiB workload, every byte (8192 steps)
+  small_zero_lr   the same input with lr = 0 (static random model), 2 KiB prefix
+  mid_prefix      the 1024-stream x 64 KiB workload cut to its first 160 bytes
+  mid_bf16_slice  4 streams x 512 bytes of the mid workload
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import gen  # noqa: E402
+import oracle  # noqa: E402
+from oracle.codec import split_streams  # noqa: E402
+from oracle.model import Config  # noqa: E402
+
+CASES = {
+    "small_full": ("small", None, None, {}),
+    "small_zero_lr": ("small", 2048, None, {"lr": 0.0}),
+    "mid_prefix": ("mid_fp32", 160, None, {}),
+    "mid_slice": ("mid_fp32", 512, 4, {}),
+}
+
+
+def run_case(name):
+    wl, prefix, nst, over = CASES[name]
+    w = gen.WORKLOADS[wl]
+    data, lens = gen.make_streams(w, prefix=prefix, n_streams=nst)
+    cfg = Config.from_dict(w.model).with_(**over)
+    t = time.time()
+    pay, info = oracle.encode(split_streams(data, lens), cfg)
+    return {
+        "workload": wl, "prefix": prefix, "n_streams": int(len(lens)), "overrides": over,
+        "lens": [int(x) for x in lens],
+        "payload_bytes": [len(p) for p in pay],
+        "ideal_bits": [float(b) for b in info["ideal_bits"]],
+        "final_loss": float(info["losses"][-1]) if info["losses"] else None,
+        "oracle_seconds": time.time() - t,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--only", default=None)
+    a = ap.parse_args()
+    path = os.path.join(HERE, "oracle_sizes.json")
+    out = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            out = json.load(f)
+    for name in CASES:
+        if a.only and name != a.only:
+            continue
+        out[name] = run_case(name)
+        print(name, sum(out[name]["payload_bytes"]), f"{out[name]['oracle_seconds']:.1f}s", flush=True)
+        with open(path, "w") as f:
+            json.dump(out, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,113 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads and
+exports every declared symbol, the host-compiled coder is byte-identical to
+the oracle's coder, configuration and container errors are reported."""
+
+import os
+import re
+import struct
+import zlib
+
+import numpy as np
+import pytest
+
+import paper_2507_18969_amd as E
+from oracle.quantize import cumulative, quantize
+from oracle.rangecoder import RangeEncoder
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_exports_every_declared_symbol():
+    L = E.lib()
+    with open(os.path.join(ROOT, "include", "edpc.h")) as f:
+        hdr = f.read()
+    declared = set(re.findall(r"\b(edpc_[a-z0-9_]+)\s*\(", hdr))
+    assert declared == set(E.EXPORTS)
+    for name in declared:
+        assert hasattr(L, name), name
+    assert L.edpc_abi_version() == 1
+
+
+def test_host_coder_matches_oracle_coder():
+    r = np.random.default_rng(5)
+    for n in (0, 1, 2, 17, 1500):
+        z = r.standard_normal((max(n, 1), 256)) * r.choice([0.5, 4.0, 15.0])
+        p = np.exp(z - z.max(1, keepdims=True))
+        p /= p.sum(1, keepdims=True)
+        q = quantize(p)
+        cum = cumulative(q)
+        sym = np.array([r.choice(256, p=pp) for pp in p[:n]], dtype=np.uint8)
+        e = RangeEncoder()
+        for t in range(n):
+            e.encode(int(cum[t, sym[t]]), int(q[t, sym[t]]))
+        ref = e.finish()
+        got = E.edpc_rc_encode_host(cum[:max(n, 1)], sym)
+        assert got == ref
+        assert np.array_equal(E.edpc_rc_decode_host(cum, got, n), sym)
+
+
+def test_config_validation():
+    E.edpc_config_validate(E.edpc_config_default())
+    for bad in (dict(embed=12), dict(latent=48), dict(branches=4), dict(cdf_bits=12),
+                dict(hidden=100), dict(context=0), dict(precision=7), dict(beta1=1.0)):
+        with pytest.raises(E.EdpcError) as ei:
+            E.edpc_config_validate(E.edpc_config_default(**bad))
+        assert ei.value.status == -1
+    c = E.edpc_config_default()
+    c.struct_size = 12
+    with pytest.raises(E.EdpcError):
+        E.edpc_config_validate(c)
+
+
+def test_encode_bound():
+    c = E.edpc_config_default()
+    assert E.edpc_encode_bound(c, [10, 0, 5]) == 96 + 20 * 3 + (22 + 2 + 12)
+    with pytest.raises(E.EdpcError):
+        E.edpc_encode_bound(c, [])
+
+
+def _header(lens, pay_lens, crcs, cfg=None, version=1, kernel=1 << 48, arch=950):
+    """Container header written from the documented layout (independent of
+    the library's writer)."""
+    c = cfg or E.edpc_config_default()
+    n = len(lens)
+    b = b"EDPC" + struct.pack("<HHII", version, 0, 96 + 20 * n, n)
+    b += struct.pack("<9I", c.context, c.embed, c.latent, c.blocks, c.hidden, c.branches,
+                     c.cdf_bits, c.precision, c.flags)
+    b += struct.pack("<4f", c.lr, c.beta1, c.beta2, c.eps)
+    b += struct.pack("<QQII", c.seed, kernel, arch, 0)
+    for l, p, k in zip(lens, pay_lens, crcs):
+        b += struct.pack("<QQI", l, p, k)
+    return b + struct.pack("<I", zlib.crc32(b))
+
+
+def test_decode_info_reads_documented_layout():
+    h = _header([100, 0, 7], [80, 0, 9], [1, 2, 3])
+    cfg, lens, hl, total = E.edpc_decode_info(h)
+    assert list(lens) == [100, 0, 7] and hl == len(h) and total == 107
+    assert cfg.context == 16 and cfg.latent == 64
+
+
+@pytest.mark.parametrize("mutate,status", [
+    (lambda h: h[:10], -4),                       # shorter than the fixed header
+    (lambda h: h[:-3], -4),                       # shorter than its header
+    (lambda h: b"EDPX" + h[4:], -4),              # bad magic
+    (lambda h: h[:30] + bytes([h[30] ^ 1]) + h[31:], -5),  # header CRC
+])
+def test_decode_info_errors(mutate, status):
+    h = _header([100, 5], [80, 4], [1, 2])
+    with pytest.raises(E.EdpcError) as ei:
+        E.edpc_decode_info(mutate(h))
+    assert ei.value.status == status
+
+
+def test_decode_info_rejects_version_and_bad_lengths():
+    with pytest.raises(E.EdpcError) as ei:
+        E.edpc_decode_info(_header([10], [8], [0], version=2))
+    assert ei.value.status == -6
+    with pytest.raises(E.EdpcError) as ei:  # payload longer than 2 * len + 2
+        E.edpc_decode_info(_header([10], [23], [0]))
+    assert ei.value.status == -4
+    with pytest.raises(E.EdpcError) as ei:  # non-empty payload for an empty stream
+        E.edpc_decode_info(_header([0], [2], [0]))
+    assert ei.value.status == -4

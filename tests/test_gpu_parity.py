@@ -1,0 +1,295 @@
+"""GPU parity: the HIP path, called through the C ABI, against the oracle.
+
+Tolerances: FP32 path probabilities within 1e-5 absolute, BF16 within 2e-3;
+integer work (coder bytes, CDF sums, round trips) bit-exact; compressed size
+within 0.5 % of the oracle's.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from oracle.codec import split_streams
+from oracle.model import Model as OModel
+from oracle.model import init_fdm, init_shared
+from oracle.quantize import cumulative, quantize
+from oracle.rangecoder import RangeEncoder
+from tests.gpu_util import banner, lib_cfg, load_oracle_state, oracle_cfg, parse_container
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "oracle_sizes.json")
+SMALL = gen.WORKLOADS["small"].model
+MID = gen.WORKLOADS["mid_fp32"].model
+
+
+@pytest.fixture(scope="module")
+def E():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2507_18969_amd as E
+    E.lib()
+    return E
+
+
+@pytest.fixture(autouse=True)
+def _name(request):
+    banner(request.node.nodeid)
+
+
+def _dev(a, dtype=torch.uint8):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+# ---------------------------------------------------------------- coder lanes
+
+def test_range_coder_lanes_bit_exact(E):
+    r = np.random.default_rng(7)
+    n_steps, n_streams = 700, 37
+    z = r.standard_normal((n_steps, n_streams, 256)) * r.choice([0.3, 3.0, 12.0], size=(n_steps, n_streams, 1))
+    p = np.exp(z - z.max(-1, keepdims=True))
+    p /= p.sum(-1, keepdims=True)
+    q = quantize(p.reshape(-1, 256)).reshape(n_steps, n_streams, 256)
+    cum = cumulative(q.reshape(-1, 256)).reshape(n_steps, n_streams, 257)
+    sym = np.array([[r.choice(256, p=p[t, s]) for s in range(n_streams)] for t in range(n_steps)],
+                   dtype=np.uint8)
+    expect = []
+    for s in range(n_streams):
+        e = RangeEncoder()
+        for t in range(n_steps):
+            x = int(sym[t, s])
+            e.encode(int(cum[t, s, x]), int(q[t, s, x]))
+        expect.append(e.finish())
+    d_cum = _dev(cum.astype(np.uint32), torch.int32)
+    d_sym = _dev(sym)
+    out, lens = E.edpc_rc_encode(d_cum, d_sym, 2 * n_steps + 2)
+    got = out.cpu().numpy()
+    for s in range(n_streams):
+        assert got[s, : lens[s]].tobytes() == expect[s]
+    back = E.edpc_rc_decode(d_cum, out, lens).cpu().numpy()
+    assert np.array_equal(back, sym)
+
+
+# ---------------------------------------------------------------- model step
+
+def test_initial_parameters_bit_identical(E):
+    cfg = lib_cfg(E, SMALL)
+    m = E.Model(cfg, 8, 8)
+    ref = init_shared(oracle_cfg(SMALL))
+    for k, v in ref.items():
+        assert np.array_equal(m.edpc_model_read(k), v.reshape(-1)), k
+    assert np.array_equal(m.edpc_model_read("U"), init_fdm(oracle_cfg(SMALL), range(8)).reshape(-1))
+
+
+def _step_case(E, model, precision, rows, pos, om_steps=0, n_slots=None, prefix=None, wl="small"):
+    data, lens = gen.make_streams(wl, prefix=prefix or (pos + 1), n_streams=rows)
+    st = np.frombuffer(data.tobytes(), dtype=np.uint8).reshape(rows, -1)
+    C = model["context"]
+    ocfg = oracle_cfg(model)
+    om = OModel(ocfg, n_slots or rows)
+    # advance the oracle on this input, then start both sides from its state
+    for i in range(C, C + om_steps):
+        om.step(st[:, i - C:i].astype(np.int64), st[:, i].astype(np.int64), np.arange(rows))
+    om.round_to_f32()
+    cfg = lib_cfg(E, model, precision)
+    m = E.Model(cfg, n_slots or rows, rows)
+    if om_steps:
+        load_oracle_state(m, om)
+    ctx = st[:, pos - C:pos]
+    tgt = st[:, pos]
+    return om, m, ctx, tgt
+
+
+def _compare_step(E, om, m, ctx, tgt, p_tol, g_rtol):
+    rows = ctx.shape[0]
+    slots = np.arange(rows)
+    c = om.forward(ctx.astype(np.int64), slots)
+    loss_o = OModel.loss(c, tgt.astype(np.int64))
+    g_o, dU_o = om.backward(c, tgt.astype(np.int64))
+    d_ctx, d_tgt = _dev(ctx), _dev(tgt)
+    probs = torch.empty((rows, 256), dtype=torch.float32, device="cuda")
+    cum = torch.empty((rows, 257), dtype=torch.int32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    m.edpc_model_step(d_ctx, d_tgt, slots, probs, cum, loss,
+                      flags=E.EDPC_STEP_BACKWARD | E.EDPC_STEP_KEEP_FDM_GRAD)
+    torch.cuda.synchronize()
+    p_g = probs.cpu().numpy()
+    assert np.abs(p_g - c["p"]).max() <= p_tol
+    assert abs(loss.item() - loss_o) <= 1e-5 * max(1.0, abs(loss_o)) + p_tol
+    cg = cum.cpu().numpy().astype(np.int64)
+    assert np.all(cg[:, 0] == 0) and np.all(cg[:, 256] == 65536)
+    qg = np.diff(cg, axis=1)
+    assert qg.min() >= 1
+    # the GPU's CDF is the quantisation of its own FP32 probabilities
+    fl = 1 + np.floor(p_g.astype(np.float32) * np.float32(65280.0)).astype(np.int64)
+    am = np.argmax(qg, axis=1)
+    mask = np.ones_like(qg, dtype=bool)
+    mask[np.arange(rows), am] = False
+    assert np.array_equal(qg[mask], fl[mask])
+    # and within one count of the oracle's away from the remainder bin
+    qo = quantize(c["p"])
+    assert np.abs(qg - qo)[mask].max() <= 1
+    for k in om.p:
+        gg = m.edpc_model_read(k, kind=E.EDPC_KIND_GRAD)
+        go = g_o[k].reshape(-1)
+        scale = np.abs(go).max() + 1e-30
+        err = np.abs(gg - go).max() / scale
+        assert err <= g_rtol, (k, err)
+    dU = m.edpc_model_read("U", kind=E.EDPC_KIND_GRAD).reshape(om.U.shape)
+    for r in range(rows):
+        scale = np.abs(dU_o[r]).max() + 1e-30
+        assert np.abs(dU[r] - dU_o[r]).max() / scale <= g_rtol
+    return c, g_o, dU_o
+
+
+def _compare_update(E, om, m, ctx, tgt, g_o, dU_o, tol):
+    rows = ctx.shape[0]
+    slots = np.arange(rows)
+    d_ctx, d_tgt = _dev(ctx), _dev(tgt)
+    m.edpc_model_step(d_ctx, d_tgt, slots, flags=E.EDPC_STEP_UPDATE)
+    torch.cuda.synchronize()
+    before = {k: v.copy() for k, v in om.p.items()}
+    om.adam(g_o, dU_o, slots)
+    for k in om.p:
+        new_g = m.edpc_model_read(k)
+        new_o = om.p[k].reshape(-1)
+        # elements whose gradient stands clear of rounding noise must move
+        # exactly like the oracle's; near-zero gradients may differ in sign
+        g = np.abs(g_o[k].reshape(-1))
+        clear = g > 1e-3 * (g.max() + 1e-30)
+        d = np.abs(new_g - new_o)[clear]
+        assert d.size == 0 or d.max() <= tol, (k, d.max())
+        assert np.abs(new_g - before[k].reshape(-1)).max() <= 2.01 * om.cfg.lr
+    assert m.edpc_model_get_step() == om.tau
+
+
+@pytest.mark.parametrize("om_steps", [0, 24])
+def test_one_step_fp32_small(E, om_steps):
+    om, m, ctx, tgt = _step_case(E, SMALL, "fp32", rows=8, pos=16 + om_steps, om_steps=om_steps,
+                                 prefix=16 + om_steps + 1)
+    _, g_o, dU_o = _compare_step(E, om, m, ctx, tgt, p_tol=1e-5, g_rtol=1e-4)
+    _compare_update(E, om, m, ctx, tgt, g_o, dU_o, tol=1e-6)
+
+
+def test_one_step_fp32_ragged_rows_and_slots(E):
+    # 5 rows mapped to scattered slots of a 13-slot model: tails of every tile
+    data, lens = gen.make_streams("small", prefix=40, n_streams=8)
+    st = np.frombuffer(data.tobytes(), dtype=np.uint8).reshape(8, -1)
+    ocfg = oracle_cfg(SMALL)
+    om = OModel(ocfg, 13)
+    cfg = lib_cfg(E, SMALL)
+    m = E.Model(cfg, 13, 5)
+    slots = np.array([12, 3, 7, 0, 9])
+    ctx = st[:5, 20:36]
+    tgt = st[:5, 36]
+    c = om.forward(ctx.astype(np.int64), slots)
+    probs = torch.empty((5, 256), dtype=torch.float32, device="cuda")
+    m.edpc_model_step(_dev(ctx), _dev(tgt), slots, probs, flags=E.EDPC_STEP_BACKWARD)
+    torch.cuda.synchronize()
+    assert np.abs(probs.cpu().numpy() - c["p"]).max() <= 1e-5
+
+
+def test_one_step_bf16_small(E):
+    om, m, ctx, tgt = _step_case(E, SMALL, "bf16", rows=8, pos=16, prefix=17)
+    _compare_step(E, om, m, ctx, tgt, p_tol=2e-3, g_rtol=3e-2)
+
+
+def test_mid_first_step_sampled_rows_full_batch(E):
+    # full 1024-stream batch in the encoder's launch configuration; the
+    # oracle checks sampled rows one by one (at the first model step a row's
+    # probabilities depend only on its own context and U_s)
+    rows = 1024
+    C = MID["context"]
+    data, lens = gen.make_streams("mid_fp32", prefix=C + 1)
+    st = np.frombuffer(data.tobytes(), dtype=np.uint8).reshape(rows, -1)
+    cfg = lib_cfg(E, MID)
+    m = E.Model(cfg, rows, rows)
+    probs = torch.empty((rows, 256), dtype=torch.float32, device="cuda")
+    m.edpc_model_step(_dev(st[:, :C]), _dev(st[:, C]), np.arange(rows), probs)
+    torch.cuda.synchronize()
+    pg = probs.cpu().numpy()
+    ocfg = oracle_cfg(MID)
+    sample = np.random.default_rng(3).choice(rows, size=12, replace=False)
+    shared = init_shared(ocfg)
+    for s in sample:
+        om = OModel(ocfg, 1, shared=shared, fdm=init_fdm(ocfg, [s]))
+        c = om.forward(st[s:s + 1, :C].astype(np.int64), np.array([0]))
+        assert np.abs(pg[s] - c["p"][0]).max() <= 1e-5
+
+
+# ---------------------------------------------------------------- codec
+
+def _encode(E, cfg, data, lens):
+    d = _dev(data)
+    cont = E.edpc_encode(cfg, d, lens)
+    torch.cuda.synchronize()
+    return cont
+
+
+def test_identity_case_payload_is_the_stream(E):
+    data, lens = gen.make_streams("small", prefix=300, n_streams=5)
+    cfg = lib_cfg(E, SMALL, lr=0.0, zero_head=True)
+    cont = _encode(E, cfg, data, lens).cpu().numpy().tobytes()
+    _, pays = parse_container(cont)
+    for s, p in zip(split_streams(data, lens), pays):
+        assert p == s + b"\x00"
+
+
+def test_roundtrip_ragged_empty_short(E):
+    data, lens = gen.make_streams("small", prefix=160, n_streams=8)
+    st = split_streams(data, lens)
+    cuts = [160, 0, 5, 16, 17, 100, 1, 159]
+    st = [s[:c] for s, c in zip(st, cuts)]
+    flat = np.frombuffer(b"".join(st), dtype=np.uint8)
+    cfg = lib_cfg(E, SMALL)
+    cont = _encode(E, cfg, flat, cuts)
+    out, lens_back = E.edpc_decode(cont)
+    assert list(lens_back) == cuts
+    assert out.cpu().numpy().tobytes() == b"".join(st)
+    _, pays = parse_container(cont.cpu().numpy().tobytes())
+    pay_o, _ = oracle.encode(st, oracle_cfg(SMALL))
+    for s, p, po in zip(st, pays, pay_o):
+        k = min(len(s), SMALL["context"])
+        assert p[:k] == s[:k]
+        assert len(p) == 0 if len(s) == 0 else abs(len(p) - len(po)) <= 2
+
+
+def test_small_full_roundtrip_determinism_and_size(E):
+    data, lens = gen.make_streams("small")
+    cfg = lib_cfg(E, SMALL)
+    cont1 = _encode(E, cfg, data, lens)
+    cont2 = _encode(E, cfg, data, lens)
+    assert torch.equal(cont1, cont2)
+    out, _ = E.edpc_decode(cont1)
+    assert out.cpu().numpy().tobytes() == data.tobytes()
+    _, pays = parse_container(cont1.cpu().numpy().tobytes())
+    with open(GOLDEN) as f:
+        gold = json.load(f)["small_full"]
+    g = sum(map(len, pays))
+    o = sum(gold["payload_bytes"])
+    assert abs(g - o) / o <= 0.005, (g, o)
+
+
+def test_decoder_rejects_corruption(E):
+    data, lens = gen.make_streams("small", prefix=200, n_streams=3)
+    cfg = lib_cfg(E, SMALL)
+    cont = _encode(E, cfg, data, lens)
+    bad = cont.clone()
+    hl = 96 + 20 * 3
+    bad[hl + 5] ^= 0x5A  # inside stream 0's verbatim prefix
+    with pytest.raises(E.EdpcError) as ei:
+        E.edpc_decode(bad)
+    assert ei.value.status == -5
+    hdr = cont.clone()
+    hdr[20] ^= 1
+    with pytest.raises(E.EdpcError) as ei:
+        E.edpc_decode(hdr)
+    assert ei.value.status == -5
+    with pytest.raises(E.EdpcError) as ei:
+        E.edpc_decode(cont[:-10])
+    assert ei.value.status == -4
