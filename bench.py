@@ -1,0 +1,214 @@
+"""Throughput of the online-adaptive byte-model codec on one MI355X.
+
+A step is one pass of the whole hot path over one batch: for every one of
+the 1024 streams, gather the context window, embed, LTE, refinement blocks,
+softmax, integer CDF, range-code the byte, then the adjoint and the Adam
+update (shared weights and each stream's FDM slice).  One step codes one
+byte per stream.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--full]
+
+Workload: 64 MiB of order-2 Markov Zipf(1.2) bytes in 1024 streams of 64
+KiB; model context 32, embed 16, latent 128, 4 blocks of hidden 256.  The
+input is resident in HBM before timing; each timed region covers K
+consecutive steps of an encoder (and a decoder) session after W warm-up
+steps, bracketed by device synchronisation and HIP events on the library's
+stream.  Steady-state steps all cost the same, so K steps' rate is the rate
+of the whole 65,536-step job (the first 32 bytes of each stream are coded
+uniformly and are not timed).  --full also times a complete encode and
+decode of the whole 64 MiB.
+
+Prints one JSON line.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("encode/decode MB/s on 1 MI355X (BF16 vs FP32 path) at compressed bits/byte "
+          "within 0.5% of oracle")
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def lib_cfg(E, model, precision):
+    keys = ("context", "embed", "latent", "blocks", "hidden", "branches", "lr", "beta1",
+            "beta2", "eps", "seed")
+    return E.edpc_config_default(precision=precision, **{k: model[k] for k in keys})
+
+
+def time_session(torch, sess, warmup, steps):
+    sess.edpc_session_run(warmup)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    a.record()
+    done = sess.edpc_session_run(steps)
+    b.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return done, a.elapsed_time(b), wall
+
+
+def run_precision(torch, E, w, d_in, lens, data, precision, warmup, steps):
+    cfg = lib_cfg(E, w.model, precision)
+    rows = len(lens)
+    log(f"{precision}: encoder session")
+    enc = E.edpc_encoder_begin(cfg, d_in, lens)
+    done, ms, wall = time_session(torch, enc, warmup, steps)
+    kern = enc.edpc_session_time_kernels(16)
+    enc.edpc_session_destroy()
+    enc_mbps = done * rows / (ms * 1e-3) / 1e6
+    log(f"{precision}: encode {enc_mbps:.3f} MB/s ({ms / done:.3f} ms/step)")
+
+    # decoder: a container of the streams cut after the steps it will run
+    C = w.model["context"]
+    cut = C + warmup + steps + 16
+    sub = np.ascontiguousarray(data.reshape(rows, -1)[:, :cut]).reshape(-1)
+    d_sub = torch.as_tensor(sub).to("cuda")
+    cont = E.edpc_encode(cfg, d_sub, np.full(rows, cut))
+    out = torch.empty(rows * cut, dtype=torch.uint8, device="cuda")
+    log(f"{precision}: decoder session")
+    dec = E.edpc_decoder_begin(cont, out)
+    ddone, dms, _ = time_session(torch, dec, warmup, steps)
+    dec.edpc_decoder_finish()
+    dec.edpc_session_destroy()
+    torch.cuda.synchronize()
+    assert torch.equal(out, d_sub), "decoder output differs from the input"
+    dec_mbps = ddone * rows / (dms * 1e-3) / 1e6
+    log(f"{precision}: decode {dec_mbps:.3f} MB/s ({dms / ddone:.3f} ms/step)")
+    return dict(encode=enc_mbps, decode=dec_mbps, ms_per_step=ms / done, wall_s=wall,
+                kernels=kern, steps=done)
+
+
+def full_job(torch, E, w, d_in, lens, precision):
+    cfg = lib_cfg(E, w.model, precision)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cont = E.edpc_encode(cfg, d_in, lens)
+    torch.cuda.synchronize()
+    te = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    out, _ = E.edpc_decode(cont)
+    torch.cuda.synchronize()
+    td = time.perf_counter() - t0
+    ok = bool(torch.equal(out, d_in))
+    n = int(d_in.numel())
+    hdr = 96 + 20 * len(lens)
+    return dict(encode_MBps=n / te / 1e6, decode_MBps=n / td / 1e6, roundtrip=ok,
+                bits_per_byte=8.0 * (cont.numel() - hdr) / n)
+
+
+def fdm_roofline(w, kern, rows):
+    """FDM adjoint + Adam kernel: U, m, v read and written per step (24 B per
+    element of the active streams' L x L slices) plus the x', dy rows read and
+    dx' written."""
+    L = w.model["latent"]
+    ms, launches = kern["fdm_bwd_adam"]
+    per_launch_s = ms / launches * 1e-3
+    algo = rows * L * L * 24 + rows * L * 4 * 3
+    gbs = algo / per_launch_s / 1e9
+    return {"kernel": "fdm_bwd_adam", "bound": "hbm", "achieved": round(gbs, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "traffic": None, "algorithmic_bytes_per_launch": algo,
+            "avg_launch_us": round(per_launch_s * 1e6, 2)}
+
+
+def cpu_baseline(w, data, lens, n_model_steps):
+    """The CPU oracle on a bounded sample of the same workload: all 1024
+    streams, the uniform prefix plus n_model_steps model steps."""
+    import oracle
+    from oracle.codec import _run
+    from oracle.model import Config
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    C = w.model["context"]
+    cut = C + n_model_steps
+    rows = len(lens)
+    sub = data.reshape(rows, -1)[:, :cut]
+    streams = [sub[s].tobytes() for s in range(rows)]
+    cfg = Config.from_dict(w.model)
+    t0 = time.perf_counter()
+    _run(cfg, [cut] * rows, streams=streams)
+    dt = time.perf_counter() - t0
+    del oracle
+    return {"value": round(rows * cut / dt / 1e6, 6), "unit": "MB/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"{rows} streams x {cut} bytes ({C} uniform + {n_model_steps} model steps), "
+                      f"FP64 numpy, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--full", action="store_true", help="also time a whole encode + decode")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-steps", type=int, default=16)
+    ap.add_argument("--precisions", default="bf16,fp32")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import gen
+    import paper_2507_18969_amd as E
+    E.lib()
+    w = gen.WORKLOADS["mid_bf16"]
+    log("generating 64 MiB input")
+    data, lens = gen.make_streams(w)
+    d_in = torch.as_tensor(data).to("cuda")
+    torch.cuda.synchronize()
+    rows = len(lens)
+    res = {}
+    for prec in a.precisions.split(","):
+        res[prec] = run_precision(torch, E, w, d_in, lens, data, prec, a.warmup, a.steps)
+    main_p = "bf16" if "bf16" in res else list(res)[0]
+    r = res[main_p]
+    kern = {k: [round(v[0] / 16, 4), v[1] // 16] for k, v in r["kernels"].items() if v[1]}
+    line = {
+        "metric": METRIC, "value": round(r["encode"], 4), "unit": "MB/s", "n_gpus": 1,
+        "steps": int(r["steps"]), "warmup": a.warmup, "ms_per_step": round(r["ms_per_step"], 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": main_p,
+        "data": "synthetic",
+        "config": {"workload": "64 MiB order-2 Markov Zipf(1.2), 1024 streams x 64 KiB; "
+                               "context 32, embed 16, latent 128, 4 blocks x hidden 256",
+                   "streams": rows, "stream_bytes": int(lens[0]), "bytes_per_step": rows,
+                   "precision": main_p},
+        "encode_MBps": {p: round(v["encode"], 4) for p, v in res.items()},
+        "decode_MBps": {p: round(v["decode"], 4) for p, v in res.items()},
+        "ms_per_step_by_precision": {p: round(v["ms_per_step"], 4) for p, v in res.items()},
+        "kernels_ms_per_step": kern,
+        "roofline": fdm_roofline(w, r["kernels"], rows),
+    }
+    if "bf16" in res and "fp32" in res:
+        line["bf16_over_fp32_encode"] = round(res["bf16"]["encode"] / res["fp32"]["encode"], 3)
+    if a.full:
+        line["full_job"] = {p: full_job(torch, E, w, d_in, lens, p) for p in res}
+    if not a.no_cpu:
+        log("CPU oracle baseline")
+        line["cpu_baseline"] = cpu_baseline(w, data, lens, a.cpu_steps)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -145,6 +145,16 @@ edpc_status edpc_encoder_finish(edpc_session* s, uint8_t* d_out, size_t out_cap,
 edpc_status edpc_decoder_finish(edpc_session* s, size_t* out_len);
 void edpc_session_destroy(edpc_session* s);
 
+/* Kernel-level timing (profiling aid).  Runs the next n_steps of the session
+ * with a HIP event recorded before and after every kernel launch on the
+ * session's stream, then synchronises: h_ms[c] receives the summed kernel
+ * milliseconds and h_launches[c] the launch count of kernel class c, for
+ * c < EDPC_KCLASS_COUNT.  The class names come from edpc_kclass_name. */
+#define EDPC_KCLASS_COUNT 22
+edpc_status edpc_session_time_kernels(edpc_session* s, uint64_t n_steps, float* h_ms,
+                                      uint32_t* h_launches);
+const char* edpc_kclass_name(int c);
+
 /* ------------------------------------------------------------------------
  * Model-level access: one step of the network on explicit contexts.
  * ---------------------------------------------------------------------- */

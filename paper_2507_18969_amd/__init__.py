@@ -25,6 +25,7 @@ EDPC_FP32, EDPC_BF16 = 0, 1
 EDPC_CFG_ZERO_HEAD = 0x1
 EDPC_STEP_BACKWARD, EDPC_STEP_UPDATE, EDPC_STEP_KEEP_FDM_GRAD = 0x1, 0x2, 0x4
 EDPC_KIND_PARAM, EDPC_KIND_GRAD, EDPC_KIND_ADAM_M, EDPC_KIND_ADAM_V = 0, 1, 2, 3
+KCLASS_COUNT = 22
 
 #: every symbol include/edpc.h declares
 EXPORTS = [
@@ -32,7 +33,7 @@ EXPORTS = [
     "edpc_config_validate", "edpc_encode_bound", "edpc_encode", "edpc_decode_info",
     "edpc_decode", "edpc_encoder_begin", "edpc_decoder_begin", "edpc_session_run",
     "edpc_session_progress", "edpc_encoder_finish", "edpc_decoder_finish",
-    "edpc_session_destroy", "edpc_model_create", "edpc_model_destroy", "edpc_model_step",
+    "edpc_session_destroy", "edpc_session_time_kernels", "edpc_kclass_name", "edpc_model_create", "edpc_model_destroy", "edpc_model_step",
     "edpc_model_tensor_count", "edpc_model_tensor_info", "edpc_model_read", "edpc_model_write",
     "edpc_model_get_step", "edpc_model_set_step", "edpc_rc_encode", "edpc_rc_decode",
     "edpc_rc_encode_host", "edpc_rc_decode_host",
@@ -92,6 +93,8 @@ def lib() -> ctypes.CDLL:
         "edpc_encoder_finish": (ctypes.c_int, [_P, _P, _SZ, _SZP]),
         "edpc_decoder_finish": (ctypes.c_int, [_P, _SZP]),
         "edpc_session_destroy": (None, [_P]),
+        "edpc_session_time_kernels": (ctypes.c_int, [_P, ctypes.c_uint64, _P, _P]),
+        "edpc_kclass_name": (ctypes.c_char_p, [ctypes.c_int]),
         "edpc_model_create": (ctypes.c_int, [cfgp, _SZ, _SZ, ctypes.POINTER(_P)]),
         "edpc_model_destroy": (None, [_P]),
         "edpc_model_step": (ctypes.c_int, [_P, _P, _P, _U32P, _SZ, _P, _P, _P, ctypes.c_uint32, _P]),
@@ -236,6 +239,14 @@ class Session:
         n = ctypes.c_size_t()
         _check(lib().edpc_decoder_finish(self.h, ctypes.byref(n)))
         return n.value
+
+    def edpc_session_time_kernels(self, n_steps: int) -> dict:
+        """{class name: (total ms, launches)} over the next n_steps."""
+        ms = np.zeros(KCLASS_COUNT, dtype=np.float32)
+        la = np.zeros(KCLASS_COUNT, dtype=np.uint32)
+        _check(lib().edpc_session_time_kernels(self.h, n_steps, _np_ptr(ms), _np_ptr(la)))
+        return {lib().edpc_kclass_name(c).decode(): (float(ms[c]), int(la[c]))
+                for c in range(KCLASS_COUNT)}
 
     def edpc_session_destroy(self):
         if self.h:

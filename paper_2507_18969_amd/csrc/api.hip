@@ -167,6 +167,27 @@ edpc_status edpc_decoder_finish(edpc_session* s, size_t* out_len) {
 
 void edpc_session_destroy(edpc_session* s) { delete s; }
 
+edpc_status edpc_session_time_kernels(edpc_session* s, uint64_t n_steps, float* h_ms,
+                                      uint32_t* h_launches) {
+  return guarded([&] {
+    if (!s || !s->s || !h_ms || !h_launches) fail(EDPC_E_INVALID_ARG, "NULL argument");
+    KTimer timer;
+    Model& m = *s->s->model;
+    m.timer = &timer;
+    try {
+      s->s->run(n_steps);
+      timer.collect(h_ms, h_launches);
+    } catch (...) {
+      m.timer = nullptr;
+      throw;
+    }
+    m.timer = nullptr;
+    return EDPC_OK;
+  });
+}
+
+const char* edpc_kclass_name(int c) { return kclass_name(c); }
+
 edpc_status edpc_encode(const edpc_config* cfg, const uint8_t* d_in, const uint64_t* h_lens,
                         size_t n, uint8_t* d_out, size_t out_cap, size_t* out_len, void* stream) {
   edpc_session* s = nullptr;

@@ -143,8 +143,12 @@ void Session::run(uint64_t k) {
   out.update = true;
   for (uint64_t i = next; i < end; ++i) {
     const int rows = rows_at(i);
+    KTimer* timer = model->timer;
+    if (timer) timer->begin(KC_SCHEDULE, s);
     k_step_schedule(model->st, sched, (int)i, s);
+    if (timer) { timer->end(s); timer->begin(KC_GATHER, s); }
     k_gather(model->st, io, model->C, model->ctx, model->tgt, rows, decoding, s);
+    if (timer) timer->end(s);
     model->step(decoding ? MODE_DECODE : MODE_ENCODE, io, out, rows, s);
   }
   next = end;

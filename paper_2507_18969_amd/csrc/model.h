@@ -51,6 +51,38 @@ struct TensorInfo {
   float bound;   // RNG bound or constant value
 };
 
+// Kernel classes for per-kernel timing: the product slots, then the rest.
+enum KClass : int {
+  KC_SCHEDULE = PS_COUNT,
+  KC_GATHER,
+  KC_EMBED,
+  KC_FDM_FWD,
+  KC_LN_FWD,
+  KC_HEAD,
+  KC_LN_BWD,
+  KC_FDM_BWD,
+  KC_EMB_GRAD,
+  KC_COLSUM,
+  KC_ADAM,
+  KC_COUNT
+};
+static_assert(KC_COUNT == EDPC_KCLASS_COUNT, "kernel class count");
+const char* kclass_name(int c);
+
+// HIP events around every launch (profiling aid; off unless installed).
+struct KTimer {
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  struct Span { int cls; hipEvent_t a, b; };
+  std::vector<Span> spans;
+  int cur = -1;
+  hipEvent_t cur_ev = nullptr;
+  void begin(int cls, hipStream_t s);
+  void end(hipStream_t s);
+  void collect(float* ms, uint32_t* launches);
+  ~KTimer();
+};
+
 enum StepMode : int { MODE_PLAIN = 0, MODE_ENCODE = 1, MODE_DECODE = 2 };
 
 struct StepOutputs {
@@ -101,6 +133,7 @@ struct Model {
   int n_cs = 0, cs_blocks = 0;
   ColsumJob* d_loss_job = nullptr;
   int emb_chunk = 16;
+  KTimer* timer = nullptr;
   std::vector<void*> allocs;
 
   Model(const edpc_config& c, size_t n_slots, size_t max_rows, const KernelConfig* kc);

@@ -33,6 +33,60 @@ bool KernelConfig::decode(uint64_t id, KernelConfig* out) {
   return true;
 }
 
+const char* kclass_name(int c) {
+  static const char* names[KC_COUNT] = {
+      "gemm_lte_down", "gemm_lte_up", "gemm_branches_gelu", "gemm_block_out", "gemm_head",
+      "gemm_head_bwd", "gemm_gelu_bwd", "gemm_branches_bwd", "gemm_lte_up_bwd",
+      "gemm_lte_down_bwd", "gemm_weight_grads", "step_schedule", "gather", "embed", "fdm_fwd",
+      "layernorm_fwd", "head_softmax_cdf_coder", "layernorm_bwd", "fdm_bwd_adam", "emb_grad",
+      "colsum_bias_grads", "adam_shared"};
+  return (c >= 0 && c < KC_COUNT) ? names[c] : "unknown";
+}
+
+void KTimer::begin(int cls, hipStream_t s) {
+  if (used == pool.size()) {
+    hipEvent_t e;
+    hip_check(hipEventCreate(&e), "hipEventCreate");
+    pool.push_back(e);
+  }
+  cur = cls;
+  cur_ev = pool[used++];
+  hip_check(hipEventRecord(cur_ev, s), "hipEventRecord");
+}
+
+void KTimer::end(hipStream_t s) {
+  if (used == pool.size()) {
+    hipEvent_t e;
+    hip_check(hipEventCreate(&e), "hipEventCreate");
+    pool.push_back(e);
+  }
+  hipEvent_t b = pool[used++];
+  hip_check(hipEventRecord(b, s), "hipEventRecord");
+  spans.push_back(Span{cur, cur_ev, b});
+}
+
+void KTimer::collect(float* ms, uint32_t* launches) {
+  for (int c = 0; c < KC_COUNT; ++c) { ms[c] = 0.f; launches[c] = 0; }
+  for (auto& sp : spans) {
+    hip_check(hipEventSynchronize(sp.b), "hipEventSynchronize");
+    float t = 0.f;
+    hip_check(hipEventElapsedTime(&t, sp.a, sp.b), "hipEventElapsedTime");
+    ms[sp.cls] += t;
+    launches[sp.cls] += 1;
+  }
+}
+
+KTimer::~KTimer() {
+  for (auto e : pool) (void)hipEventDestroy(e);
+}
+
+#define TIMED(cls, call)                  \
+  do {                                    \
+    if (timer) timer->begin((cls), s);    \
+    call;                                 \
+    if (timer) timer->end(s);             \
+  } while (0)
+
 static bool pow2(uint32_t x) { return x && !(x & (x - 1)); }
 
 void Model::validate(const edpc_config& c) {
@@ -289,7 +343,7 @@ void Model::build_tables(hipStream_t s) {
 void Model::gemm(int ps, bool ak, bool bk, EpiKind epi, int nb, GemmArgs g, int grid_rows,
                  hipStream_t s) {
   g.st = st;
-  hip_check(launch_gemm(kc.tile[ps], bf16, ak, bk, epi, nb, g, grid_rows, s), "gemm launch");
+  TIMED(ps, hip_check(launch_gemm(kc.tile[ps], bf16, ak, bk, epi, nb, g, grid_rows, s), "gemm launch"));
 }
 
 static GemmArgs ga() {
@@ -303,7 +357,7 @@ void Model::step(StepMode mode, const StreamIO& io, const StepOutputs& out, int 
   const int R = grid_rows;
   const void* X_op = bf16 ? (const void*)X16 : (const void*)X32;
   // ---- forward -----------------------------------------------------------
-  k_embed(st, ctx, P_("emb"), C, E, X32, X16, R, s);
+  TIMED(KC_EMBED, k_embed(st, ctx, P_("emb"), C, E, X32, X16, R, s));
   {  // LTE down-projection (Eq. 14)
     GemmArgs g = ga();
     g.A = X_op; g.lda = F; g.B = W_("w1"); g.ldb = F;
@@ -311,7 +365,7 @@ void Model::step(StepMode mode, const StreamIO& io, const StepOutputs& out, int 
     g.bias = P_("b1"); g.out32 = X1; g.ld_out32 = L;
     gemm(PS_LTE_DOWN, true, true, EPI_STORE, 1, g, R, s);
   }
-  k_fdm_fwd(st, X1, U, slot, L, Y32, Y16, R, s);  // Eq. 15
+  TIMED(KC_FDM_FWD, k_fdm_fwd(st, X1, U, slot, L, Y32, Y16, R, s));  // Eq. 15
   {  // LTE up-projection (Eq. 16)
     GemmArgs g = ga();
     g.A = bf16 ? (const void*)Y16 : (const void*)Y32; g.lda = L; g.B = W_("w2"); g.ldb = L;
@@ -322,8 +376,9 @@ void Model::step(StepMode mode, const StreamIO& io, const StepOutputs& out, int 
   }
   for (int j = 0; j < N; ++j) {  // refinement blocks (Eqs. 9-13)
     const std::string b = "blk" + std::to_string(j), ln = "ln" + std::to_string(j);
-    k_ln_fwd(st, Hs[j], P_(ln + ".gamma"), P_(ln + ".beta"), F, bf16 ? nullptr : Z32[j],
-             bf16 ? Z16[j] : nullptr, mean[j], rstd[j], R, s);
+    TIMED(KC_LN_FWD, k_ln_fwd(st, Hs[j], P_(ln + ".gamma"), P_(ln + ".beta"), F,
+                              bf16 ? nullptr : Z32[j], bf16 ? Z16[j] : nullptr, mean[j],
+                              rstd[j], R, s));
     GemmArgs g = ga();
     g.A = bf16 ? (const void*)Z16[j] : (const void*)Z32[j]; g.lda = F;
     g.B = W_(b + ".w0"); g.ldb = F; g.b_branch_stride = (long long)H * F;
@@ -364,9 +419,9 @@ void Model::step(StepMode mode, const StreamIO& io, const StepOutputs& out, int 
   ha.want_grad = backward ? 1 : 0;
   StreamIO hio = io;
   if (mode == MODE_PLAIN) hio.slot = nullptr;
-  k_head(st, ha, hio, R, s);
+  TIMED(KC_HEAD, k_head(st, ha, hio, R, s));
   if (out.loss) {
-    k_colsum(st, d_loss_job, 1, 1, s);
+    TIMED(KC_COLSUM, k_colsum(st, d_loss_job, 1, 1, s));
     hip_check(hipMemcpyAsync(out.loss, loss_out, sizeof(float), hipMemcpyDeviceToDevice, s), "copy");
   }
   if (!backward) return;
@@ -396,8 +451,8 @@ void Model::step(StepMode mode, const StreamIO& io, const StepOutputs& out, int 
     z.M = R; z.m_rows = 1; z.N = F; z.K = K * H;
     z.out32 = dZ[j]; z.ld_out32 = F;
     gemm(PS_DZ, true, false, EPI_STORE, 1, z, R, s);
-    k_ln_bwd(st, Hs[j], mean[j], rstd[j], P_(ln + ".gamma"), dZ[j], dH32[j + 1], F, dH32[j],
-             bf16 ? dH16[j] : nullptr, R, s);
+    TIMED(KC_LN_BWD, k_ln_bwd(st, Hs[j], mean[j], rstd[j], P_(ln + ".gamma"), dZ[j],
+                              dH32[j + 1], F, dH32[j], bf16 ? dH16[j] : nullptr, R, s));
   }
   {  // adjoint of Eq. 16
     GemmArgs g = ga();
@@ -409,8 +464,8 @@ void Model::step(StepMode mode, const StreamIO& io, const StepOutputs& out, int 
   }
   AdamCfg ac{cfg.lr, cfg.beta1, cfg.beta2, cfg.eps};
   // adjoint of Eq. 15 (+ Adam on U_s)
-  k_fdm_bwd(st, X1, dY, U, mU, vU, out.keep_fdm_grad ? dUkeep : nullptr, slot, L, ac, out.update,
-            dX1_32, dX1_16, R, s);
+  TIMED(KC_FDM_BWD, k_fdm_bwd(st, X1, dY, U, mU, vU, out.keep_fdm_grad ? dUkeep : nullptr, slot,
+                              L, ac, out.update, dX1_32, dX1_16, R, s));
   {  // adjoint of Eq. 14 down to the embedding
     GemmArgs g = ga();
     g.A = bf16 ? (const void*)dX1_16 : (const void*)dX1_32; g.lda = L;
@@ -419,10 +474,11 @@ void Model::step(StepMode mode, const StreamIO& io, const StepOutputs& out, int 
     g.out32 = dX; g.ld_out32 = F;
     gemm(PS_LTE_DOWN_BWD, true, false, EPI_STORE, 1, g, R, s);
   }
-  k_emb_grad(st, ctx, dX, C, E, emb_partial, emb_chunk, R, G_("emb"), s);
-  hip_check(launch_wgrad(kc.tile[PS_WGRAD], bf16, d_wg, n_wg, wg_tiles, st, s), "wgrad launch");
-  k_colsum(st, d_cs, n_cs, cs_blocks, s);
-  if (out.update) k_adam(st, param, grad, m, v, p16, P, ac, s);
+  TIMED(KC_EMB_GRAD, k_emb_grad(st, ctx, dX, C, E, emb_partial, emb_chunk, R, G_("emb"), s));
+  TIMED(PS_WGRAD, hip_check(launch_wgrad(kc.tile[PS_WGRAD], bf16, d_wg, n_wg, wg_tiles, st, s),
+                            "wgrad launch"));
+  TIMED(KC_COLSUM, k_colsum(st, d_cs, n_cs, cs_blocks, s));
+  if (out.update) TIMED(KC_ADAM, k_adam(st, param, grad, m, v, p16, P, ac, s));
   hip_check(hipGetLastError(), "step launch");
 }
 
