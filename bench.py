@@ -46,7 +46,8 @@ def log(msg):
 def lib_cfg(E, model, precision):
     keys = ("context", "embed", "latent", "blocks", "hidden", "branches", "lr", "beta1",
             "beta2", "eps", "seed")
-    return E.edpc_config_default(precision=precision, **{k: model[k] for k in keys})
+    return E.edpc_config_default(precision=precision, autotune=True,
+                                 **{k: model[k] for k in keys})
 
 
 def time_session(torch, sess, warmup, steps):

@@ -65,6 +65,12 @@ typedef enum { EDPC_FP32 = 0, EDPC_BF16 = 1 } edpc_precision;
 /* edpc_config.flags */
 #define EDPC_CFG_ZERO_HEAD 0x1u /* head weights start at zero (with lr = 0 the
                                    model predicts exactly 1/256: a test case) */
+#define EDPC_CFG_AUTOTUNE 0x2u  /* encoder / model creation times every tile
+                                   configuration of each matrix product and
+                                   keeps the fastest; the choice is written to
+                                   the container (so two encodes may pick
+                                   different, equally valid, summation orders).
+                                   Without it a fixed default is used. */
 
 typedef struct {
   uint32_t struct_size; /* sizeof(edpc_config) */

@@ -249,6 +249,7 @@ edpc_status edpc_model_create(const edpc_config* cfg, size_t n_slots, size_t max
     h->m.reset(new Model(*cfg, n_slots, max_rows, nullptr));
     h->m->init_params(nullptr);
     h->m->build_tables(nullptr);
+    if (cfg->flags & EDPC_CFG_AUTOTUNE) h->m->autotune(nullptr);
     hip_check(hipDeviceSynchronize(), "model create");
     *out = h.release();
     return EDPC_OK;

@@ -1,6 +1,7 @@
 // Multi-stream codec sessions (Algorithm 1 over b streams in lockstep) and
 // the container format.
 #pragma once
+#include <map>
 #include <memory>
 #include <vector>
 
@@ -67,9 +68,16 @@ struct Session {
   StreamIO io;
   Schedule sched;
 
+  // captured step windows: grid-row bucket -> executable graph of graph_steps steps
+  int graph_steps = 0;
+  std::map<int, hipGraphExec_t> graphs;
+  hipStream_t cap = nullptr;  // private non-blocking stream used only for capture
+
   ~Session();
   int rows_at(uint64_t i) const;
+  int bucket(int rows) const;
   void run(uint64_t k);
+  void step_direct(uint64_t i, int grid_rows, bool explicit_step, hipStream_t st);
   template <class T>
   T* dalloc(size_t n);
 };

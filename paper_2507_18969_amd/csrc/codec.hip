@@ -2,6 +2,7 @@
 #include "codec.h"
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 
@@ -117,6 +118,8 @@ size_t encode_bound(const edpc_config& cfg, const uint64_t* lens, size_t n) {
 
 Session::~Session() {
   if (s) (void)hipStreamSynchronize(s);
+  for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+  if (cap) (void)hipStreamDestroy(cap);
   model.reset();
   for (void* p : allocs) (void)hipFree(p);
 }
@@ -137,19 +140,65 @@ int Session::rows_at(uint64_t i) const {
   return (int)(it - lens_sorted.begin());
 }
 
-void Session::run(uint64_t k) {
-  const uint64_t end = std::min(maxlen, next + k);
+int Session::bucket(int rows) const {
+  // grid rows of a captured window: rows rounded up to a multiple of 128
+  const int b = ((rows + 127) / 128) * 128;
+  return std::min(b, (int)model->max_rows);
+}
+
+void Session::step_direct(uint64_t i, int grid_rows, bool explicit_step, hipStream_t st) {
+  KTimer* timer = model->timer;
   StepOutputs out;
   out.update = true;
-  for (uint64_t i = next; i < end; ++i) {
+  if (timer) timer->begin(KC_SCHEDULE, st);
+  k_step_schedule(model->st, sched, explicit_step ? (int)i : -1, st);
+  if (timer) { timer->end(st); timer->begin(KC_GATHER, st); }
+  k_gather(model->st, io, model->C, model->ctx, model->tgt, grid_rows, decoding, st);
+  if (timer) timer->end(st);
+  model->step(decoding ? MODE_DECODE : MODE_ENCODE, io, out, grid_rows, st);
+}
+
+// Steps next .. next+k-1.  Windows of graph_steps steps whose active rows fall
+// in one bucket replay a captured graph (each kernel reads the step number and
+// row count from the device-side step state); the rest launch directly.  The
+// graphs are captured on a private stream and launched on the session's.
+void Session::run(uint64_t k) {
+  const uint64_t end = std::min(maxlen, next + k);
+  uint64_t i = next;
+  const bool use_graphs = graph_steps > 0 && model->timer == nullptr;
+  while (i < end) {
     const int rows = rows_at(i);
-    KTimer* timer = model->timer;
-    if (timer) timer->begin(KC_SCHEDULE, s);
-    k_step_schedule(model->st, sched, (int)i, s);
-    if (timer) { timer->end(s); timer->begin(KC_GATHER, s); }
-    k_gather(model->st, io, model->C, model->ctx, model->tgt, rows, decoding, s);
-    if (timer) timer->end(s);
-    model->step(decoding ? MODE_DECODE : MODE_ENCODE, io, out, rows, s);
+    if (use_graphs && i + graph_steps <= end) {
+      const int b = bucket(rows);
+      if (bucket(rows_at(i + graph_steps - 1)) == b) {
+        auto it = graphs.find(b);
+        if (it == graphs.end()) {
+          if (!cap) hip_check(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "stream");
+          hipGraph_t g = nullptr;
+          hip_check(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "capture");
+          try {
+            for (int q = 0; q < graph_steps; ++q) step_direct(0, b, false, cap);
+          } catch (...) {
+            (void)hipStreamEndCapture(cap, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+          }
+          hip_check(hipStreamEndCapture(cap, &g), "capture");
+          hipGraphExec_t ex;
+          const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+          (void)hipGraphDestroy(g);
+          hip_check(e, "graph instantiate");
+          it = graphs.emplace(b, ex).first;
+        }
+        // the captured steps advance from the device step counter
+        k_step_set(model->st, (int)i - 1, s);
+        hip_check(hipGraphLaunch(it->second, s), "graph launch");
+        i += graph_steps;
+        continue;
+      }
+    }
+    step_direct(i, rows, true, s);
+    ++i;
   }
   next = end;
 }
@@ -168,6 +217,7 @@ static void common_setup(Session& ss, const KernelConfig* kc) {
   ss.model.reset(new Model(ss.cfg, n, rows, kc));
   ss.model->init_params(ss.s);
   ss.model->build_tables(ss.s);
+  if (!ss.decoding && (ss.cfg.flags & EDPC_CFG_AUTOTUNE)) ss.model->autotune(ss.s);
   hip_check(hipMemcpyAsync(ss.model->slot, perm.data(), std::min(n, rows) * sizeof(uint32_t),
                            hipMemcpyHostToDevice, ss.s), "copy");
   ss.d_lens_sorted = ss.dalloc<int64_t>(n);
@@ -193,6 +243,8 @@ static void common_setup(Session& ss, const KernelConfig* kc) {
   ss.io.off = ss.d_off;
   ss.io.lens = ss.d_lens;
   ss.next = std::min<uint64_t>(ss.cfg.context, ss.maxlen);
+  const char* env = std::getenv("EDPC_GRAPH_STEPS");
+  ss.graph_steps = env ? std::max(0, std::atoi(env)) : 32;
 }
 
 std::unique_ptr<Session> encoder_begin(const edpc_config& cfg, const uint8_t* d_in,

@@ -63,16 +63,36 @@ __device__ __forceinline__ int acc_col(int lane) {
 // ---------------------------------------------------------------------------
 // Operand tile staging.  LDS layout: FP32 tiles are stored k-major
 // [BK][ROWS + 4]; BF16 tiles row-major [ROWS][BK + 8] so that one lane reads
-// its 8 consecutive k values with a single 16-byte access.
+// its 8 consecutive k values with a single 16-byte access.  A BF16 operand
+// stored row-contiguous in memory (k slowest) is moved in 8 x 8 blocks that
+// each thread transposes in registers, so LDS still gets 16-byte stores.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ void transpose8x8_bf16(const uint4* in, uint4* out) {
+  // in[i] holds 8 bf16 of row i (columns 0..7); out[j] gets column j (rows 0..7)
+  const uint32_t* w = (const uint32_t*)in;  // w[4 * i + q] = (col 2q, col 2q+1) of row i
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int q = j >> 1;
+    const uint32_t sel = (j & 1) ? 0x07060302u : 0x05040100u;
+    uint32_t o[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      o[k] = __builtin_amdgcn_perm(w[4 * (2 * k + 1) + q], w[4 * (2 * k) + q], sel);
+    out[j] = make_uint4(o[0], o[1], o[2], o[3]);
+  }
+}
+
 template <bool BF, int ROWS, int BK>
 struct Stage {
   static constexpr int VEC = BF ? 8 : 4;                 // elements per 16-byte vector
   static constexpr int NVEC = ROWS * BK / VEC;           // vectors per tile
   static constexpr int PER_THREAD = (NVEC + kThreads - 1) / kThreads;
+  static constexpr int NBLK = (ROWS / 8) * (BK / 8);     // 8 x 8 blocks (BF16, row-contiguous)
+  static constexpr int BLK_PER_THREAD = (NBLK + kThreads - 1) / kThreads;
+  static constexpr int NREG = PER_THREAD > 8 * BLK_PER_THREAD ? PER_THREAD : 8 * BLK_PER_THREAD;
   static constexpr int STRIDE = BF ? (BK + 8) : (ROWS + 4);  // LDS row stride (elements)
   static constexpr int LDS_ELEMS = BF ? ROWS * (BK + 8) : BK * (ROWS + 4);
-  uint4 reg[PER_THREAD];
+  uint4 reg[NREG];
 
   // Global -> registers.  kmajor: src[row * ld + k]; else src[k * ld + row].
   template <bool KMAJOR>
@@ -80,6 +100,23 @@ struct Stage {
                                        int k0, int K) {
     const char* src = (const char*)srcv;
     const int esz = BF ? 2 : 4;
+    if constexpr (BF && !KMAJOR) {
+#pragma unroll
+      for (int p = 0; p < BLK_PER_THREAD; ++p) {
+        const int b = threadIdx.x + p * kThreads;
+        const int kb = b / (ROWS / 8), rb = b % (ROWS / 8);
+        const int gr = row0 + rb * 8;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int gk = k0 + kb * 8 + i;
+          uint4 val = make_uint4(0, 0, 0, 0);
+          if (b < NBLK && gr < rows_valid && gk < K)
+            val = *(const uint4*)(src + ((long long)gk * ld + gr) * esz);
+          reg[8 * p + i] = val;
+        }
+      }
+      return;
+    }
 #pragma unroll
     for (int p = 0; p < PER_THREAD; ++p) {
       const int v = threadIdx.x + p * kThreads;
@@ -103,6 +140,20 @@ struct Stage {
 
   template <bool KMAJOR>
   __device__ __forceinline__ void store(void* ldsv) {
+    if constexpr (BF && !KMAJOR) {
+      bf16_t* lds = (bf16_t*)ldsv;
+#pragma unroll
+      for (int p = 0; p < BLK_PER_THREAD; ++p) {
+        const int b = threadIdx.x + p * kThreads;
+        if (b >= NBLK) continue;
+        const int kb = b / (ROWS / 8), rb = b % (ROWS / 8);
+        uint4 t[8];
+        transpose8x8_bf16(&reg[8 * p], t);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) *(uint4*)(lds + (rb * 8 + j) * STRIDE + kb * 8) = t[j];
+      }
+      return;
+    }
 #pragma unroll
     for (int p = 0; p < PER_THREAD; ++p) {
       const int v = threadIdx.x + p * kThreads;
@@ -120,15 +171,8 @@ struct Stage {
         }
       } else {
         bf16_t* lds = (bf16_t*)ldsv;
-        if constexpr (KMAJOR) {
-          const int row = v / (BK / VEC), kq = v % (BK / VEC);
-          *(uint4*)(lds + row * STRIDE + kq * 8) = reg[p];
-        } else {
-          const int k = v / (ROWS / VEC), rq = v % (ROWS / VEC);
-          const bf16_t* h = (const bf16_t*)&reg[p];
-#pragma unroll
-          for (int j = 0; j < 8; ++j) lds[(rq * 8 + j) * STRIDE + k] = h[j];
-        }
+        const int row = v / (BK / VEC), kq = v % (BK / VEC);
+        *(uint4*)(lds + row * STRIDE + kq * 8) = reg[p];
       }
     }
   }
@@ -157,11 +201,13 @@ struct TileCfg {
 // One output tile (m0, n0) of C = A * B_i for i < NB.
 template <bool BF, class T, bool AK, bool BKM, int NB>
 struct TileCompute {
-  static constexpr int BK = 32;
+  static constexpr int BK = BF ? 128 : 64;
   static constexpr int MB = T::MB, TM = T::TM, TN = T::TN;
   typedef Mfma<BF, MB> Op;
   typedef Stage<BF, T::BM, BK> SA;
   typedef Stage<BF, T::BN, BK> SB;
+  // two register stages unless that would hold more than 16 vectors a thread
+  static constexpr int ST = (Stage<BF, T::BM, BK>::NREG + NB * Stage<BF, T::BN, BK>::NREG) <= 16 ? 2 : 1;
   typename Op::Acc acc[NB][TM][TN];
 
   __device__ __forceinline__ void run(const void* A, int lda, const void* B, int ldb,
@@ -181,39 +227,52 @@ struct TileCompute {
 #pragma unroll
           for (int r = 0; r < Op::NACC; ++r) acc[b][i][j][r] = 0.0f;
 
-    SA sa;
-    SB sb[NB];
-    sa.template load<AK>(A, lda, m0, M, 0, K);
+    // ST register stages: tiles k0 .. k0 + (ST-1)*BK are in flight together
+    SA sa[ST];
+    SB sb[ST][NB];
 #pragma unroll
-    for (int b = 0; b < NB; ++b)
-      sb[b].template load<BKM>((const char*)B + b * bstride * esz, ldb, n0, N, 0, K);
-
-    for (int k0 = 0; k0 < K; k0 += BK) {
-      __syncthreads();
-      sa.template store<AK>(lds_a);
-#pragma unroll
-      for (int b = 0; b < NB; ++b) sb[b].template store<BKM>(lds_b + b * SB::LDS_ELEMS * esz);
-      __syncthreads();
-      if (k0 + BK < K) {
-        sa.template load<AK>(A, lda, m0, M, k0 + BK, K);
+    for (int q = 0; q < ST; ++q) {
+      if (q * BK < K) {
+        sa[q].template load<AK>(A, lda, m0, M, q * BK, K);
 #pragma unroll
         for (int b = 0; b < NB; ++b)
-          sb[b].template load<BKM>((const char*)B + b * bstride * esz, ldb, n0, N, k0 + BK, K);
+          sb[q][b].template load<BKM>((const char*)B + b * bstride * esz, ldb, n0, N, q * BK, K);
       }
+    }
+    for (int k0 = 0; k0 < K; k0 += ST * BK) {
 #pragma unroll
-      for (int kk = 0; kk < BK; kk += Op::KSTEP) {
-        typename Op::Frag fa[TM];
+      for (int q = 0; q < ST; ++q) {
+        const int kq = k0 + q * BK;
+        if (kq < K) {
+          __syncthreads();
+          sa[q].template store<AK>(lds_a);
 #pragma unroll
-        for (int i = 0; i < TM; ++i)
-          fa[i] = frag_read<BF, MB, BK>(lds_a, SA::STRIDE, (wm * TM + i) * MB, kk, lane);
+          for (int b = 0; b < NB; ++b)
+            sb[q][b].template store<BKM>(lds_b + b * SB::LDS_ELEMS * esz);
+          __syncthreads();
+          if (kq + ST * BK < K) {
+            sa[q].template load<AK>(A, lda, m0, M, kq + ST * BK, K);
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
+            for (int b = 0; b < NB; ++b)
+              sb[q][b].template load<BKM>((const char*)B + b * bstride * esz, ldb, n0, N,
+                                          kq + ST * BK, K);
+          }
 #pragma unroll
-          for (int j = 0; j < TN; ++j) {
-            typename Op::Frag fb = frag_read<BF, MB, BK>(lds_b + b * SB::LDS_ELEMS * esz,
-                                                         SB::STRIDE, (wn * TN + j) * MB, kk, lane);
+          for (int kk = 0; kk < BK; kk += Op::KSTEP) {
+            typename Op::Frag fa[TM];
 #pragma unroll
-            for (int i = 0; i < TM; ++i) acc[b][i][j] = Op::mma(fa[i], fb, acc[b][i][j]);
+            for (int i = 0; i < TM; ++i)
+              fa[i] = frag_read<BF, MB, BK>(lds_a, SA::STRIDE, (wm * TM + i) * MB, kk, lane);
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+#pragma unroll
+              for (int j = 0; j < TN; ++j) {
+                typename Op::Frag fb = frag_read<BF, MB, BK>(lds_b + b * SB::LDS_ELEMS * esz,
+                                                             SB::STRIDE, (wn * TN + j) * MB, kk, lane);
+#pragma unroll
+                for (int i = 0; i < TM; ++i) acc[b][i][j] = Op::mma(fa[i], fb, acc[b][i][j]);
+              }
+            }
           }
         }
       }

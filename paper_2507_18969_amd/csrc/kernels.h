@@ -42,7 +42,9 @@ struct HeadArgs {
   int want_grad;
 };
 
+// step >= 0: state for that step; step < 0: the step after st->step.
 void k_step_schedule(StepState* st, Schedule sc, int step, hipStream_t s);
+void k_step_set(StepState* st, int step, hipStream_t s);
 void k_step_explicit(StepState* st, int rows, uint32_t tau, float beta1, float beta2, hipStream_t s);
 
 void k_gather(const StepState* st, StreamIO io, int C, uint8_t* ctx, uint8_t* tgt, int max_rows,
@@ -69,14 +71,18 @@ struct ColsumJob {
   const float* rstd;
   float* dst;          // [cols]
   int cols, ld;
-  int col_block_begin; // first block of this job
-  float scale;
+  int col_block_begin; // first 64-column block of this job
+  int col_offset;      // first column of this job in the partial buffer
+  float scale;         // 0: scale by 1/rows
 };
+size_t colsum_partial_elems(int max_rows, int total_cols);
 void k_colsum(const StepState* st, const ColsumJob* jobs, int n_jobs, int total_blocks,
-              hipStream_t s);
+              int total_cols, float* partial, int max_rows, hipStream_t s);
 
+void emb_grad_plan(int max_rows, int C, int E, int* chunk_rows, int* sub_rows);
 void k_emb_grad(const StepState* st, const uint8_t* ctx, const float* dx, int C, int E,
-                float* partial, int chunk_rows, int max_rows, float* demb, hipStream_t s);
+                float* partial, int chunk_rows, int sub_rows, int max_rows, float* demb,
+                hipStream_t s);
 void k_adam(const StepState* st, float* p, const float* g, float* m, float* v, bf16_t* p16,
             size_t n, AdamCfg ac, hipStream_t s);
 

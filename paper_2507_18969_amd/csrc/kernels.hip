@@ -31,6 +31,14 @@ void k_step_schedule(StepState* st, Schedule sc, int step, hipStream_t s) {
   hipLaunchKernelGGL(step_schedule_kernel, dim3(1), dim3(64), 0, s, st, sc, step);
 }
 
+__global__ void step_set_kernel(StepState* st, int step) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) st->step = step;
+}
+
+void k_step_set(StepState* st, int step, hipStream_t s) {
+  hipLaunchKernelGGL(step_set_kernel, dim3(1), dim3(64), 0, s, st, step);
+}
+
 __global__ void step_explicit_kernel(StepState* st, int rows, uint32_t tau, float beta1,
                                      float beta2) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -252,10 +260,68 @@ __global__ void __launch_bounds__(256) ln_fwd_kernel(const StepState* __restrict
   }
 }
 
+// Register-resident variant for F = 256 * NV: each lane holds NV float4.
+template <int NV>
+__global__ void __launch_bounds__(256) ln_fwd_reg_kernel(const StepState* __restrict__ st,
+                                                         const float* __restrict__ h,
+                                                         const float* __restrict__ gamma,
+                                                         const float* __restrict__ beta,
+                                                         float* __restrict__ z32,
+                                                         bf16_t* __restrict__ z16,
+                                                         float* __restrict__ mean,
+                                                         float* __restrict__ rstd) {
+  constexpr int F = 256 * NV;
+  const int lane = threadIdx.x & 63;
+  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= st->rows) return;
+  const float* hr = h + (size_t)r * F;
+  float4 x[NV];
+  float s = 0.f;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    x[v] = *(const float4*)(hr + 4 * (lane + 64 * v));
+    s += (x[v].x + x[v].y) + (x[v].z + x[v].w);
+  }
+  const float mu = wave_sum(s) / (float)F;
+  float q = 0.f;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const float a = x[v].x - mu, b = x[v].y - mu, c = x[v].z - mu, d = x[v].w - mu;
+    q += (a * a + b * b) + (c * c + d * d);
+  }
+  const float var = wave_sum(q) / (float)F;
+  const float rs = 1.0f / sqrtf(var + 1e-5f);
+  if (lane == 0) {
+    mean[r] = mu;
+    rstd[r] = rs;
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const int f = 4 * (lane + 64 * v);
+    const float4 gm = *(const float4*)(gamma + f);
+    const float4 bt = *(const float4*)(beta + f);
+    float4 z;
+    z.x = (x[v].x - mu) * rs * gm.x + bt.x;
+    z.y = (x[v].y - mu) * rs * gm.y + bt.y;
+    z.z = (x[v].z - mu) * rs * gm.z + bt.z;
+    z.w = (x[v].w - mu) * rs * gm.w + bt.w;
+    if (z32) *(float4*)(z32 + (size_t)r * F + f) = z;
+    if (z16)
+      *(ushort4*)(z16 + (size_t)r * F + f) = make_ushort4(f2bf(z.x), f2bf(z.y), f2bf(z.z), f2bf(z.w));
+  }
+}
+
 void k_ln_fwd(const StepState* st, const float* h, const float* gamma, const float* beta, int F,
               float* z32, bf16_t* z16, float* mean, float* rstd, int max_rows, hipStream_t s) {
-  hipLaunchKernelGGL(ln_fwd_kernel, dim3(blocks_for(max_rows, 4)), dim3(256), 0, s, st, h, gamma,
-                     beta, F, z32, z16, mean, rstd);
+  const dim3 g(blocks_for(max_rows, 4)), b(256);
+  switch (F % 256 == 0 ? F / 256 : 0) {
+    case 1: hipLaunchKernelGGL(ln_fwd_reg_kernel<1>, g, b, 0, s, st, h, gamma, beta, z32, z16, mean, rstd); return;
+    case 2: hipLaunchKernelGGL(ln_fwd_reg_kernel<2>, g, b, 0, s, st, h, gamma, beta, z32, z16, mean, rstd); return;
+    case 4: hipLaunchKernelGGL(ln_fwd_reg_kernel<4>, g, b, 0, s, st, h, gamma, beta, z32, z16, mean, rstd); return;
+    case 8: hipLaunchKernelGGL(ln_fwd_reg_kernel<8>, g, b, 0, s, st, h, gamma, beta, z32, z16, mean, rstd); return;
+    default:
+      hipLaunchKernelGGL(ln_fwd_kernel, g, b, 0, s, st, h, gamma, beta, F, z32, z16, mean, rstd);
+  }
 }
 
 // dh = dh_next + rstd * (dxhat - mean(dxhat) - xhat * mean(dxhat * xhat)),
@@ -299,11 +365,59 @@ __global__ void __launch_bounds__(256) ln_bwd_kernel(
   }
 }
 
+template <int NV>
+__global__ void __launch_bounds__(256) ln_bwd_reg_kernel(
+    const StepState* __restrict__ st, const float* __restrict__ h, const float* __restrict__ mean,
+    const float* __restrict__ rstd, const float* __restrict__ gamma, const float* __restrict__ dz,
+    const float* __restrict__ dh_next, float* __restrict__ dh32, bf16_t* __restrict__ dh16) {
+  constexpr int F = 256 * NV;
+  const int lane = threadIdx.x & 63;
+  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= st->rows) return;
+  const float mu = mean[r], rs = rstd[r];
+  float xh[NV][4], dx[NV][4];
+  float s1 = 0.f, s2 = 0.f;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const int f = 4 * (lane + 64 * v);
+    const float4 x = *(const float4*)(h + (size_t)r * F + f);
+    const float4 d = *(const float4*)(dz + (size_t)r * F + f);
+    const float4 gm = *(const float4*)(gamma + f);
+    xh[v][0] = (x.x - mu) * rs; xh[v][1] = (x.y - mu) * rs;
+    xh[v][2] = (x.z - mu) * rs; xh[v][3] = (x.w - mu) * rs;
+    dx[v][0] = d.x * gm.x; dx[v][1] = d.y * gm.y; dx[v][2] = d.z * gm.z; dx[v][3] = d.w * gm.w;
+    s1 += (dx[v][0] + dx[v][1]) + (dx[v][2] + dx[v][3]);
+    s2 += (dx[v][0] * xh[v][0] + dx[v][1] * xh[v][1]) + (dx[v][2] * xh[v][2] + dx[v][3] * xh[v][3]);
+  }
+  const float m1 = wave_sum(s1) / (float)F;
+  const float m2 = wave_sum(s2) / (float)F;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const int f = 4 * (lane + 64 * v);
+    const float4 dn = *(const float4*)(dh_next + (size_t)r * F + f);
+    float4 o;
+    o.x = dn.x + rs * (dx[v][0] - m1 - xh[v][0] * m2);
+    o.y = dn.y + rs * (dx[v][1] - m1 - xh[v][1] * m2);
+    o.z = dn.z + rs * (dx[v][2] - m1 - xh[v][2] * m2);
+    o.w = dn.w + rs * (dx[v][3] - m1 - xh[v][3] * m2);
+    *(float4*)(dh32 + (size_t)r * F + f) = o;
+    if (dh16)
+      *(ushort4*)(dh16 + (size_t)r * F + f) = make_ushort4(f2bf(o.x), f2bf(o.y), f2bf(o.z), f2bf(o.w));
+  }
+}
+
 void k_ln_bwd(const StepState* st, const float* h, const float* mean, const float* rstd,
               const float* gamma, const float* dz, const float* dh_next, int F, float* dh32,
               bf16_t* dh16, int max_rows, hipStream_t s) {
-  hipLaunchKernelGGL(ln_bwd_kernel, dim3(blocks_for(max_rows, 4)), dim3(256), 0, s, st, h, mean,
-                     rstd, gamma, dz, dh_next, F, dh32, dh16);
+  const dim3 g(blocks_for(max_rows, 4)), b(256);
+  switch (F % 256 == 0 ? F / 256 : 0) {
+    case 1: hipLaunchKernelGGL(ln_bwd_reg_kernel<1>, g, b, 0, s, st, h, mean, rstd, gamma, dz, dh_next, dh32, dh16); return;
+    case 2: hipLaunchKernelGGL(ln_bwd_reg_kernel<2>, g, b, 0, s, st, h, mean, rstd, gamma, dz, dh_next, dh32, dh16); return;
+    case 4: hipLaunchKernelGGL(ln_bwd_reg_kernel<4>, g, b, 0, s, st, h, mean, rstd, gamma, dz, dh_next, dh32, dh16); return;
+    case 8: hipLaunchKernelGGL(ln_bwd_reg_kernel<8>, g, b, 0, s, st, h, mean, rstd, gamma, dz, dh_next, dh32, dh16); return;
+    default:
+      hipLaunchKernelGGL(ln_bwd_kernel, g, b, 0, s, st, h, mean, rstd, gamma, dz, dh_next, F, dh32, dh16);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -419,74 +533,125 @@ void k_head(const StepState* st, HeadArgs a, StreamIO io, int max_rows, hipStrea
 }
 
 // ---------------------------------------------------------------------------
-// Column sums over the active rows, fixed order: 4 row slices per column
-// combined in slice order.
+// Column sums over the active rows (bias and LayerNorm affine gradients).
+// Two passes with a fixed order: rows are cut into chunks of kColChunk; a
+// block sums 64 columns of one chunk (4 interleaved row slices added in slice
+// order) into partial[chunk][col]; the second pass adds the chunks in order.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) colsum_kernel(const StepState* __restrict__ st,
-                                                     const ColsumJob* __restrict__ jobs,
-                                                     int n_jobs) {
+constexpr int kColChunk = 64;
+
+__global__ void __launch_bounds__(256) colsum_partial_kernel(const StepState* __restrict__ st,
+                                                             const ColsumJob* __restrict__ jobs,
+                                                             int n_jobs, int total_cols,
+                                                             float* __restrict__ partial) {
+  const int rows = st->rows;
+  const int r0 = blockIdx.y * kColChunk;
+  if (r0 >= rows) return;
   int j = 0;
   while (j + 1 < n_jobs && (int)blockIdx.x >= jobs[j + 1].col_block_begin) ++j;
   const ColsumJob jb = jobs[j];
-  const int col = ((int)blockIdx.x - jb.col_block_begin) * 64 + (threadIdx.x & 63);
+  const int lc = ((int)blockIdx.x - jb.col_block_begin) * 64 + (threadIdx.x & 63);
   const int slice = threadIdx.x >> 6;
-  const int rows = st->rows;
+  const int r1 = min(rows, r0 + kColChunk);
   float acc = 0.f;
-  if (col < jb.cols) {
+  if (lc < jb.cols) {
     if (jb.h) {
-      for (int r = slice; r < rows; r += 4) {
-        const float xh = (jb.h[(size_t)r * jb.ld + col] - jb.mean[r]) * jb.rstd[r];
-        acc += jb.src[(size_t)r * jb.ld + col] * xh;
+#pragma unroll 4
+      for (int r = r0 + slice; r < r1; r += 4) {
+        const float xh = (jb.h[(size_t)r * jb.ld + lc] - jb.mean[r]) * jb.rstd[r];
+        acc += jb.src[(size_t)r * jb.ld + lc] * xh;
       }
     } else {
-      for (int r = slice; r < rows; r += 4) acc += jb.src[(size_t)r * jb.ld + col];
+#pragma unroll 4
+      for (int r = r0 + slice; r < r1; r += 4) acc += jb.src[(size_t)r * jb.ld + lc];
     }
   }
   __shared__ float part[4][64];
   part[slice][threadIdx.x & 63] = acc;
   __syncthreads();
-  if (slice == 0 && col < jb.cols) {
-    const float tot = (part[0][threadIdx.x] + part[1][threadIdx.x]) +
-                      (part[2][threadIdx.x] + part[3][threadIdx.x]);
-    jb.dst[col] = tot * (jb.scale == 0.0f ? st->inv_rows : jb.scale);
+  if (slice == 0 && lc < jb.cols) {
+    const int t = threadIdx.x;
+    partial[(size_t)blockIdx.y * total_cols + jb.col_offset + lc] =
+        (part[0][t] + part[1][t]) + (part[2][t] + part[3][t]);
   }
 }
 
+__global__ void colsum_reduce_kernel(const StepState* __restrict__ st,
+                                     const ColsumJob* __restrict__ jobs, int n_jobs,
+                                     int total_cols, const float* __restrict__ partial) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= total_cols) return;
+  int j = 0;
+  while (j + 1 < n_jobs && c >= jobs[j + 1].col_offset) ++j;
+  const ColsumJob& jb = jobs[j];
+  const int nch = (st->rows + kColChunk - 1) / kColChunk;
+  float s = 0.f;
+  for (int k = 0; k < nch; ++k) s += partial[(size_t)k * total_cols + c];
+  jb.dst[c - jb.col_offset] = s * (jb.scale == 0.0f ? st->inv_rows : jb.scale);
+}
+
+size_t colsum_partial_elems(int max_rows, int total_cols) {
+  return (size_t)((max_rows + kColChunk - 1) / kColChunk) * total_cols;
+}
+
 void k_colsum(const StepState* st, const ColsumJob* jobs, int n_jobs, int total_blocks,
-              hipStream_t s) {
+              int total_cols, float* partial, int max_rows, hipStream_t s) {
   if (total_blocks == 0) return;
-  hipLaunchKernelGGL(colsum_kernel, dim3(total_blocks), dim3(256), 0, s, st, jobs, n_jobs);
+  dim3 grid(total_blocks, (max_rows + kColChunk - 1) / kColChunk);
+  hipLaunchKernelGGL(colsum_partial_kernel, grid, dim3(256), 0, s, st, jobs, n_jobs, total_cols,
+                     partial);
+  hipLaunchKernelGGL(colsum_reduce_kernel, dim3(blocks_for(total_cols, 256)), dim3(256), 0, s, st,
+                     jobs, n_jobs, total_cols, (const float*)partial);
 }
 
 // ---------------------------------------------------------------------------
 // Embedding gradient: dEmb[v] = sum over (row, position) with ctx = v of the
-// matching E-slice of dX.  Chunks of rows accumulate in LDS, cell (v, e)
-// owned by one thread so the additions happen in row-major pair order; the
-// chunk partials are then summed in chunk order.
+// matching E-slice of dX.  A block takes a chunk of rows, staged through LDS
+// a few rows at a time; thread v keeps the E sums of byte value v in
+// registers and adds the matching pairs in row-major pair order.  The chunk
+// partials are then added in chunk order.
 // ---------------------------------------------------------------------------
+template <int E>
 __global__ void __launch_bounds__(256) emb_grad_partial_kernel(
     const StepState* __restrict__ st, const uint8_t* __restrict__ ctx, const float* __restrict__ dx,
-    int C, int E, int chunk_rows, float* __restrict__ partial) {
-  extern __shared__ float acc[];  // [256][E]
+    int C, int chunk_rows, int sub_rows, float* __restrict__ partial) {
+  extern __shared__ float smem_f[];
+  float* lds_dx = smem_f;                                   // [sub_rows][F]
+  uint8_t* lds_ctx = (uint8_t*)(smem_f + (size_t)sub_rows * C * E);  // [sub_rows][C] (+16 pad)
   const int rows = st->rows;
+  const int F = C * E;
   const int r0 = blockIdx.x * chunk_rows;
-  const int G = 256 / E;
-  const int g = threadIdx.x / E, e = threadIdx.x % E;
-  float* out = partial + (size_t)blockIdx.x * 256 * E;
-  if (g < G)
-    for (int v = g; v < 256; v += G) acc[v * E + e] = 0.f;
-  if (r0 < rows && g < G) {
-    const int r1 = min(rows, r0 + chunk_rows);
-    const int F = C * E;
-    for (int r = r0; r < r1; ++r) {
-      for (int c = 0; c < C; ++c) {
-        const int v = ctx[r * C + c];
-        if (v % G == g) acc[v * E + e] += dx[(size_t)r * F + c * E + e];
+  const int v = threadIdx.x;
+  float acc[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) acc[e] = 0.f;
+  const int r_end = min(rows, r0 + chunk_rows);
+  for (int rs = r0; rs < r_end; rs += sub_rows) {
+    const int nr = min(sub_rows, r_end - rs);
+    __syncthreads();
+    const float4* src = (const float4*)(dx + (size_t)rs * F);
+    for (int k = threadIdx.x; k < nr * F / 4; k += 256) ((float4*)lds_dx)[k] = src[k];
+    for (int k = threadIdx.x; k < nr * C; k += 256) lds_ctx[k] = ctx[(size_t)rs * C + k];
+    __syncthreads();
+    const int np = nr * C;
+    // 16 context bytes per LDS read; pairs still visited in increasing order
+    for (int p0 = 0; p0 < np; p0 += 16) {
+      const uint4 w = *(const uint4*)(lds_ctx + p0);
+      const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int p = p0 + q;
+        if (p < np && ((ws[q >> 2] >> (8 * (q & 3))) & 0xFFu) == (uint32_t)v) {
+          const float* d = lds_dx + (size_t)(p / C) * F + (p % C) * E;
+#pragma unroll
+          for (int e = 0; e < E; ++e) acc[e] += d[e];
+        }
       }
     }
   }
-  __syncthreads();
-  for (int k = threadIdx.x; k < 256 * E; k += 256) out[k] = acc[k];
+  float* out = partial + (size_t)blockIdx.x * 256 * E + (size_t)v * E;
+#pragma unroll
+  for (int e = 0; e < E; ++e) out[e] = acc[e];
 }
 
 __global__ void emb_grad_reduce_kernel(const StepState* __restrict__ st,
@@ -500,11 +665,34 @@ __global__ void emb_grad_reduce_kernel(const StepState* __restrict__ st,
   demb[k] = s;
 }
 
+void emb_grad_plan(int max_rows, int C, int E, int* chunk_rows, int* sub_rows) {
+  const int F = C * E;
+  int sub = 8192 / F;
+  sub = sub < 1 ? 1 : (sub > 16 ? 16 : sub);
+  int chunk = sub;
+  while ((max_rows + chunk - 1) / chunk > 256) chunk += sub;
+  *chunk_rows = chunk;
+  *sub_rows = sub;
+}
+
 void k_emb_grad(const StepState* st, const uint8_t* ctx, const float* dx, int C, int E,
-                float* partial, int chunk_rows, int max_rows, float* demb, hipStream_t s) {
+                float* partial, int chunk_rows, int sub_rows, int max_rows, float* demb,
+                hipStream_t s) {
   const int nb = (max_rows + chunk_rows - 1) / chunk_rows;
-  hipLaunchKernelGGL(emb_grad_partial_kernel, dim3(nb), dim3(256), 256 * E * sizeof(float), s, st,
-                     ctx, dx, C, E, chunk_rows, partial);
+  const size_t smem = (size_t)sub_rows * C * E * sizeof(float) + (size_t)sub_rows * C + 32;
+#define EMB_CASE(EE)                                                                            \
+  case EE:                                                                                      \
+    hipLaunchKernelGGL(emb_grad_partial_kernel<EE>, dim3(nb), dim3(256), smem, s, st, ctx, dx, C, \
+                       chunk_rows, sub_rows, partial);                                          \
+    break;
+  switch (E) {
+    EMB_CASE(4)
+    EMB_CASE(8)
+    EMB_CASE(16)
+    EMB_CASE(32)
+    EMB_CASE(64)
+  }
+#undef EMB_CASE
   const int n = 256 * E;
   hipLaunchKernelGGL(emb_grad_reduce_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, st, partial,
                      chunk_rows, n, demb);

@@ -127,12 +127,16 @@ struct Model {
   bf16_t* dz16 = nullptr;
   float *dY = nullptr, *dX1_32 = nullptr, *dX = nullptr, *emb_partial = nullptr;
   bf16_t* dX1_16 = nullptr;
-  WgradProblem* d_wg = nullptr;
-  int n_wg = 0, wg_tiles = 0;
+  struct WgTable {
+    WgradProblem* d = nullptr;
+    int n = 0, tiles = 0;
+  } wg_tab[TILE_COUNT];
   ColsumJob* d_cs = nullptr;
-  int n_cs = 0, cs_blocks = 0;
+  int n_cs = 0, cs_blocks = 0, cs_cols = 0;
+  float* cs_partial = nullptr;
   ColsumJob* d_loss_job = nullptr;
-  int emb_chunk = 16;
+  float* loss_partial = nullptr;
+  int emb_chunk = 16, emb_sub = 16;
   KTimer* timer = nullptr;
   std::vector<void*> allocs;
 
@@ -153,6 +157,8 @@ struct Model {
   void step(StepMode mode, const StreamIO& io, const StepOutputs& out, int grid_rows,
             hipStream_t s);
 
+  void product(int ps, int j, int R, hipStream_t s);
+  void autotune(hipStream_t s);
   static KernelConfig default_config(const edpc_config& c, size_t rows);
   static void validate(const edpc_config& c);
 

@@ -99,22 +99,50 @@ void Model::validate(const edpc_config& c) {
   if (c.branches < 1 || c.branches > 3) fail(EDPC_E_INVALID_ARG, "branches must be 1..3");
   if (c.cdf_bits != 16) fail(EDPC_E_INVALID_ARG, "only 16-bit CDFs are supported");
   if (c.precision != EDPC_FP32 && c.precision != EDPC_BF16) fail(EDPC_E_INVALID_ARG, "unknown precision");
-  if (c.flags & ~EDPC_CFG_ZERO_HEAD) fail(EDPC_E_INVALID_ARG, "unknown config flags");
+  if (c.flags & ~(EDPC_CFG_ZERO_HEAD | EDPC_CFG_AUTOTUNE)) fail(EDPC_E_INVALID_ARG, "unknown config flags");
   if ((c.context * c.embed) % 8) fail(EDPC_E_INVALID_ARG, "context * embed must be a multiple of 8");
   if ((uint64_t)c.context * c.embed > 16384) fail(EDPC_E_INVALID_ARG, "context * embed must be <= 16384");
   if (!(c.lr >= 0.f) || !(c.beta1 >= 0.f && c.beta1 < 1.f) || !(c.beta2 >= 0.f && c.beta2 < 1.f) || !(c.eps > 0.f))
     fail(EDPC_E_INVALID_ARG, "invalid Adam constants");
 }
 
+// Largest tile whose grid still has >= `want` tiles; the smallest otherwise.
+static int pick_tile(size_t M, const std::vector<std::pair<int, int>>& shapes, size_t want) {
+  static const int order[] = {TILE_128x128, TILE_128x64, TILE_64x128, TILE_64x64,
+                              TILE_64x32,   TILE_32x64,  TILE_32x32};
+  for (int t : order) {
+    const TileShape ts = tile_shape(t);
+    size_t n = 0;
+    for (auto& mn : shapes) {
+      const size_t m = mn.first ? (size_t)mn.first : M;
+      n += ((m + ts.bm - 1) / ts.bm) * ((mn.second + ts.bn - 1) / ts.bn);
+    }
+    if (n >= want) return t;
+  }
+  return TILE_32x32;
+}
+
 KernelConfig Model::default_config(const edpc_config& c, size_t rows) {
   KernelConfig k;
-  const int big = rows >= 4096 ? TILE_128x128 : rows >= 1024 ? TILE_64x64 : TILE_32x32;
-  for (int i = 0; i < PS_COUNT; ++i) k.tile[i] = big;
-  const int mid = rows >= 4096 ? TILE_128x64 : rows >= 1024 ? TILE_64x32 : TILE_32x32;
-  k.tile[PS_LTE_DOWN] = mid;
-  k.tile[PS_LTE_UP_BWD] = mid;
-  k.tile[PS_WGRAD] = rows >= 1024 ? TILE_64x64 : TILE_32x32;
-  (void)c;
+  const int F = c.context * c.embed, L = c.latent, H = c.hidden;
+  const int KH = c.branches * H;
+  auto one = [&](int n) { return pick_tile(rows, {{0, n}}, 256); };
+  k.tile[PS_LTE_DOWN] = one(L);
+  k.tile[PS_LTE_UP] = one(F);
+  k.tile[PS_GATE] = one(H);
+  k.tile[PS_OUT] = one(F);
+  k.tile[PS_HEAD] = one(256);
+  k.tile[PS_HEAD_BWD] = one(F);
+  k.tile[PS_GATE_BWD] = one(H);
+  k.tile[PS_DZ] = one(F);
+  k.tile[PS_LTE_UP_BWD] = one(L);
+  k.tile[PS_LTE_DOWN_BWD] = one(F);
+  std::vector<std::pair<int, int>> wg = {{256, F}, {F, L}, {L, F}};
+  for (uint32_t j = 0; j < c.blocks; ++j) {
+    wg.push_back({F, H});
+    wg.push_back({KH, F});
+  }
+  k.tile[PS_WGRAD] = pick_tile(rows, wg, 512);
   return k;
 }
 
@@ -224,6 +252,7 @@ Model::Model(const edpc_config& c, size_t nslots, size_t rows, const KernelConfi
   dX1_32 = dalloc<float>(R * L);
   if (bf16) dX1_16 = dalloc<bf16_t>(R * L);
   dX = dalloc<float>(R * F);
+  emb_grad_plan((int)R, C, E, &emb_chunk, &emb_sub);
   emb_partial = dalloc<float>(((R + emb_chunk - 1) / emb_chunk) * 256 * (size_t)E);
 }
 
@@ -261,39 +290,44 @@ void Model::init_params(hipStream_t s) {
 }
 
 void Model::build_tables(hipStream_t s) {
-  // weight-gradient products (sum over rows)
-  std::vector<WgradProblem> wg;
-  const TileShape ts = tile_shape(kc.tile[PS_WGRAD]);
-  auto addw = [&](const void* dout, const void* in, float* dw, int Mo, int Ni) {
-    WgradProblem p;
-    p.dout = dout;
-    p.in = in;
-    p.dw = dw;
-    p.M = Mo;
-    p.N = Ni;
-    p.tiles_n = (Ni + ts.bn - 1) / ts.bn;
-    p.tile_begin = wg_tiles;
-    wg_tiles += p.tiles_n * ((Mo + ts.bm - 1) / ts.bm);
-    wg.push_back(p);
-  };
+  // weight-gradient products (sum over rows), one table per tile shape
   const void* dz_op = bf16 ? (const void*)dz16 : (const void*)dz32;
   const void* hN_op = bf16 ? (const void*)HN16 : (const void*)Hs[N];
-  addw(dz_op, hN_op, G_("wh"), 256, F);
-  for (int j = 0; j < N; ++j) {
-    const std::string b = "blk" + std::to_string(j);
-    addw(bf16 ? (const void*)dH16[j + 1] : (const void*)dH32[j + 1],
-         bf16 ? (const void*)G16[j] : (const void*)G32[j], G_(b + ".wo"), F, H);
-    addw(bf16 ? (const void*)dA16[j] : (const void*)dA32[j],
-         bf16 ? (const void*)Z16[j] : (const void*)Z32[j], G_(b + ".w0"), K * H, F);
+  for (int tile = 0; tile < TILE_COUNT; ++tile) {
+    std::vector<WgradProblem> wg;
+    const TileShape ts = tile_shape(tile);
+    int tiles = 0;
+    auto addw = [&](const void* dout, const void* in, float* dw, int Mo, int Ni) {
+      WgradProblem p;
+      p.dout = dout;
+      p.in = in;
+      p.dw = dw;
+      p.M = Mo;
+      p.N = Ni;
+      p.tiles_n = (Ni + ts.bn - 1) / ts.bn;
+      p.tile_begin = tiles;
+      tiles += p.tiles_n * ((Mo + ts.bm - 1) / ts.bm);
+      wg.push_back(p);
+    };
+    addw(dz_op, hN_op, G_("wh"), 256, F);
+    for (int j = 0; j < N; ++j) {
+      const std::string b = "blk" + std::to_string(j);
+      addw(bf16 ? (const void*)dH16[j + 1] : (const void*)dH32[j + 1],
+           bf16 ? (const void*)G16[j] : (const void*)G32[j], G_(b + ".wo"), F, H);
+      addw(bf16 ? (const void*)dA16[j] : (const void*)dA32[j],
+           bf16 ? (const void*)Z16[j] : (const void*)Z32[j], G_(b + ".w0"), K * H, F);
+    }
+    addw(bf16 ? (const void*)dH16[0] : (const void*)dH32[0],
+         bf16 ? (const void*)Y16 : (const void*)Y32, G_("w2"), F, L);
+    addw(bf16 ? (const void*)dX1_16 : (const void*)dX1_32,
+         bf16 ? (const void*)X16 : (const void*)X32, G_("w1"), L, F);
+    WgTable& t = wg_tab[tile];
+    t.n = (int)wg.size();
+    t.tiles = tiles;
+    t.d = dalloc<WgradProblem>(wg.size());
+    hip_check(hipMemcpyAsync(t.d, wg.data(), wg.size() * sizeof(WgradProblem),
+                             hipMemcpyHostToDevice, s), "copy");
   }
-  addw(bf16 ? (const void*)dH16[0] : (const void*)dH32[0], bf16 ? (const void*)Y16 : (const void*)Y32,
-       G_("w2"), F, L);
-  addw(bf16 ? (const void*)dX1_16 : (const void*)dX1_32, bf16 ? (const void*)X16 : (const void*)X32,
-       G_("w1"), L, F);
-  n_wg = (int)wg.size();
-  d_wg = dalloc<WgradProblem>(wg.size());
-  hip_check(hipMemcpyAsync(d_wg, wg.data(), wg.size() * sizeof(WgradProblem), hipMemcpyHostToDevice, s),
-            "copy");
 
   // column sums: bias gradients, LayerNorm affine gradients
   std::vector<ColsumJob> cs;
@@ -308,6 +342,8 @@ void Model::build_tables(hipStream_t s) {
     j.cols = cols;
     j.ld = ld;
     j.col_block_begin = cs_blocks;
+    j.col_offset = cs_cols;
+    cs_cols += cols;
     j.scale = 1.0f;
     cs_blocks += (cols + 63) / 64;
     cs.push_back(j);
@@ -324,6 +360,7 @@ void Model::build_tables(hipStream_t s) {
   addc(dX1_32, L, L, G_("b1"), nullptr, nullptr, nullptr);
   n_cs = (int)cs.size();
   d_cs = dalloc<ColsumJob>(cs.size());
+  cs_partial = dalloc<float>(colsum_partial_elems((int)max_rows, cs_cols));
   hip_check(hipMemcpyAsync(d_cs, cs.data(), cs.size() * sizeof(ColsumJob), hipMemcpyHostToDevice, s),
             "copy");
   ColsumJob lj;
@@ -334,7 +371,9 @@ void Model::build_tables(hipStream_t s) {
   lj.cols = 1;
   lj.ld = 1;
   lj.col_block_begin = 0;
+  lj.col_offset = 0;
   lj.scale = 0.0f;  // scale by 1/rows
+  loss_partial = dalloc<float>(colsum_partial_elems((int)max_rows, 1));
   d_loss_job = dalloc<ColsumJob>(1);
   hip_check(hipMemcpyAsync(d_loss_job, &lj, sizeof(lj), hipMemcpyHostToDevice, s), "copy");
   hip_check(hipStreamSynchronize(s), "sync");
@@ -352,58 +391,91 @@ static GemmArgs ga() {
   return g;
 }
 
+// One dense product of the step; j = block index where it applies.
+void Model::product(int ps, int j, int R, hipStream_t s) {
+  const std::string b = "blk" + std::to_string(j);
+  GemmArgs g = ga();
+  g.M = R;
+  g.m_rows = 1;
+  switch (ps) {
+    case PS_LTE_DOWN:  // Eq. 14
+      g.A = bf16 ? (const void*)X16 : (const void*)X32; g.lda = F; g.B = W_("w1"); g.ldb = F;
+      g.N = L; g.K = F; g.bias = P_("b1"); g.out32 = X1; g.ld_out32 = L;
+      return gemm(ps, true, true, EPI_STORE, 1, g, R, s);
+    case PS_LTE_UP:  // Eq. 16
+      g.A = bf16 ? (const void*)Y16 : (const void*)Y32; g.lda = L; g.B = W_("w2"); g.ldb = L;
+      g.N = F; g.K = L; g.bias = P_("b2"); g.out32 = Hs[0]; g.ld_out32 = F;
+      if (N == 0 && bf16) { g.out16 = HN16; g.ld_out16 = F; }
+      return gemm(ps, true, true, EPI_STORE, 1, g, R, s);
+    case PS_GATE:  // Eqs. 10-12: k branch products sharing the LayerNorm output
+      g.A = bf16 ? (const void*)Z16[j] : (const void*)Z32[j]; g.lda = F;
+      g.B = W_(b + ".w0"); g.ldb = F; g.b_branch_stride = (long long)H * F;
+      g.N = H; g.K = F; g.bias = P_(b + ".b0"); g.bias_branch_stride = H;
+      g.aux = Abr[j]; g.ld_aux = K * H; g.aux_branch = H;
+      if (bf16) { g.out16 = G16[j]; g.ld_out16 = H; } else { g.out32 = G32[j]; g.ld_out32 = H; }
+      return gemm(ps, true, true, EPI_GATE_FWD, K, g, R, s);
+    case PS_OUT:  // Eq. 13: output linear + residual
+      g.A = bf16 ? (const void*)G16[j] : (const void*)G32[j]; g.lda = H;
+      g.B = W_(b + ".wo"); g.ldb = H; g.N = F; g.K = H;
+      g.bias = P_(b + ".bo"); g.resid = Hs[j]; g.ld_resid = F;
+      g.out32 = Hs[j + 1]; g.ld_out32 = F;
+      if (j == N - 1 && bf16) { g.out16 = HN16; g.ld_out16 = F; }
+      return gemm(ps, true, true, EPI_STORE, 1, g, R, s);
+    case PS_HEAD:
+      g.A = bf16 ? (const void*)HN16 : (const void*)Hs[N]; g.lda = F; g.B = W_("wh"); g.ldb = F;
+      g.N = 256; g.K = F; g.bias = P_("bh"); g.out32 = logits; g.ld_out32 = 256;
+      return gemm(ps, true, true, EPI_STORE, 1, g, R, s);
+    case PS_HEAD_BWD:
+      g.A = bf16 ? (const void*)dz16 : (const void*)dz32; g.lda = 256; g.B = W_("wh"); g.ldb = F;
+      g.N = F; g.K = 256; g.out32 = dH32[N]; g.ld_out32 = F;
+      if (bf16) { g.out16 = dH16[N]; g.ld_out16 = F; }
+      return gemm(ps, true, false, EPI_STORE, 1, g, R, s);
+    case PS_GATE_BWD:  // dX_ff = dH Wo, then dX_i through GeLU and the product
+      g.A = bf16 ? (const void*)dH16[j + 1] : (const void*)dH32[j + 1]; g.lda = F;
+      g.B = W_(b + ".wo"); g.ldb = H; g.N = H; g.K = F;
+      g.aux = Abr[j]; g.ld_aux = K * H; g.aux_branch = H; g.bias_branch_stride = K;
+      g.out32 = dA32[j]; g.ld_out32 = K * H;
+      if (bf16) { g.out16 = dA16[j]; g.ld_out16 = K * H; }
+      return gemm(ps, true, false, EPI_GATE_BWD, 1, g, R, s);
+    case PS_DZ:  // dX0 = sum_i dX_i W_i
+      g.A = bf16 ? (const void*)dA16[j] : (const void*)dA32[j]; g.lda = K * H;
+      g.B = W_(b + ".w0"); g.ldb = F; g.N = F; g.K = K * H;
+      g.out32 = dZ[j]; g.ld_out32 = F;
+      return gemm(ps, true, false, EPI_STORE, 1, g, R, s);
+    case PS_LTE_UP_BWD:
+      g.A = bf16 ? (const void*)dH16[0] : (const void*)dH32[0]; g.lda = F;
+      g.B = W_("w2"); g.ldb = L; g.N = L; g.K = F; g.out32 = dY; g.ld_out32 = L;
+      return gemm(ps, true, false, EPI_STORE, 1, g, R, s);
+    case PS_LTE_DOWN_BWD:
+      g.A = bf16 ? (const void*)dX1_16 : (const void*)dX1_32; g.lda = L;
+      g.B = W_("w1"); g.ldb = F; g.N = F; g.K = L; g.out32 = dX; g.ld_out32 = F;
+      return gemm(ps, true, false, EPI_STORE, 1, g, R, s);
+    case PS_WGRAD: {
+      const WgTable& t = wg_tab[kc.tile[PS_WGRAD]];
+      TIMED(PS_WGRAD, hip_check(launch_wgrad(kc.tile[PS_WGRAD], bf16, t.d, t.n, t.tiles, st, s),
+                                "wgrad launch"));
+      return;
+    }
+  }
+}
+
 void Model::step(StepMode mode, const StreamIO& io, const StepOutputs& out, int grid_rows,
                  hipStream_t s) {
   const int R = grid_rows;
-  const void* X_op = bf16 ? (const void*)X16 : (const void*)X32;
-  // ---- forward -----------------------------------------------------------
+  // ---- forward: Eq. 1 through Eqs. 14-16 and 9-13 -------------------------
   TIMED(KC_EMBED, k_embed(st, ctx, P_("emb"), C, E, X32, X16, R, s));
-  {  // LTE down-projection (Eq. 14)
-    GemmArgs g = ga();
-    g.A = X_op; g.lda = F; g.B = W_("w1"); g.ldb = F;
-    g.M = R; g.m_rows = 1; g.N = L; g.K = F;
-    g.bias = P_("b1"); g.out32 = X1; g.ld_out32 = L;
-    gemm(PS_LTE_DOWN, true, true, EPI_STORE, 1, g, R, s);
-  }
+  product(PS_LTE_DOWN, 0, R, s);
   TIMED(KC_FDM_FWD, k_fdm_fwd(st, X1, U, slot, L, Y32, Y16, R, s));  // Eq. 15
-  {  // LTE up-projection (Eq. 16)
-    GemmArgs g = ga();
-    g.A = bf16 ? (const void*)Y16 : (const void*)Y32; g.lda = L; g.B = W_("w2"); g.ldb = L;
-    g.M = R; g.m_rows = 1; g.N = F; g.K = L;
-    g.bias = P_("b2"); g.out32 = Hs[0]; g.ld_out32 = F;
-    if (N == 0 && bf16) { g.out16 = HN16; g.ld_out16 = F; }
-    gemm(PS_LTE_UP, true, true, EPI_STORE, 1, g, R, s);
-  }
-  for (int j = 0; j < N; ++j) {  // refinement blocks (Eqs. 9-13)
-    const std::string b = "blk" + std::to_string(j), ln = "ln" + std::to_string(j);
+  product(PS_LTE_UP, 0, R, s);
+  for (int j = 0; j < N; ++j) {
+    const std::string ln = "ln" + std::to_string(j);
     TIMED(KC_LN_FWD, k_ln_fwd(st, Hs[j], P_(ln + ".gamma"), P_(ln + ".beta"), F,
                               bf16 ? nullptr : Z32[j], bf16 ? Z16[j] : nullptr, mean[j],
                               rstd[j], R, s));
-    GemmArgs g = ga();
-    g.A = bf16 ? (const void*)Z16[j] : (const void*)Z32[j]; g.lda = F;
-    g.B = W_(b + ".w0"); g.ldb = F; g.b_branch_stride = (long long)H * F;
-    g.M = R; g.m_rows = 1; g.N = H; g.K = F;
-    g.bias = P_(b + ".b0"); g.bias_branch_stride = H;
-    g.aux = Abr[j]; g.ld_aux = K * H; g.aux_branch = H;
-    if (bf16) { g.out16 = G16[j]; g.ld_out16 = H; } else { g.out32 = G32[j]; g.ld_out32 = H; }
-    gemm(PS_GATE, true, true, EPI_GATE_FWD, K, g, R, s);
-    GemmArgs o = ga();
-    o.A = bf16 ? (const void*)G16[j] : (const void*)G32[j]; o.lda = H;
-    o.B = W_(b + ".wo"); o.ldb = H;
-    o.M = R; o.m_rows = 1; o.N = F; o.K = H;
-    o.bias = P_(b + ".bo"); o.resid = Hs[j]; o.ld_resid = F;
-    o.out32 = Hs[j + 1]; o.ld_out32 = F;
-    if (j == N - 1 && bf16) { o.out16 = HN16; o.ld_out16 = F; }
-    gemm(PS_OUT, true, true, EPI_STORE, 1, o, R, s);
+    product(PS_GATE, j, R, s);
+    product(PS_OUT, j, R, s);
   }
-  const void* HN_op = bf16 ? (const void*)HN16 : (const void*)Hs[N];
-  {  // head logits
-    GemmArgs g = ga();
-    g.A = HN_op; g.lda = F; g.B = W_("wh"); g.ldb = F;
-    g.M = R; g.m_rows = 1; g.N = 256; g.K = F;
-    g.bias = P_("bh"); g.out32 = logits; g.ld_out32 = 256;
-    gemm(PS_HEAD, true, true, EPI_STORE, 1, g, R, s);
-  }
+  product(PS_HEAD, 0, R, s);
   const bool backward = out.backward || out.update || out.keep_fdm_grad;
   HeadArgs ha;
   std::memset(&ha, 0, sizeof(ha));
@@ -421,65 +493,67 @@ void Model::step(StepMode mode, const StreamIO& io, const StepOutputs& out, int 
   if (mode == MODE_PLAIN) hio.slot = nullptr;
   TIMED(KC_HEAD, k_head(st, ha, hio, R, s));
   if (out.loss) {
-    TIMED(KC_COLSUM, k_colsum(st, d_loss_job, 1, 1, s));
+    TIMED(KC_COLSUM, k_colsum(st, d_loss_job, 1, 1, 1, loss_partial, R, s));
     hip_check(hipMemcpyAsync(out.loss, loss_out, sizeof(float), hipMemcpyDeviceToDevice, s), "copy");
   }
   if (!backward) return;
 
-  // ---- adjoint of the mean cross entropy ---------------------------------
-  {
-    GemmArgs g = ga();
-    g.A = bf16 ? (const void*)dz16 : (const void*)dz32; g.lda = 256; g.B = W_("wh"); g.ldb = F;
-    g.M = R; g.m_rows = 1; g.N = F; g.K = 256;
-    g.out32 = dH32[N]; g.ld_out32 = F;
-    if (bf16) { g.out16 = dH16[N]; g.ld_out16 = F; }
-    gemm(PS_HEAD_BWD, true, false, EPI_STORE, 1, g, R, s);
-  }
+  // ---- adjoint of the mean cross entropy (Eq. 2) -------------------------
+  product(PS_HEAD_BWD, 0, R, s);
   for (int j = N - 1; j >= 0; --j) {
-    const std::string b = "blk" + std::to_string(j), ln = "ln" + std::to_string(j);
-    GemmArgs g = ga();  // dX_ff = dH Wo, then dX_i through GeLU and the product
-    g.A = bf16 ? (const void*)dH16[j + 1] : (const void*)dH32[j + 1]; g.lda = F;
-    g.B = W_(b + ".wo"); g.ldb = H;
-    g.M = R; g.m_rows = 1; g.N = H; g.K = F;
-    g.aux = Abr[j]; g.ld_aux = K * H; g.aux_branch = H; g.bias_branch_stride = K;
-    g.out32 = dA32[j]; g.ld_out32 = K * H;
-    if (bf16) { g.out16 = dA16[j]; g.ld_out16 = K * H; }
-    gemm(PS_GATE_BWD, true, false, EPI_GATE_BWD, 1, g, R, s);
-    GemmArgs z = ga();  // dX0 = sum_i dX_i W_i
-    z.A = bf16 ? (const void*)dA16[j] : (const void*)dA32[j]; z.lda = K * H;
-    z.B = W_(b + ".w0"); z.ldb = F;
-    z.M = R; z.m_rows = 1; z.N = F; z.K = K * H;
-    z.out32 = dZ[j]; z.ld_out32 = F;
-    gemm(PS_DZ, true, false, EPI_STORE, 1, z, R, s);
+    const std::string ln = "ln" + std::to_string(j);
+    product(PS_GATE_BWD, j, R, s);
+    product(PS_DZ, j, R, s);
     TIMED(KC_LN_BWD, k_ln_bwd(st, Hs[j], mean[j], rstd[j], P_(ln + ".gamma"), dZ[j],
                               dH32[j + 1], F, dH32[j], bf16 ? dH16[j] : nullptr, R, s));
   }
-  {  // adjoint of Eq. 16
-    GemmArgs g = ga();
-    g.A = bf16 ? (const void*)dH16[0] : (const void*)dH32[0]; g.lda = F;
-    g.B = W_("w2"); g.ldb = L;
-    g.M = R; g.m_rows = 1; g.N = L; g.K = F;
-    g.out32 = dY; g.ld_out32 = L;
-    gemm(PS_LTE_UP_BWD, true, false, EPI_STORE, 1, g, R, s);
-  }
+  product(PS_LTE_UP_BWD, 0, R, s);
   AdamCfg ac{cfg.lr, cfg.beta1, cfg.beta2, cfg.eps};
-  // adjoint of Eq. 15 (+ Adam on U_s)
+  // adjoint of Eq. 15, fused with Adam on U_s
   TIMED(KC_FDM_BWD, k_fdm_bwd(st, X1, dY, U, mU, vU, out.keep_fdm_grad ? dUkeep : nullptr, slot,
                               L, ac, out.update, dX1_32, dX1_16, R, s));
-  {  // adjoint of Eq. 14 down to the embedding
-    GemmArgs g = ga();
-    g.A = bf16 ? (const void*)dX1_16 : (const void*)dX1_32; g.lda = L;
-    g.B = W_("w1"); g.ldb = F;
-    g.M = R; g.m_rows = 1; g.N = F; g.K = L;
-    g.out32 = dX; g.ld_out32 = F;
-    gemm(PS_LTE_DOWN_BWD, true, false, EPI_STORE, 1, g, R, s);
-  }
-  TIMED(KC_EMB_GRAD, k_emb_grad(st, ctx, dX, C, E, emb_partial, emb_chunk, R, G_("emb"), s));
-  TIMED(PS_WGRAD, hip_check(launch_wgrad(kc.tile[PS_WGRAD], bf16, d_wg, n_wg, wg_tiles, st, s),
-                            "wgrad launch"));
-  TIMED(KC_COLSUM, k_colsum(st, d_cs, n_cs, cs_blocks, s));
+  product(PS_LTE_DOWN_BWD, 0, R, s);
+  TIMED(KC_EMB_GRAD, k_emb_grad(st, ctx, dX, C, E, emb_partial, emb_chunk, emb_sub, R, G_("emb"), s));
+  product(PS_WGRAD, 0, R, s);
+  TIMED(KC_COLSUM, k_colsum(st, d_cs, n_cs, cs_blocks, cs_cols, cs_partial, R, s));
   if (out.update) TIMED(KC_ADAM, k_adam(st, param, grad, m, v, p16, P, ac, s));
   hip_check(hipGetLastError(), "step launch");
+}
+
+// Time every tile configuration of every product on the model's own buffers
+// (rows = max_rows) and keep the fastest.  Outputs of the trial launches are
+// scratch: every buffer they write is rewritten by the first real step.
+void Model::autotune(hipStream_t s) {
+  const int R = (int)max_rows;
+  k_step_explicit(st, R, 1, cfg.beta1, cfg.beta2, s);
+  hipEvent_t e0, e1;
+  hip_check(hipEventCreate(&e0), "event");
+  hip_check(hipEventCreate(&e1), "event");
+  KTimer* saved = timer;
+  timer = nullptr;
+  for (int ps = 0; ps < PS_COUNT; ++ps) {
+    const bool per_block = ps == PS_GATE || ps == PS_OUT || ps == PS_GATE_BWD || ps == PS_DZ;
+    if (per_block && N == 0) continue;
+    int best = kc.tile[ps];
+    float best_ms = 1e30f;
+    for (int t = 0; t < TILE_COUNT; ++t) {
+      const TileShape sh = tile_shape(t);
+      if (ps != PS_WGRAD && sh.bm > 2 * R && t != TILE_32x32) continue;
+      kc.tile[ps] = t;
+      product(ps, 0, R, s);  // warm-up (first launch may set attributes)
+      hip_check(hipEventRecord(e0, s), "event");
+      for (int rep = 0; rep < 3; ++rep) product(ps, 0, R, s);
+      hip_check(hipEventRecord(e1, s), "event");
+      hip_check(hipEventSynchronize(e1), "event");
+      float ms = 0.f;
+      hip_check(hipEventElapsedTime(&ms, e0, e1), "event");
+      if (ms < best_ms) { best_ms = ms; best = t; }
+    }
+    kc.tile[ps] = best;
+  }
+  timer = saved;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
 }
 
 }  // namespace edpc

@@ -21,7 +21,8 @@ def lib_cfg(E, model: dict, precision: str = "fp32", **over):
     d.update(over)
     kw = {k: d[k] for k in ("context", "embed", "latent", "blocks", "hidden", "branches", "lr",
                             "beta1", "beta2", "eps", "seed") if k in d}
-    return E.edpc_config_default(precision=precision, zero_head=d.get("zero_head", False), **kw)
+    return E.edpc_config_default(precision=precision, zero_head=d.get("zero_head", False),
+                                 autotune=d.get("autotune", False), **kw)
 
 
 def oracle_cfg(model: dict, **over) -> Config:

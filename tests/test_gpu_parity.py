@@ -293,3 +293,43 @@ def test_decoder_rejects_corruption(E):
     with pytest.raises(E.EdpcError) as ei:
         E.edpc_decode(cont[:-10])
     assert ei.value.status == -4
+
+
+def test_autotuned_encode_roundtrip(E):
+    data, lens = gen.make_streams("small", prefix=120, n_streams=8)
+    cfg = lib_cfg(E, SMALL, autotune=True)
+    cont = _encode(E, cfg, data, lens)
+    kid = int.from_bytes(cont[76:84].cpu().numpy().tobytes(), "little")
+    assert kid >> 48 == 1
+    out, _ = E.edpc_decode(cont)
+    assert out.cpu().numpy().tobytes() == data.tobytes()
+
+
+def test_bf16_roundtrip_and_size_vs_fp32(E):
+    data, lens = gen.make_streams("small", prefix=1024)
+    c32 = _encode(E, lib_cfg(E, SMALL), data, lens)
+    c16 = _encode(E, lib_cfg(E, SMALL, "bf16"), data, lens)
+    out, _ = E.edpc_decode(c16)
+    assert out.cpu().numpy().tobytes() == data.tobytes()
+    assert abs(c16.numel() - c32.numel()) / c32.numel() <= 0.005
+
+
+def test_graph_replay_matches_direct_launches(E, monkeypatch):
+    # same input through captured step windows and through direct launches:
+    # identical containers, and each decodes in the other mode
+    data, lens = gen.make_streams("small", prefix=400, n_streams=8)
+    lens = np.array([400, 400, 399, 250, 130, 129, 64, 17])
+    st = split_streams(data, [400] * 8)
+    flat = np.frombuffer(b"".join(s[:l] for s, l in zip(st, lens)), dtype=np.uint8)
+    cfg = lib_cfg(E, SMALL)
+    monkeypatch.setenv("EDPC_GRAPH_STEPS", "0")
+    direct = _encode(E, cfg, flat, lens)
+    monkeypatch.setenv("EDPC_GRAPH_STEPS", "16")
+    graph = _encode(E, cfg, flat, lens)
+    graph2 = _encode(E, cfg, flat, lens)
+    assert torch.equal(direct, graph) and torch.equal(graph, graph2)
+    out, _ = E.edpc_decode(direct)
+    assert out.cpu().numpy().tobytes() == flat.tobytes()
+    monkeypatch.setenv("EDPC_GRAPH_STEPS", "0")
+    out, _ = E.edpc_decode(graph)
+    assert out.cpu().numpy().tobytes() == flat.tobytes()
