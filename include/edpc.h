@@ -201,6 +201,12 @@ edpc_status edpc_model_read(const edpc_model* m, uint32_t kind, size_t idx,
                             float* h_dst, size_t numel);
 edpc_status edpc_model_write(edpc_model* m, uint32_t kind, size_t idx,
                              const float* h_src, size_t numel);
+/* The same transfers between a model tensor and caller device memory,
+ * asynchronous on `stream` (for autograd wrappers and zero-copy callers). */
+edpc_status edpc_model_read_device(const edpc_model* m, uint32_t kind, size_t idx,
+                                   float* d_dst, size_t numel, void* stream);
+edpc_status edpc_model_write_device(edpc_model* m, uint32_t kind, size_t idx,
+                                    const float* d_src, size_t numel, void* stream);
 /* Adam step counter (number of updates taken). */
 edpc_status edpc_model_get_step(const edpc_model* m, uint64_t* tau);
 edpc_status edpc_model_set_step(edpc_model* m, uint64_t tau);

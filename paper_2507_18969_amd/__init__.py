@@ -36,6 +36,7 @@ EXPORTS = [
     "edpc_session_progress", "edpc_encoder_finish", "edpc_decoder_finish",
     "edpc_session_destroy", "edpc_session_time_kernels", "edpc_kclass_name", "edpc_model_create", "edpc_model_destroy", "edpc_model_step",
     "edpc_model_tensor_count", "edpc_model_tensor_info", "edpc_model_read", "edpc_model_write",
+    "edpc_model_read_device", "edpc_model_write_device",
     "edpc_model_get_step", "edpc_model_set_step", "edpc_rc_encode", "edpc_rc_decode",
     "edpc_rc_encode_host", "edpc_rc_decode_host",
 ]
@@ -103,6 +104,8 @@ def lib() -> ctypes.CDLL:
         "edpc_model_tensor_info": (ctypes.c_int, [_P, _SZ, ctypes.c_char_p, _SZ, _SZP]),
         "edpc_model_read": (ctypes.c_int, [_P, ctypes.c_uint32, _SZ, _P, _SZ]),
         "edpc_model_write": (ctypes.c_int, [_P, ctypes.c_uint32, _SZ, _P, _SZ]),
+        "edpc_model_read_device": (ctypes.c_int, [_P, ctypes.c_uint32, _SZ, _P, _SZ, _P]),
+        "edpc_model_write_device": (ctypes.c_int, [_P, ctypes.c_uint32, _SZ, _P, _SZ, _P]),
         "edpc_model_get_step": (ctypes.c_int, [_P, _U64P]),
         "edpc_model_set_step": (ctypes.c_int, [_P, ctypes.c_uint64]),
         "edpc_rc_encode": (ctypes.c_int, [_P, _P, _SZ, _SZ, _P, _SZ, _U32P, _P]),
@@ -331,6 +334,17 @@ class Model:
         a = np.ascontiguousarray(np.asarray(values, dtype=np.float32).reshape(-1))
         _check(lib().edpc_model_write(self.h, kind, i, _np_ptr(a), a.size))
 
+    def edpc_model_read_device(self, name: str, out, kind: int = EDPC_KIND_PARAM, stream=None):
+        i = self.index(name)
+        _check(lib().edpc_model_read_device(self.h, kind, i, _dptr(out), out.numel(),
+                                            _stream(stream)))
+        return out
+
+    def edpc_model_write_device(self, name: str, src, kind: int = EDPC_KIND_PARAM, stream=None):
+        i = self.index(name)
+        _check(lib().edpc_model_write_device(self.h, kind, i, _dptr(src), src.numel(),
+                                             _stream(stream)))
+
     def edpc_model_get_step(self) -> int:
         t = ctypes.c_uint64()
         _check(lib().edpc_model_get_step(self.h, ctypes.byref(t)))
@@ -385,3 +399,47 @@ def edpc_rc_decode_host(cum: np.ndarray, payload: bytes, n_steps: int) -> np.nda
     _check(lib().edpc_rc_decode_host(_np_ptr(cum), _np_ptr(buf), len(payload), n_steps,
                                      _np_ptr(sym)))
     return sym[:n_steps]
+
+
+def _step_function():
+    import torch
+
+    class StepFunction(torch.autograd.Function):
+        """Mean cross entropy of one model step (Eq. 2) as an autograd op.
+
+        ``StepFunction.apply(model, ctx, target, slots, *tensors)`` where
+        ``tensors`` are FP32 device tensors holding every model tensor in
+        ``model.names`` order (the FDM "U" last, all slots).  Forward loads
+        them into the model and runs the forward kernels; backward runs the
+        library's hand-written adjoint kernels (no update) and returns their
+        gradients scaled by the incoming gradient.
+        """
+
+        @staticmethod
+        def forward(fctx, model, d_ctx, d_tgt, slots, *tensors):
+            for name, t in zip(model.names, tensors):
+                model.edpc_model_write_device(name, t.detach().contiguous())
+            loss = torch.empty(1, dtype=torch.float32, device=d_ctx.device)
+            model.edpc_model_step(d_ctx, d_tgt, slots, loss=loss,
+                                  flags=EDPC_STEP_BACKWARD | EDPC_STEP_KEEP_FDM_GRAD)
+            fctx.model = model
+            fctx.shapes = [t.shape for t in tensors]
+            return loss[0]
+
+        @staticmethod
+        def backward(fctx, g):
+            m = fctx.model
+            grads = []
+            for name, shp in zip(m.names, fctx.shapes):
+                out = torch.empty(shp, dtype=torch.float32, device=g.device)
+                m.edpc_model_read_device(name, out, kind=EDPC_KIND_GRAD)
+                grads.append(out * g)
+            return (None, None, None, None, *grads)
+
+    return StepFunction
+
+
+def __getattr__(name):
+    if name == "StepFunction":
+        return _step_function()
+    raise AttributeError(name)

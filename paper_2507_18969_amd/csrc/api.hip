@@ -295,8 +295,9 @@ edpc_status edpc_model_step(edpc_model* mh, const uint8_t* d_ctx, const uint8_t*
       hip_check(hipMalloc(&p, m.n_slots * (size_t)m.L * m.L * sizeof(float)), "hipMalloc");
       m.allocs.push_back(p);
       m.dUkeep = (float*)p;
-      hip_check(hipMemsetAsync(m.dUkeep, 0, m.n_slots * (size_t)m.L * m.L * sizeof(float), s), "memset");
     }
+    if (out.keep_fdm_grad)  // slots outside this call get a zero gradient
+      hip_check(hipMemsetAsync(m.dUkeep, 0, m.n_slots * (size_t)m.L * m.L * sizeof(float), s), "memset");
     const uint32_t tau = out.update ? (uint32_t)(m.tau + 1) : (uint32_t)(m.tau > 0 ? m.tau : 1);
     k_step_explicit(m.st, (int)rows, tau, m.cfg.beta1, m.cfg.beta2, s);
     StreamIO io;
@@ -389,6 +390,35 @@ edpc_status edpc_model_write(edpc_model* mh, uint32_t kind, size_t idx, const fl
       const TensorInfo& t = m.tens[idx];
       k_to_bf16(m.param + t.off, m.p16 + t.off, t.numel, nullptr);
       hip_check(hipDeviceSynchronize(), "sync");
+    }
+    return EDPC_OK;
+  });
+}
+
+edpc_status edpc_model_read_device(const edpc_model* mh, uint32_t kind, size_t idx, float* d_dst,
+                                   size_t numel, void* stream) {
+  return guarded([&] {
+    if (!mh || !d_dst) fail(EDPC_E_INVALID_ARG, "NULL argument");
+    size_t ne = 0;
+    float* p = tensor_ptr(*mh->m, kind, idx, &ne, false);
+    if (numel != ne) fail(EDPC_E_INVALID_ARG, "numel mismatch");
+    hip_check(hipMemcpyAsync(d_dst, p, ne * sizeof(float), hipMemcpyDeviceToDevice, S(stream)), "copy");
+    return EDPC_OK;
+  });
+}
+
+edpc_status edpc_model_write_device(edpc_model* mh, uint32_t kind, size_t idx, const float* d_src,
+                                    size_t numel, void* stream) {
+  return guarded([&] {
+    if (!mh || !d_src) fail(EDPC_E_INVALID_ARG, "NULL argument");
+    Model& m = *mh->m;
+    size_t ne = 0;
+    float* p = tensor_ptr(m, kind, idx, &ne, true);
+    if (numel != ne) fail(EDPC_E_INVALID_ARG, "numel mismatch");
+    hip_check(hipMemcpyAsync(p, d_src, ne * sizeof(float), hipMemcpyDeviceToDevice, S(stream)), "copy");
+    if (kind == EDPC_KIND_PARAM && m.bf16 && idx < m.tens.size()) {
+      const TensorInfo& t = m.tens[idx];
+      k_to_bf16(m.param + t.off, m.p16 + t.off, t.numel, S(stream));
     }
     return EDPC_OK;
   });

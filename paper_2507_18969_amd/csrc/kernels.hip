@@ -540,6 +540,22 @@ void k_head(const StepState* st, HeadArgs a, StreamIO io, int max_rows, hipStrea
 // ---------------------------------------------------------------------------
 constexpr int kColChunk = 64;
 
+// p[0] + p[stride] + ... + p[(n-1) stride], added strictly in index order;
+// the loads are issued 16 at a time so their latencies overlap.
+__device__ __forceinline__ float ordered_sum(const float* __restrict__ p, size_t stride, int n) {
+  float s = 0.f;
+  int k = 0;
+  for (; k + 16 <= n; k += 16) {
+    float v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v[q] = p[(size_t)(k + q) * stride];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) s += v[q];
+  }
+  for (; k < n; ++k) s += p[(size_t)k * stride];
+  return s;
+}
+
 __global__ void __launch_bounds__(256) colsum_partial_kernel(const StepState* __restrict__ st,
                                                              const ColsumJob* __restrict__ jobs,
                                                              int n_jobs, int total_cols,
@@ -585,8 +601,7 @@ __global__ void colsum_reduce_kernel(const StepState* __restrict__ st,
   while (j + 1 < n_jobs && c >= jobs[j + 1].col_offset) ++j;
   const ColsumJob& jb = jobs[j];
   const int nch = (st->rows + kColChunk - 1) / kColChunk;
-  float s = 0.f;
-  for (int k = 0; k < nch; ++k) s += partial[(size_t)k * total_cols + c];
+  const float s = ordered_sum(partial + c, (size_t)total_cols, nch);
   jb.dst[c - jb.col_offset] = s * (jb.scale == 0.0f ? st->inv_rows : jb.scale);
 }
 
@@ -660,9 +675,7 @@ __global__ void emb_grad_reduce_kernel(const StepState* __restrict__ st,
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   const int nb = (st->rows + chunk_rows - 1) / chunk_rows;
-  float s = 0.f;
-  for (int b = 0; b < nb; ++b) s += partial[(size_t)b * n + k];
-  demb[k] = s;
+  demb[k] = ordered_sum(partial + k, (size_t)n, nb);
 }
 
 void emb_grad_plan(int max_rows, int C, int E, int* chunk_rows, int* sub_rows) {

@@ -9,7 +9,9 @@ Cases:
   small_full      the 8-stream x 8 KiB workload, every byte (8192 steps)
   small_zero_lr   the same input with lr = 0 (static random model), 2 KiB prefix
   mid_prefix      the 1024-stream x 64 KiB workload cut to its first 160 bytes
-  mid_bf16_slice  4 streams x 512 bytes of the mid workload
+  mid_slice       4 streams x 512 bytes of the mid workload
+  ragged_prefix   32 streams of the mixture source cut to seeded lengths in
+                  [100, 1500] (ragged), mid model
 """
 
 from __future__ import annotations
@@ -28,18 +30,34 @@ import oracle  # noqa: E402
 from oracle.codec import split_streams  # noqa: E402
 from oracle.model import Config  # noqa: E402
 
+def ragged_prefix_input():
+    """32 mixture streams cut to lengths drawn from a seeded generator."""
+    import numpy as np
+    data, lens = gen.make_streams("ragged", prefix=1500, n_streams=32)
+    cut = np.random.default_rng(2507).integers(100, 1501, size=32)
+    cut[0] = 1500
+    cut = np.minimum(cut, lens)
+    offs = np.concatenate([[0], np.cumsum(lens)])
+    parts = [data[offs[s]:offs[s] + cut[s]] for s in range(32)]
+    return np.concatenate(parts), cut.astype(np.int64)
+
+
 CASES = {
     "small_full": ("small", None, None, {}),
     "small_zero_lr": ("small", 2048, None, {"lr": 0.0}),
     "mid_prefix": ("mid_fp32", 160, None, {}),
     "mid_slice": ("mid_fp32", 512, 4, {}),
+    "ragged_prefix": ("ragged", "ragged_prefix", None, {}),
 }
 
 
 def run_case(name):
     wl, prefix, nst, over = CASES[name]
     w = gen.WORKLOADS[wl]
-    data, lens = gen.make_streams(w, prefix=prefix, n_streams=nst)
+    if prefix == "ragged_prefix":
+        data, lens = ragged_prefix_input()
+    else:
+        data, lens = gen.make_streams(w, prefix=prefix, n_streams=nst)
     cfg = Config.from_dict(w.model).with_(**over)
     t = time.time()
     pay, info = oracle.encode(split_streams(data, lens), cfg)

@@ -1,0 +1,91 @@
+"""Hand-written adjoint behind torch.autograd, against central finite
+differences of the FP64 oracle's loss, on a 4-stream x 512-byte slice of the
+1024-stream workload with its model, at a state reached after 256 online steps."""
+
+import numpy as np
+import pytest
+
+import gen
+from oracle.model import Model as OModel
+from tests.gpu_util import banner, lib_cfg, load_oracle_state, oracle_cfg
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+MID = gen.WORKLOADS["mid_fp32"].model
+ROWS, SLICE, ONLINE = 4, 512, 256
+
+
+@pytest.fixture(scope="module")
+def E():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2507_18969_amd as E
+    E.lib()
+    return E
+
+
+@pytest.fixture(scope="module")
+def state():
+    data, _ = gen.make_streams("mid_fp32", prefix=SLICE, n_streams=ROWS)
+    st = np.frombuffer(data.tobytes(), dtype=np.uint8).reshape(ROWS, SLICE)
+    C = MID["context"]
+    om = OModel(oracle_cfg(MID), ROWS)
+    slots = np.arange(ROWS)
+    for i in range(C, C + ONLINE):
+        om.step(st[:, i - C:i].astype(np.int64), st[:, i].astype(np.int64), slots)
+    om.round_to_f32()
+    pos = C + ONLINE
+    return om, st[:, pos - C:pos].copy(), st[:, pos].copy()
+
+
+def _fd(om, ctx, tgt, name, idx, eps=1e-3):
+    slots = np.arange(ROWS)
+    arr = om.U if name == "U" else om.p[name]
+    flat = arr.reshape(-1)
+    old = flat[idx]
+    flat[idx] = old + eps
+    lp = OModel.loss(om.forward(ctx, slots), tgt)
+    flat[idx] = old - eps
+    lm = OModel.loss(om.forward(ctx, slots), tgt)
+    flat[idx] = old
+    return (lp - lm) / (2 * eps)
+
+
+@pytest.mark.parametrize("precision,rtol", [("fp32", 1e-4), ("bf16", 3e-2)])
+def test_step_function_gradients_vs_finite_differences(E, state, precision, rtol):
+    banner(f"gradients {precision}")
+    om, ctx, tgt = state
+    m = E.Model(lib_cfg(E, MID, precision), ROWS, ROWS)
+    load_oracle_state(m, om)
+    tensors = []
+    for name, ne in zip(m.names, m.numel):
+        src = om.U if name == "U" else om.p[name]
+        tensors.append(torch.tensor(src.astype(np.float32).reshape(-1), device="cuda",
+                                    requires_grad=True))
+    d_ctx = torch.as_tensor(ctx).to("cuda")
+    d_tgt = torch.as_tensor(tgt).to("cuda")
+    loss = E.StepFunction.apply(m, d_ctx, d_tgt, np.arange(ROWS), *tensors)
+    (2.0 * loss).backward()  # the incoming gradient scales the adjoint
+    c = om.forward(ctx.astype(np.int64), np.arange(ROWS))
+    lt = 1e-4 if precision == "fp32" else 5e-3
+    assert abs(loss.item() - OModel.loss(c, tgt.astype(np.int64))) < lt
+    g_or, dU = om.backward(c, tgt.astype(np.int64))
+    r = np.random.default_rng(0)
+    ctx64, tgt64 = ctx.astype(np.int64), tgt.astype(np.int64)
+    for name, t in zip(m.names, tensors):
+        gg = t.grad.detach().cpu().numpy() / 2.0
+        if name != "U":
+            go = g_or[name].reshape(-1)
+        else:
+            go = np.zeros(om.U.size)
+            go[: dU.size] = dU.reshape(-1)  # slots 0..3 are rows 0..3
+        idx = r.choice(go.size, size=min(64, go.size), replace=False)
+        idx = np.union1d(idx, np.argsort(-np.abs(go))[:8])  # include the largest entries
+        fd = np.array([_fd(om, ctx64, tgt64, name, int(i)) for i in idx])
+        scale = np.abs(go).max() + 1e-12
+        # the oracle's adjoint against its own central differences
+        assert np.abs(fd - go[idx]).max() <= 1e-5 * scale + 1e-9, name
+        # the GPU adjoint against the finite differences
+        err = np.abs(gg[idx] - fd).max() / scale
+        assert err <= rtol, (name, err)

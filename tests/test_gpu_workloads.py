@@ -1,0 +1,86 @@
+"""GPU checks on the ragged (mixture, uneven streams) and large workloads."""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+import gen
+from oracle.model import Model as OModel
+from oracle.model import init_fdm, init_shared
+from tests.gpu_util import banner, lib_cfg, oracle_cfg, parse_container
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "oracle_sizes.json")
+MID = gen.WORKLOADS["ragged"].model
+LARGE = gen.WORKLOADS["large"].model
+
+
+@pytest.fixture(scope="module")
+def E():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2507_18969_amd as E
+    E.lib()
+    return E
+
+
+def _ragged_prefix_input():
+    from tests.golden.make_oracle_golden import ragged_prefix_input
+    return ragged_prefix_input()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_ragged_mixture_roundtrip_and_size(E, precision):
+    banner(f"ragged mixture {precision}")
+    data, lens = _ragged_prefix_input()
+    with open(GOLDEN) as f:
+        gold = json.load(f)["ragged_prefix"]
+    assert gold["lens"] == [int(x) for x in lens]
+    d = torch.as_tensor(data).to("cuda")
+    cont = E.edpc_encode(lib_cfg(E, MID, precision), d, lens)
+    out, _ = E.edpc_decode(cont)
+    assert torch.equal(out, d)
+    _, pays = parse_container(cont.cpu().numpy().tobytes())
+    g, o = sum(map(len, pays)), sum(gold["payload_bytes"])
+    assert abs(g - o) / o <= 0.005, (g, o)
+
+
+def test_large_first_step_sampled_rows_full_batch(E):
+    banner("large first step, 16384 rows")
+    rows = 16384
+    C = LARGE["context"]
+    data, _ = gen.make_streams("large", prefix=C + 1)
+    st = np.frombuffer(data.tobytes(), dtype=np.uint8).reshape(rows, -1)
+    m = E.Model(lib_cfg(E, LARGE, "bf16"), rows, rows)
+    probs = torch.empty((rows, 256), dtype=torch.float32, device="cuda")
+    m.edpc_model_step(torch.as_tensor(st[:, :C].copy()).to("cuda"),
+                      torch.as_tensor(st[:, C].copy()).to("cuda"), np.arange(rows), probs)
+    torch.cuda.synchronize()
+    pg = probs.cpu().numpy()
+    assert np.all(np.isfinite(pg)) and np.allclose(pg.sum(1), 1.0, atol=1e-4)
+    ocfg = oracle_cfg(LARGE)
+    shared = init_shared(ocfg)
+    for s in np.random.default_rng(5).choice(rows, size=6, replace=False):
+        om = OModel(ocfg, 1, shared=shared, fdm=init_fdm(ocfg, [s]))
+        c = om.forward(st[s:s + 1, :C].astype(np.int64), np.array([0]))
+        assert np.abs(pg[s] - c["p"][0]).max() <= 2e-3
+    del m
+
+
+def test_large_prefix_roundtrip_bf16_vs_fp32_size(E):
+    banner("large prefix encode/decode")
+    data, lens = gen.make_streams("large", prefix=160)
+    d = torch.as_tensor(data).to("cuda")
+    sizes = {}
+    for p in ("bf16", "fp32"):
+        cont = E.edpc_encode(lib_cfg(E, LARGE, p), d, lens)
+        out, _ = E.edpc_decode(cont)
+        assert torch.equal(out, d), p
+        sizes[p] = cont.numel()
+        del cont, out
+        torch.cuda.empty_cache()
+    assert abs(sizes["bf16"] - sizes["fp32"]) / sizes["fp32"] <= 0.005
