@@ -113,6 +113,34 @@ def full_job(torch, E, w, d_in, lens, precision):
                 bits_per_byte=8.0 * (cont.numel() - hdr) / n)
 
 
+def extra_workload(torch, E, name, warmup, steps):
+    """Encoder steady-state rate of another workload in its own precision.
+    Ragged: steps from the start of the model phase while all 4096 streams are
+    active (the shortest stream is > 1 KiB long), so the rate is of full-batch
+    steps; the tail with fewer active streams is slower per step but cheaper."""
+    import gen
+    w = gen.WORKLOADS[name]
+    C = w.model["context"]
+    prefix = C + warmup + steps + 8
+    log(f"{name}: generating input (prefix {prefix} bytes per stream)")
+    data, lens = gen.make_streams(w, prefix=prefix)
+    d_in = torch.as_tensor(data).to("cuda")
+    cfg = lib_cfg(E, w.model, w.precision)
+    enc = E.edpc_encoder_begin(cfg, d_in, lens)
+    done, ms, _ = time_session(torch, enc, warmup, steps)
+    kern = enc.edpc_session_time_kernels(4)
+    enc.edpc_session_destroy()
+    rows = int((lens > C + warmup).sum())
+    res = {"workload": w.description, "precision": w.precision, "streams": int(len(lens)),
+           "encode_MBps": round(done * rows / (ms * 1e-3) / 1e6, 4),
+           "ms_per_step": round(ms / done, 4), "steps": int(done)}
+    if "fdm_bwd_adam" in kern:
+        res["roofline_fdm_bwd_adam"] = fdm_roofline(w, kern, rows)
+    del d_in
+    torch.cuda.empty_cache()
+    return res
+
+
 def fdm_roofline(w, kern, rows):
     """FDM adjoint + Adam kernel: U, m, v read and written per step (24 B per
     element of the active streams' L x L slices) plus the x', dy rows read and
@@ -164,6 +192,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=16)
     ap.add_argument("--precisions", default="bf16,fp32")
+    ap.add_argument("--extra", default="",
+                    help="comma list of further workloads measured after the main one "
+                         "(ragged, large); reported under extra_workloads")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -203,6 +234,11 @@ def main():
     }
     if "bf16" in res and "fp32" in res:
         line["bf16_over_fp32_encode"] = round(res["bf16"]["encode"] / res["fp32"]["encode"], 3)
+    extra = {}
+    for name in [x for x in a.extra.split(",") if x]:
+        extra[name] = extra_workload(torch, E, name, a.warmup, min(a.steps, 200))
+    if extra:
+        line["extra_workloads"] = extra
     if a.full:
         line["full_job"] = {p: full_job(torch, E, w, d_in, lens, p) for p in res}
     if not a.no_cpu:

@@ -68,7 +68,7 @@ def test_step_function_gradients_vs_finite_differences(E, state, precision, rtol
     loss = E.StepFunction.apply(m, d_ctx, d_tgt, np.arange(ROWS), *tensors)
     (2.0 * loss).backward()  # the incoming gradient scales the adjoint
     c = om.forward(ctx.astype(np.int64), np.arange(ROWS))
-    lt = 1e-4 if precision == "fp32" else 5e-3
+    lt = 1e-4 if precision == "fp32" else 2e-2
     assert abs(loss.item() - OModel.loss(c, tgt.astype(np.int64))) < lt
     g_or, dU = om.backward(c, tgt.astype(np.int64))
     r = np.random.default_rng(0)
@@ -84,8 +84,11 @@ def test_step_function_gradients_vs_finite_differences(E, state, precision, rtol
         idx = np.union1d(idx, np.argsort(-np.abs(go))[:8])  # include the largest entries
         fd = np.array([_fd(om, ctx64, tgt64, name, int(i)) for i in idx])
         scale = np.abs(go).max() + 1e-12
-        # the oracle's adjoint against its own central differences
-        assert np.abs(fd - go[idx]).max() <= 1e-5 * scale + 1e-9, name
-        # the GPU adjoint against the finite differences
-        err = np.abs(gg[idx] - fd).max() / scale
+        # the oracle's adjoint against its own central differences (eps 1e-3:
+        # truncation error of order eps^2 times the third derivative)
+        fd_err = np.abs(fd - go[idx]).max() / scale
+        assert fd_err <= 1e-4, (name, fd_err)
+        # the GPU adjoint against the oracle's adjoint and the differences
+        err = np.abs(gg[idx] - go[idx]).max() / scale
         assert err <= rtol, (name, err)
+        assert np.abs(gg[idx] - fd).max() / scale <= rtol + fd_err, name
