@@ -156,7 +156,7 @@ void edpc_session_destroy(edpc_session* s);
  * session's stream, then synchronises: h_ms[c] receives the summed kernel
  * milliseconds and h_launches[c] the launch count of kernel class c, for
  * c < EDPC_KCLASS_COUNT.  The class names come from edpc_kclass_name. */
-#define EDPC_KCLASS_COUNT 22
+#define EDPC_KCLASS_COUNT 24
 edpc_status edpc_session_time_kernels(edpc_session* s, uint64_t n_steps, float* h_ms,
                                       uint32_t* h_launches);
 const char* edpc_kclass_name(int c);

@@ -26,7 +26,7 @@ EDPC_CFG_ZERO_HEAD = 0x1
 EDPC_CFG_AUTOTUNE = 0x2
 EDPC_STEP_BACKWARD, EDPC_STEP_UPDATE, EDPC_STEP_KEEP_FDM_GRAD = 0x1, 0x2, 0x4
 EDPC_KIND_PARAM, EDPC_KIND_GRAD, EDPC_KIND_ADAM_M, EDPC_KIND_ADAM_V = 0, 1, 2, 3
-KCLASS_COUNT = 22
+KCLASS_COUNT = 24
 
 #: every symbol include/edpc.h declares
 EXPORTS = [

@@ -389,6 +389,7 @@ edpc_status edpc_model_write(edpc_model* mh, uint32_t kind, size_t idx, const fl
     if (kind == EDPC_KIND_PARAM && m.bf16 && idx < m.tens.size()) {
       const TensorInfo& t = m.tens[idx];
       k_to_bf16(m.param + t.off, m.p16 + t.off, t.numel, nullptr);
+      if (m.kc.fused) m.build_frags(nullptr);
       hip_check(hipDeviceSynchronize(), "sync");
     }
     return EDPC_OK;
@@ -419,6 +420,7 @@ edpc_status edpc_model_write_device(edpc_model* mh, uint32_t kind, size_t idx, c
     if (kind == EDPC_KIND_PARAM && m.bf16 && idx < m.tens.size()) {
       const TensorInfo& t = m.tens[idx];
       k_to_bf16(m.param + t.off, m.p16 + t.off, t.numel, S(stream));
+      if (m.kc.fused) m.build_frags(S(stream));
     }
     return EDPC_OK;
   });

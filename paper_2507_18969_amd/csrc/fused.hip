@@ -1,0 +1,496 @@
+// Row-block fused step (BF16 operands, FP32 accumulation); see fused.h.
+#include "fused.h"
+#include "head_row.h"
+
+namespace edpc {
+
+// ---------------------------------------------------------------------------
+// Fragment-ordered BF16 weight copies
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) build_frags_kernel(const FragJob* __restrict__ jobs,
+                                                          int n_jobs, int total_frags) {
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = gid & 63;
+  const int f = gid >> 6;
+  if (f >= total_frags) return;
+  int j = 0;
+  while (j + 1 < n_jobs && f >= jobs[j + 1].frag_begin) ++j;
+  const FragJob jb = jobs[j];
+  const int nfr = jb.rows * jb.cols / 512;  // 16 x 32 elements per fragment
+  int local = f - jb.frag_begin;
+  uint32_t w[4];
+  if (local < nfr) {  // nt
+    const int KB = jb.cols / 32;
+    const int nb = local / KB, kb = local % KB;
+    const float* s = jb.src + (size_t)(nb * 16 + (lane & 15)) * jb.cols + kb * 32 + 8 * (lane >> 4);
+    const float4 a = *(const float4*)s, b = *(const float4*)(s + 4);
+    w[0] = (uint32_t)f2bf(a.x) | ((uint32_t)f2bf(a.y) << 16);
+    w[1] = (uint32_t)f2bf(a.z) | ((uint32_t)f2bf(a.w) << 16);
+    w[2] = (uint32_t)f2bf(b.x) | ((uint32_t)f2bf(b.y) << 16);
+    w[3] = (uint32_t)f2bf(b.z) | ((uint32_t)f2bf(b.w) << 16);
+    jb.nt[(size_t)local * 64 + lane] = make_uint4(w[0], w[1], w[2], w[3]);
+  } else {  // nn
+    local -= nfr;
+    const int KB = jb.rows / 32;
+    const int nb = local / KB, kb = local % KB;
+    const int col = nb * 16 + (lane & 15);
+    const int k0 = kb * 32 + 8 * (lane >> 4);
+    bf16_t h[8];
+#pragma unroll
+    for (int v = 0; v < 8; ++v) h[v] = f2bf(jb.src[(size_t)(k0 + v) * jb.cols + col]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) w[q] = (uint32_t)h[2 * q] | ((uint32_t)h[2 * q + 1] << 16);
+    jb.nn[(size_t)local * 64 + lane] = make_uint4(w[0], w[1], w[2], w[3]);
+  }
+}
+
+void k_build_frags(const FragJob* jobs, int n_jobs, int total_frags, hipStream_t s) {
+  if (total_frags == 0) return;
+  const size_t threads = (size_t)total_frags * 64;
+  hipLaunchKernelGGL(build_frags_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s,
+                     jobs, n_jobs, total_frags);
+}
+
+// ---------------------------------------------------------------------------
+// Row-block products
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ f32x4 mfma16(uint4 a, uint4 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
+// acc[t] = A (16 rows in LDS, bf16, row stride lda, K columns) x fragments of
+// column block cb[t] (fragment base + cb*K/32*64 uint4), for the NT column
+// blocks of this wave.  Fragments stream through a ring of D registers.
+template <int K, int NT, int D>
+__device__ __forceinline__ void mm(const bf16_t* sA, int lda, const uint4* __restrict__ base,
+                                   const int (&cb)[NT], f32x4 (&acc)[NT]) {
+  constexpr int KB = K / 32;
+  constexpr int TOT = KB * NT;
+  constexpr int DD = D < TOT ? D : TOT;
+  const int lane = threadIdx.x & 63;
+  const uint4* ptr[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    ptr[t] = base + (size_t)cb[t] * KB * 64 + lane;
+    acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  }
+  uint4 ring[DD];
+#pragma unroll
+  for (int i = 0; i < DD; ++i) ring[i] = ptr[i % NT][(i / NT) * 64];
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) {
+    const uint4 a = *(const uint4*)(sA + (lane & 15) * lda + kb * 32 + 8 * (lane >> 4));
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int i = kb * NT + t;
+      acc[t] = mfma16(a, ring[i % DD], acc[t]);
+      if (i + DD < TOT) ring[i % DD] = ptr[(i + DD) % NT][((i + DD) / NT) * 64];
+    }
+  }
+}
+
+template <int F, int L, int H>
+struct FusedDims {
+  static constexpr int BM = kFusedRows;
+  static constexpr int H2 = 2 * H;
+  static constexpr int KM0 = F > H2 ? F : H2;
+  static constexpr int KMAX = KM0 > 256 ? KM0 : 256;
+  static constexpr int LDA = KMAX + 8;   // bf16 row stride
+  static constexpr int LDF = KMAX + 4;   // fp32 row stride
+  static constexpr int LDH = F + 4;
+  static constexpr size_t OFF_H = 0;
+  static constexpr size_t OFF_F = OFF_H + (size_t)BM * LDH * 4;
+  static constexpr size_t OFF_A = OFF_F + (size_t)BM * LDF * 4;
+  static constexpr size_t OFF_B = OFF_A + (size_t)BM * LDA * 2;
+  static constexpr size_t OFF_RED = OFF_B + (size_t)BM * LDA * 2;
+  static constexpr size_t OFF_STAT = OFF_RED + 4 * BM * 2 * 4;
+  static constexpr size_t BYTES = OFF_STAT + (size_t)kMaxFusedBlocks * BM * 2 * 4;
+};
+
+template <int F, int L, int H>
+__global__ void __launch_bounds__(256, 1) fused_kernel(FusedArgs a) {
+  typedef FusedDims<F, L, H> D;
+  constexpr int BM = D::BM, H2 = D::H2, LDA = D::LDA, LDF = D::LDF, LDH = D::LDH;
+  extern __shared__ __align__(16) char smem[];
+  float (*sH)[LDH] = (float (*)[LDH])(smem + D::OFF_H);      // residual stream / its adjoint
+  float (*sF)[LDF] = (float (*)[LDF])(smem + D::OFF_F);      // fp32 scratch (logits, dz, dA)
+  bf16_t (*sA)[LDA] = (bf16_t (*)[LDA])(smem + D::OFF_A);    // product operand
+  bf16_t (*sB)[LDA] = (bf16_t (*)[LDA])(smem + D::OFF_B);    // second product operand
+  float (*sRed)[BM][2] = (float (*)[BM][2])(smem + D::OFF_RED);
+  float (*sStat)[BM][2] = (float (*)[BM][2])(smem + D::OFF_STAT);
+
+  const StepState* st = a.st;
+  const int rows = st->rows;
+  const int r0 = blockIdx.x * BM;
+  if (r0 >= rows) return;
+  const int nr = min(BM, rows - r0);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = 4 * (lane >> 4), lc = lane & 15;
+  float* colp = a.colpart + (size_t)blockIdx.x * a.colpart_cols;
+  const int NB = a.n_blocks;
+
+  // ---- LTE up-projection (Eq. 16): X'' = W2 Y + b2 -------------------------
+  for (int idx = tid; idx < BM * (L / 8); idx += 256) {
+    const int i = idx / (L / 8), q = idx % (L / 8);
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (i < nr) v = *(const uint4*)(a.y16 + (size_t)(r0 + i) * L + 8 * q);
+    *(uint4*)(&sA[i][8 * q]) = v;
+  }
+  __syncthreads();
+  {
+    constexpr int NT = F / 64;
+    int cb[NT];
+    f32x4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) cb[t] = w + 4 * t;
+    mm<L, NT, 16>(&sA[0][0], LDA, a.w2_nt, cb, acc);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int c = cb[t] * 16 + lc;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = li + r;
+        const float v = acc[t][r] + a.b2[c];
+        sH[i][c] = v;
+        if (i < nr) a.hs[0][(size_t)(r0 + i) * F + c] = v;
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- refinement blocks (Eqs. 9-13) ----------------------------------------
+  for (int j = 0; j < NB; ++j) {
+    // LayerNorm (Eq. 9): wave w normalises rows 4w .. 4w+3
+    for (int q = 0; q < 4; ++q) {
+      const int i = 4 * w + q;
+      float s = 0.f;
+      for (int f = lane; f < F; f += 64) s += sH[i][f];
+      const float mu = wave_sum(s) / (float)F;
+      float v2 = 0.f;
+      for (int f = lane; f < F; f += 64) {
+        const float d = sH[i][f] - mu;
+        v2 += d * d;
+      }
+      const float rs = 1.0f / sqrtf(wave_sum(v2) / (float)F + 1e-5f);
+      const float* gm = a.gamma[j];
+      const float* bt = a.beta[j];
+      for (int f = lane; f < F; f += 64) {
+        const bf16_t z = f2bf((sH[i][f] - mu) * rs * gm[f] + bt[f]);
+        sA[i][f] = z;
+        if (i < nr) a.z16[j][(size_t)(r0 + i) * F + f] = z;
+      }
+      if (lane == 0) {
+        sStat[j][i][0] = mu;
+        sStat[j][i][1] = rs;
+        if (i < nr) {
+          a.mean[j][r0 + i] = mu;
+          a.rstd[j][r0 + i] = rs;
+        }
+      }
+    }
+    __syncthreads();
+    {  // branches (Eq. 10), product fusion (Eq. 11), GeLU (Eq. 12)
+      constexpr int NH = H / 64;
+      constexpr int NT = 2 * NH;
+      int cb[NT];
+      f32x4 acc[NT];
+#pragma unroll
+      for (int t = 0; t < NH; ++t) {
+        cb[t] = w + 4 * t;
+        cb[NH + t] = H / 16 + w + 4 * t;
+      }
+      mm<F, NT, 16>(&sA[0][0], LDA, a.wab_nt[j], cb, acc);
+      const float* bb = a.bab[j];
+#pragma unroll
+      for (int t = 0; t < NH; ++t) {
+        const int c = cb[t] * 16 + lc;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = li + r;
+          const float a0 = acc[t][r] + bb[c];
+          const float a1 = acc[NH + t][r] + bb[H + c];
+          const bf16_t g = f2bf(gelu_f(a0 * a1));
+          sB[i][c] = g;
+          if (i < nr) {
+            a.abr[j][(size_t)(r0 + i) * H2 + c] = a0;
+            a.abr[j][(size_t)(r0 + i) * H2 + H + c] = a1;
+            a.g16[j][(size_t)(r0 + i) * H + c] = g;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    {  // output linear + residual (Eq. 13)
+      constexpr int NT = F / 64;
+      int cb[NT];
+      f32x4 acc[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) cb[t] = w + 4 * t;
+      mm<H, NT, 16>(&sB[0][0], LDA, a.wo_nt[j], cb, acc);
+      const float* bo = a.bo[j];
+      const bool last = j == NB - 1;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int c = cb[t] * 16 + lc;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = li + r;
+          const float v = acc[t][r] + bo[c] + sH[i][c];
+          sH[i][c] = v;
+          if (i < nr) a.hs[j + 1][(size_t)(r0 + i) * F + c] = v;
+          if (last) {
+            const bf16_t hb = f2bf(v);
+            sA[i][c] = hb;
+            if (i < nr) a.hn16[(size_t)(r0 + i) * F + c] = hb;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- head logits ------------------------------------------------------------
+  {
+    constexpr int NT = 4;  // 256 outputs
+    int cb[NT];
+    f32x4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) cb[t] = w + 4 * t;
+    mm<F, NT, 16>(&sA[0][0], LDA, a.wh_nt, cb, acc);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int c = cb[t] * 16 + lc;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) sF[li + r][c] = acc[t][r] + a.bh[c];
+    }
+  }
+  __syncthreads();
+
+  // ---- softmax, CDF, coder lane, cross-entropy adjoint (Eqs. 1-2) -------------
+  const bool grad = a.head.want_grad != 0;
+  for (int q = 0; q < 4; ++q) {
+    const int i = 4 * w + q;
+    float d[4] = {0.f, 0.f, 0.f, 0.f};
+    if (i < nr) {
+      const float z[4] = {sF[i][4 * lane], sF[i][4 * lane + 1], sF[i][4 * lane + 2],
+                          sF[i][4 * lane + 3]};
+      float p[4];
+      int x = 0;
+      const bool have = head_row(st, a.head, a.io, r0 + i, lane, z, p, &x);
+      if (have && grad) {
+        const float ir = st->inv_rows;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) d[k] = (p[k] - (4 * lane + k == x ? 1.0f : 0.0f)) * ir;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      sF[i][4 * lane + k] = d[k];
+      sA[i][4 * lane + k] = f2bf(d[k]);
+    }
+    if (i < nr && grad)
+      *(ushort4*)(a.dz16 + (size_t)(r0 + i) * 256 + 4 * lane) =
+          make_ushort4(f2bf(d[0]), f2bf(d[1]), f2bf(d[2]), f2bf(d[3]));
+  }
+  if (!grad) return;
+  __syncthreads();
+  {  // bias gradient of the head: column sums of dz over this block's rows
+    float s = 0.f;
+    for (int i = 0; i < nr; ++i) s += sF[i][tid];
+    colp[a.off_bh + tid] = s;
+  }
+  {  // dH_N = dz Wh
+    constexpr int NT = F / 64;
+    int cb[NT];
+    f32x4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) cb[t] = w + 4 * t;
+    mm<256, NT, 16>(&sA[0][0], LDA, a.wh_nn, cb, acc);
+    __syncthreads();  // every wave is done reading sA / sF
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int c = cb[t] * 16 + lc;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = li + r;
+        sH[i][c] = acc[t][r];
+        const bf16_t hb = f2bf(acc[t][r]);
+        sA[i][c] = hb;
+        if (i < nr) a.dh16[NB][(size_t)(r0 + i) * F + c] = hb;
+      }
+    }
+  }
+  __syncthreads();
+
+  for (int j = NB - 1; j >= 0; --j) {
+    // bias gradient of the block's output linear: column sums of dH_{j+1}
+    for (int c = tid; c < F; c += 256) {
+      float s = 0.f;
+      for (int i = 0; i < nr; ++i) s += sH[i][c];
+      colp[a.off_bo[j] + c] = s;
+    }
+    {  // dX_ff = dH Wo; through GeLU and the branch product (adjoint of Eqs. 11-13)
+      constexpr int NH = H / 64;
+      int cb[NH];
+      f32x4 acc[NH];
+#pragma unroll
+      for (int t = 0; t < NH; ++t) cb[t] = w + 4 * t;
+      mm<F, NH, 16>(&sA[0][0], LDA, a.wo_nn[j], cb, acc);
+#pragma unroll
+      for (int t = 0; t < NH; ++t) {
+        const int c = cb[t] * 16 + lc;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = li + r;
+          float a0 = 0.f, a1 = 0.f;
+          if (i < nr) {
+            a0 = a.abr[j][(size_t)(r0 + i) * H2 + c];
+            a1 = a.abr[j][(size_t)(r0 + i) * H2 + H + c];
+          }
+          const float dp = acc[t][r] * gelu_grad_f(a0 * a1);
+          const float d0 = dp * a1, d1 = dp * a0;
+          sF[i][c] = d0;
+          sF[i][H + c] = d1;
+          const bf16_t h0 = f2bf(d0), h1 = f2bf(d1);
+          sB[i][c] = h0;
+          sB[i][H + c] = h1;
+          if (i < nr) {
+            a.da16[j][(size_t)(r0 + i) * H2 + c] = h0;
+            a.da16[j][(size_t)(r0 + i) * H2 + H + c] = h1;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    for (int c = tid; c < H2; c += 256) {  // branch bias gradients
+      float s = 0.f;
+      for (int i = 0; i < nr; ++i) s += sF[i][c];
+      colp[a.off_bab[j] + c] = s;
+    }
+    {  // dX0 = sum_i dX_i W_i, then the LayerNorm adjoint (Eq. 9)
+      constexpr int NT = F / 64;
+      int cb[NT];
+      f32x4 acc[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) cb[t] = w + 4 * t;
+      mm<H2, NT, 16>(&sB[0][0], LDA, a.wab_nn[j], cb, acc);
+      const float* gm = a.gamma[j];
+      float xh[NT][4];
+      float s1[4] = {0.f, 0.f, 0.f, 0.f}, s2[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int c = cb[t] * 16 + lc;
+        float cz = 0.f, czx = 0.f;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = li + r;
+          float x = 0.f, dz = 0.f;
+          if (i < nr) {
+            x = (a.hs[j][(size_t)(r0 + i) * F + c] - sStat[j][i][0]) * sStat[j][i][1];
+            dz = acc[t][r];
+          }
+          xh[t][r] = x;
+          acc[t][r] = dz * gm[c];  // dxhat
+          s1[r] += acc[t][r];
+          s2[r] += acc[t][r] * x;
+          cz += dz;
+          czx += dz * x;
+        }
+        // LayerNorm affine gradients: column sums over the 16 rows
+        cz += __shfl_xor(cz, 16, 64);
+        cz += __shfl_xor(cz, 32, 64);
+        czx += __shfl_xor(czx, 16, 64);
+        czx += __shfl_xor(czx, 32, 64);
+        if (lane < 16) {
+          colp[a.off_beta[j] + c] = cz;
+          colp[a.off_gamma[j] + c] = czx;
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+#pragma unroll
+        for (int o = 8; o >= 1; o >>= 1) {
+          s1[r] += __shfl_xor(s1[r], o, 64);
+          s2[r] += __shfl_xor(s2[r], o, 64);
+        }
+        if (lc == 0) {
+          sRed[w][li + r][0] = s1[r];
+          sRed[w][li + r][1] = s2[r];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = li + r;
+        const float m1 = ((sRed[0][i][0] + sRed[1][i][0]) + (sRed[2][i][0] + sRed[3][i][0])) / (float)F;
+        const float m2 = ((sRed[0][i][1] + sRed[1][i][1]) + (sRed[2][i][1] + sRed[3][i][1])) / (float)F;
+        const float rs = sStat[j][i][1];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const int c = cb[t] * 16 + lc;
+          float dh = 0.f;
+          if (i < nr) dh = sH[i][c] + rs * (acc[t][r] - m1 - xh[t][r] * m2);
+          sH[i][c] = dh;
+          const bf16_t hb = f2bf(dh);
+          sA[i][c] = hb;
+          if (i < nr) a.dh16[j][(size_t)(r0 + i) * F + c] = hb;
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- adjoint of Eq. 16 ---------------------------------------------------------
+  for (int c = tid; c < F; c += 256) {
+    float s = 0.f;
+    for (int i = 0; i < nr; ++i) s += sH[i][c];
+    colp[a.off_b2 + c] = s;
+  }
+  {
+    constexpr int NT = L / 64;
+    int cb[NT];
+    f32x4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) cb[t] = w + 4 * t;
+    mm<F, NT, 16>(&sA[0][0], LDA, a.w2_nn, cb, acc);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int c = cb[t] * 16 + lc;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = li + r;
+        if (i < nr) a.dy[(size_t)(r0 + i) * L + c] = acc[t][r];
+      }
+    }
+  }
+}
+
+bool fused_supported(int F, int L, int H, int branches, int blocks) {
+  if (branches != 2 || blocks < 1 || blocks > kMaxFusedBlocks) return false;
+  return (F == 512 && L == 128 && H == 256) || (F == 256 && L == 64 && H == 128);
+}
+
+template <int F, int L, int H>
+static hipError_t launch_t(const FusedArgs& a, int grid_rows, hipStream_t s) {
+  typedef FusedDims<F, L, H> D;
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)fused_kernel<F, L, H>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)D::BYTES);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  const int blocks = (grid_rows + kFusedRows - 1) / kFusedRows;
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL((fused_kernel<F, L, H>), dim3(blocks), dim3(256), D::BYTES, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fused(int F, int L, int H, const FusedArgs& a, int grid_rows, hipStream_t s) {
+  if (F == 512 && L == 128 && H == 256) return launch_t<512, 128, 256>(a, grid_rows, s);
+  if (F == 256 && L == 64 && H == 128) return launch_t<256, 64, 128>(a, grid_rows, s);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace edpc

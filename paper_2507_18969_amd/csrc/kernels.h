@@ -79,6 +79,10 @@ size_t colsum_partial_elems(int max_rows, int total_cols);
 void k_colsum(const StepState* st, const ColsumJob* jobs, int n_jobs, int total_blocks,
               int total_cols, float* partial, int max_rows, hipStream_t s);
 
+// Second pass only: partial[k][col] over chunks of chunk_rows rows.
+void k_colsum_reduce(const StepState* st, const ColsumJob* jobs, int n_jobs, int total_cols,
+                     const float* partial, int chunk_rows, hipStream_t s);
+
 void emb_grad_plan(int max_rows, int C, int E, int* chunk_rows, int* sub_rows);
 void k_emb_grad(const StepState* st, const uint8_t* ctx, const float* dx, int C, int E,
                 float* partial, int chunk_rows, int sub_rows, int max_rows, float* demb,

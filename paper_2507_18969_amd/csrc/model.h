@@ -5,6 +5,7 @@
 #include <vector>
 
 #include "../../include/edpc.h"
+#include "fused.h"
 #include "gemm.h"
 #include "kernels.h"
 
@@ -39,6 +40,7 @@ enum ProductSlot : int {
 constexpr uint32_t kNumericsRevision = 1;
 struct KernelConfig {
   int tile[PS_COUNT];
+  bool fused = false;  // BF16 row-block fused step (bit 47 of the id)
   uint64_t encode() const;
   static bool decode(uint64_t id, KernelConfig* out);
 };
@@ -64,6 +66,8 @@ enum KClass : int {
   KC_EMB_GRAD,
   KC_COLSUM,
   KC_ADAM,
+  KC_FUSED,
+  KC_FRAGS,
   KC_COUNT
 };
 static_assert(KC_COUNT == EDPC_KCLASS_COUNT, "kernel class count");
@@ -138,6 +142,18 @@ struct Model {
   float* loss_partial = nullptr;
   int emb_chunk = 16, emb_sub = 16;
   KTimer* timer = nullptr;
+  // fused BF16 path: fragment-ordered weight copies and column-sum partials
+  uint4* frags = nullptr;
+  FragJob* d_frag_jobs = nullptr;
+  int n_frag_jobs = 0, total_frags = 0;
+  FusedArgs fa;
+  float* fused_colpart = nullptr;
+  ColsumJob* d_fcs = nullptr;
+  int n_fcs = 0, fcs_cols = 0;
+  ColsumJob* d_b1_job = nullptr;
+  int b1_blocks = 0;
+  float* b1_partial = nullptr;
+  void build_frags(hipStream_t s) { k_build_frags(d_frag_jobs, n_frag_jobs, total_frags, s); }
   std::vector<void*> allocs;
 
   Model(const edpc_config& c, size_t n_slots, size_t max_rows, const KernelConfig* kc);
@@ -158,6 +174,7 @@ struct Model {
             hipStream_t s);
 
   void product(int ps, int j, int R, hipStream_t s);
+  void setup_fused(hipStream_t s);
   void autotune(hipStream_t s);
   static KernelConfig default_config(const edpc_config& c, size_t rows);
   static void validate(const edpc_config& c);

@@ -19,12 +19,14 @@ void hip_check(hipError_t e, const char* what) {
 uint64_t KernelConfig::encode() const {
   uint64_t id = (uint64_t)kNumericsRevision << 48;
   for (int i = 0; i < PS_COUNT; ++i) id |= (uint64_t)(tile[i] & 7) << (3 * i);
+  if (fused) id |= 1ull << 47;
   return id;
 }
 
 bool KernelConfig::decode(uint64_t id, KernelConfig* out) {
   if ((id >> 48) != kNumericsRevision) return false;
-  if ((id >> (3 * PS_COUNT)) & ((1ull << (48 - 3 * PS_COUNT)) - 1)) return false;
+  if ((id >> (3 * PS_COUNT)) & ((1ull << (47 - 3 * PS_COUNT)) - 1)) return false;
+  out->fused = ((id >> 47) & 1) != 0;
   for (int i = 0; i < PS_COUNT; ++i) {
     const int t = (int)((id >> (3 * i)) & 7);
     if (t >= TILE_COUNT) return false;
@@ -39,7 +41,7 @@ const char* kclass_name(int c) {
       "gemm_head_bwd", "gemm_gelu_bwd", "gemm_branches_bwd", "gemm_lte_up_bwd",
       "gemm_lte_down_bwd", "gemm_weight_grads", "step_schedule", "gather", "embed", "fdm_fwd",
       "layernorm_fwd", "head_softmax_cdf_coder", "layernorm_bwd", "fdm_bwd_adam", "emb_grad",
-      "colsum_bias_grads", "adam_shared"};
+      "colsum_bias_grads", "adam_shared", "fused_rowblock_step", "weight_fragments"};
   return (c >= 0 && c < KC_COUNT) ? names[c] : "unknown";
 }
 
@@ -143,6 +145,8 @@ KernelConfig Model::default_config(const edpc_config& c, size_t rows) {
     wg.push_back({KH, F});
   }
   k.tile[PS_WGRAD] = pick_tile(rows, wg, 512);
+  k.fused = c.precision == EDPC_BF16 &&
+            fused_supported(F, L, H, (int)c.branches, (int)c.blocks);
   return k;
 }
 
@@ -171,6 +175,8 @@ Model::Model(const edpc_config& c, size_t nslots, size_t rows, const KernelConfi
   K = c.branches;
   bf16 = c.precision == EDPC_BF16;
   kc = kcfg ? *kcfg : default_config(c, rows);
+  if (kc.fused && !(bf16 && fused_supported(F, L, H, K, N)))
+    fail(EDPC_E_UNSUPPORTED, "fused step requested for an unsupported shape");
 
   // Flat layout of the shared parameters; each tensor starts 64-aligned.
   auto add = [&](const std::string& n, size_t numel, uint32_t tid, double bound) {
@@ -285,6 +291,7 @@ void Model::init_params(hipStream_t s) {
   hip_check(hipMemsetAsync(mU, 0, n_slots * (size_t)L * L * sizeof(float), s), "memset");
   hip_check(hipMemsetAsync(vU, 0, n_slots * (size_t)L * L * sizeof(float), s), "memset");
   if (bf16) k_to_bf16(param, p16, P, s);
+  if (kc.fused) build_frags(s);
   hip_check(hipGetLastError(), "init");
   tau = 0;
 }
@@ -376,7 +383,132 @@ void Model::build_tables(hipStream_t s) {
   loss_partial = dalloc<float>(colsum_partial_elems((int)max_rows, 1));
   d_loss_job = dalloc<ColsumJob>(1);
   hip_check(hipMemcpyAsync(d_loss_job, &lj, sizeof(lj), hipMemcpyHostToDevice, s), "copy");
+  if (kc.fused) setup_fused(s);
   hip_check(hipStreamSynchronize(s), "sync");
+}
+
+void Model::setup_fused(hipStream_t s) {
+  // fragment-ordered BF16 copies of every matrix the row-block kernel streams
+  struct Mat { const char* name; int rows, cols; };
+  std::vector<FragJob> jobs;
+  std::vector<std::pair<std::string, size_t>> where;  // matrix -> uint4 offset of its nt copy
+  size_t off = 0;
+  int fr = 0;
+  auto add = [&](const std::string& name, int rows, int cols) {
+    FragJob j;
+    j.src = param + tensor(name).off;
+    j.rows = rows;
+    j.cols = cols;
+    j.frag_begin = fr;
+    j.nt = (uint4*)(size_t)off;  // offsets for now
+    j.nn = (uint4*)(size_t)(off + (size_t)rows * cols / 8);
+    where.push_back({name, off});
+    off += 2 * (size_t)rows * cols / 8;
+    fr += 2 * rows * cols / 512;
+    jobs.push_back(j);
+  };
+  add("w2", F, L);
+  for (int j = 0; j < N; ++j) {
+    add("blk" + std::to_string(j) + ".w0", K * H, F);
+    add("blk" + std::to_string(j) + ".wo", F, H);
+  }
+  add("wh", 256, F);
+  frags = dalloc<uint4>(off);
+  for (auto& j : jobs) {
+    j.nt = frags + (size_t)j.nt;
+    j.nn = frags + (size_t)j.nn;
+  }
+  n_frag_jobs = (int)jobs.size();
+  total_frags = fr;
+  d_frag_jobs = dalloc<FragJob>(jobs.size());
+  hip_check(hipMemcpyAsync(d_frag_jobs, jobs.data(), jobs.size() * sizeof(FragJob),
+                           hipMemcpyHostToDevice, s), "copy");
+  auto nt = [&](const std::string& n) -> const uint4* {
+    for (auto& w : where) if (w.first == n) return frags + w.second;
+    fail(EDPC_E_DEVICE, "fragment table");
+  };
+  auto nn = [&](const std::string& n, int numel) -> const uint4* { return nt(n) + numel / 8; };
+
+  std::memset(&fa, 0, sizeof(fa));
+  fa.st = st;
+  fa.n_blocks = N;
+  fa.w2_nt = nt("w2");
+  fa.w2_nn = nn("w2", F * L);
+  fa.wh_nt = nt("wh");
+  fa.wh_nn = nn("wh", 256 * F);
+  fa.b2 = P_("b2");
+  fa.bh = P_("bh");
+  for (int j = 0; j < N; ++j) {
+    const std::string b = "blk" + std::to_string(j), ln = "ln" + std::to_string(j);
+    fa.wab_nt[j] = nt(b + ".w0");
+    fa.wab_nn[j] = nn(b + ".w0", K * H * F);
+    fa.wo_nt[j] = nt(b + ".wo");
+    fa.wo_nn[j] = nn(b + ".wo", F * H);
+    fa.bab[j] = P_(b + ".b0");
+    fa.bo[j] = P_(b + ".bo");
+    fa.gamma[j] = P_(ln + ".gamma");
+    fa.beta[j] = P_(ln + ".beta");
+    fa.z16[j] = Z16[j];
+    fa.mean[j] = mean[j];
+    fa.rstd[j] = rstd[j];
+    fa.abr[j] = Abr[j];
+    fa.g16[j] = G16[j];
+    fa.da16[j] = dA16[j];
+  }
+  for (int j = 0; j <= N; ++j) {
+    fa.hs[j] = Hs[j];
+    fa.dh16[j] = dH16[j];
+  }
+  fa.y16 = Y16;
+  fa.hn16 = HN16;
+  fa.dz16 = dz16;
+  fa.dy = dY;
+  fa.loss_rows = loss_rows;
+
+  // column-sum partials: [row block][bh | per block: bo, bab, beta, gamma | b2]
+  std::vector<ColsumJob> cs;
+  int cols = 0;
+  auto addc = [&](float* dst, int n) {
+    ColsumJob j;
+    std::memset(&j, 0, sizeof(j));
+    j.dst = dst;
+    j.cols = n;
+    j.col_offset = cols;
+    j.scale = 1.0f;
+    cols += n;
+    cs.push_back(j);
+    return j.col_offset;
+  };
+  fa.off_bh = addc(G_("bh"), 256);
+  for (int j = 0; j < N; ++j) {
+    const std::string b = "blk" + std::to_string(j), ln = "ln" + std::to_string(j);
+    fa.off_bo[j] = addc(G_(b + ".bo"), F);
+    fa.off_bab[j] = addc(G_(b + ".b0"), K * H);
+    fa.off_beta[j] = addc(G_(ln + ".beta"), F);
+    fa.off_gamma[j] = addc(G_(ln + ".gamma"), F);
+  }
+  fa.off_b2 = addc(G_("b2"), F);
+  fcs_cols = cols;
+  n_fcs = (int)cs.size();
+  fa.colpart_cols = cols;
+  fused_colpart = dalloc<float>(((max_rows + kFusedRows - 1) / kFusedRows) * (size_t)cols);
+  fa.colpart = fused_colpart;
+  d_fcs = dalloc<ColsumJob>(cs.size());
+  hip_check(hipMemcpyAsync(d_fcs, cs.data(), cs.size() * sizeof(ColsumJob), hipMemcpyHostToDevice, s),
+            "copy");
+  // b1 (from the FDM adjoint's output) still by the two-pass column sum
+  ColsumJob b1;
+  std::memset(&b1, 0, sizeof(b1));
+  b1.src = dX1_32;
+  b1.dst = G_("b1");
+  b1.cols = L;
+  b1.ld = L;
+  b1.scale = 1.0f;
+  b1_blocks = (L + 63) / 64;
+  d_b1_job = dalloc<ColsumJob>(1);
+  hip_check(hipMemcpyAsync(d_b1_job, &b1, sizeof(b1), hipMemcpyHostToDevice, s), "copy");
+  b1_partial = dalloc<float>(colsum_partial_elems((int)max_rows, L));
+  build_frags(s);
 }
 
 void Model::gemm(int ps, bool ak, bool bk, EpiKind epi, int nb, GemmArgs g, int grid_rows,
@@ -466,16 +598,6 @@ void Model::step(StepMode mode, const StreamIO& io, const StepOutputs& out, int 
   TIMED(KC_EMBED, k_embed(st, ctx, P_("emb"), C, E, X32, X16, R, s));
   product(PS_LTE_DOWN, 0, R, s);
   TIMED(KC_FDM_FWD, k_fdm_fwd(st, X1, U, slot, L, Y32, Y16, R, s));  // Eq. 15
-  product(PS_LTE_UP, 0, R, s);
-  for (int j = 0; j < N; ++j) {
-    const std::string ln = "ln" + std::to_string(j);
-    TIMED(KC_LN_FWD, k_ln_fwd(st, Hs[j], P_(ln + ".gamma"), P_(ln + ".beta"), F,
-                              bf16 ? nullptr : Z32[j], bf16 ? Z16[j] : nullptr, mean[j],
-                              rstd[j], R, s));
-    product(PS_GATE, j, R, s);
-    product(PS_OUT, j, R, s);
-  }
-  product(PS_HEAD, 0, R, s);
   const bool backward = out.backward || out.update || out.keep_fdm_grad;
   HeadArgs ha;
   std::memset(&ha, 0, sizeof(ha));
@@ -491,6 +613,42 @@ void Model::step(StepMode mode, const StreamIO& io, const StepOutputs& out, int 
   ha.want_grad = backward ? 1 : 0;
   StreamIO hio = io;
   if (mode == MODE_PLAIN) hio.slot = nullptr;
+  AdamCfg ac{cfg.lr, cfg.beta1, cfg.beta2, cfg.eps};
+  if (kc.fused) {
+    // LTE up .. head .. coder .. adjoint back to dY, one workgroup per 16 rows
+    FusedArgs a = fa;
+    a.head = ha;
+    a.io = hio;
+    TIMED(KC_FUSED, hip_check(launch_fused(F, L, H, a, R, s), "fused launch"));
+    if (out.loss) {
+      TIMED(KC_COLSUM, k_colsum(st, d_loss_job, 1, 1, 1, loss_partial, R, s));
+      hip_check(hipMemcpyAsync(out.loss, loss_out, sizeof(float), hipMemcpyDeviceToDevice, s), "copy");
+    }
+    if (!backward) return;
+    TIMED(KC_FDM_BWD, k_fdm_bwd(st, X1, dY, U, mU, vU, out.keep_fdm_grad ? dUkeep : nullptr, slot,
+                                L, ac, out.update, dX1_32, dX1_16, R, s));
+    product(PS_LTE_DOWN_BWD, 0, R, s);
+    TIMED(KC_EMB_GRAD, k_emb_grad(st, ctx, dX, C, E, emb_partial, emb_chunk, emb_sub, R, G_("emb"), s));
+    product(PS_WGRAD, 0, R, s);
+    TIMED(KC_COLSUM, k_colsum(st, d_b1_job, 1, b1_blocks, L, b1_partial, R, s));
+    TIMED(KC_COLSUM, k_colsum_reduce(st, d_fcs, n_fcs, fcs_cols, fused_colpart, kFusedRows, s));
+    if (out.update) {
+      TIMED(KC_ADAM, k_adam(st, param, grad, m, v, p16, P, ac, s));
+      TIMED(KC_FRAGS, build_frags(s));
+    }
+    hip_check(hipGetLastError(), "step launch");
+    return;
+  }
+  product(PS_LTE_UP, 0, R, s);
+  for (int j = 0; j < N; ++j) {
+    const std::string ln = "ln" + std::to_string(j);
+    TIMED(KC_LN_FWD, k_ln_fwd(st, Hs[j], P_(ln + ".gamma"), P_(ln + ".beta"), F,
+                              bf16 ? nullptr : Z32[j], bf16 ? Z16[j] : nullptr, mean[j],
+                              rstd[j], R, s));
+    product(PS_GATE, j, R, s);
+    product(PS_OUT, j, R, s);
+  }
+  product(PS_HEAD, 0, R, s);
   TIMED(KC_HEAD, k_head(st, ha, hio, R, s));
   if (out.loss) {
     TIMED(KC_COLSUM, k_colsum(st, d_loss_job, 1, 1, 1, loss_partial, R, s));
@@ -508,7 +666,6 @@ void Model::step(StepMode mode, const StreamIO& io, const StepOutputs& out, int 
                               dH32[j + 1], F, dH32[j], bf16 ? dH16[j] : nullptr, R, s));
   }
   product(PS_LTE_UP_BWD, 0, R, s);
-  AdamCfg ac{cfg.lr, cfg.beta1, cfg.beta2, cfg.eps};
   // adjoint of Eq. 15, fused with Adam on U_s
   TIMED(KC_FDM_BWD, k_fdm_bwd(st, X1, dY, U, mU, vU, out.keep_fdm_grad ? dUkeep : nullptr, slot,
                               L, ac, out.update, dX1_32, dX1_16, R, s));
