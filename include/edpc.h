@@ -74,8 +74,8 @@ typedef enum { EDPC_FP32 = 0, EDPC_BF16 = 1 } edpc_precision;
 
 typedef struct {
   uint32_t struct_size; /* sizeof(edpc_config) */
-  uint32_t context;     /* t: bytes of history (Algorithm 1), 1..256 */
-  uint32_t embed;       /* embedding width E; F = context * embed */
+  uint32_t context;     /* t: bytes of history (Algorithm 1), multiple of 4 in 4..256 */
+  uint32_t embed;       /* embedding width E (16, 32 or 64); F = context * embed */
   uint32_t latent;      /* F' of the LTE (Eq. 14), multiple of 16 */
   uint32_t blocks;      /* number of refinement blocks, 0..16 */
   uint32_t hidden;      /* hidden width of each branch, multiple of 16 */

@@ -152,9 +152,12 @@ void Session::step_direct(uint64_t i, int grid_rows, bool explicit_step, hipStre
   out.update = true;
   if (timer) timer->begin(KC_SCHEDULE, st);
   k_step_schedule(model->st, sched, explicit_step ? (int)i : -1, st);
-  if (timer) { timer->end(st); timer->begin(KC_GATHER, st); }
-  k_gather(model->st, io, model->C, model->ctx, model->tgt, grid_rows, decoding, st);
   if (timer) timer->end(st);
+  if (!model->kc.fused) {  // the fused path gathers inside its first kernel
+    if (timer) timer->begin(KC_GATHER, st);
+    k_gather(model->st, io, model->C, model->ctx, model->tgt, grid_rows, decoding, st);
+    if (timer) timer->end(st);
+  }
   model->step(decoding ? MODE_DECODE : MODE_ENCODE, io, out, grid_rows, st);
 }
 

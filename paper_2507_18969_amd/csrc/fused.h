@@ -71,8 +71,42 @@ struct FusedArgs {
   StreamIO io;
 };
 
+// Row-block kernel before the FDM: context gather (streams) or staged
+// contexts, byte embedding, LTE down-projection (Eq. 14).
+struct FusedInArgs {
+  const StepState* st;
+  int gather;             // 1: read the contexts from the streams; 0: use ctx / tgt as staged
+  int decoding;
+  StreamIO io;
+  int C, E;
+  const float* emb;       // [256, E] FP32 master
+  const uint4* w1_nt;
+  const float* b1;
+  uint8_t* ctx;           // [rows, C]
+  uint8_t* tgt;           // [rows]
+  bf16_t* x16;            // [rows, F]
+  float* x1;              // [rows, L]
+};
+
+// Row-block kernel after the FDM adjoint: dX = dX' W1 (adjoint of Eq. 14),
+// the embedding gradient of the block as a one-hot product, and the column
+// partial of b1.
+struct FusedOutArgs {
+  const StepState* st;
+  int C, E;
+  const uint4* w1_nn;
+  const bf16_t* dx1_16;   // [rows, L]
+  const float* dx1_32;    // [rows, L]
+  const uint8_t* ctx;     // [rows, C]
+  float* emb_partial;     // [row block][256 * E]
+  float* colpart;
+  int colpart_cols, off_b1;
+};
+
 // F, L, H combinations compiled for the fused path.
 bool fused_supported(int F, int L, int H, int branches, int blocks);
 hipError_t launch_fused(int F, int L, int H, const FusedArgs& a, int grid_rows, hipStream_t s);
+hipError_t launch_fused_in(int F, int L, const FusedInArgs& a, int grid_rows, hipStream_t s);
+hipError_t launch_fused_out(int F, int L, const FusedOutArgs& a, int grid_rows, hipStream_t s);
 
 }  // namespace edpc

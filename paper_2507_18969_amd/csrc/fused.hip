@@ -466,6 +466,166 @@ __global__ void __launch_bounds__(256, 1) fused_kernel(FusedArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Before the FDM: gather, embedding, LTE down-projection
+// ---------------------------------------------------------------------------
+template <int F, int L>
+__global__ void __launch_bounds__(256) fused_in_kernel(FusedInArgs a) {
+  constexpr int BM = kFusedRows, LDA = F + 8;
+  __shared__ __align__(16) bf16_t sA[BM][LDA];
+  __shared__ uint8_t sC[BM][256];
+  const StepState* st = a.st;
+  const int rows = st->rows;
+  const int r0 = blockIdx.x * BM;
+  if (r0 >= rows) return;
+  const int nr = min(BM, rows - r0);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int C = a.C, E = a.E;
+  for (int idx = tid; idx < BM * C; idx += 256) {
+    const int i = idx / C, c = idx % C;
+    uint8_t v = 0;
+    if (i < nr) {
+      const int r = r0 + i;
+      if (a.gather) {
+        const uint32_t sidx = a.io.slot[r];
+        const uint8_t* base = a.decoding ? a.io.dst : a.io.src;
+        const uint64_t o = a.io.off[sidx];
+        v = base[o + (uint64_t)(st->step - C + c)];
+        a.ctx[(size_t)r * C + c] = v;
+        if (!a.decoding && c == 0) a.tgt[r] = a.io.src[o + (uint64_t)st->step];
+      } else {
+        v = a.ctx[(size_t)r * C + c];
+      }
+    }
+    sC[i][c] = v;
+  }
+  __syncthreads();
+  // byte embedding, oldest byte first: X[i][c*E + e] = Emb[ctx[i][c]][e]
+  for (int idx = tid; idx < BM * F / 4; idx += 256) {
+    const int i = idx / (F / 4), f = (idx % (F / 4)) * 4;
+    const int c = f / E, e = f % E;
+    const float4 v = *(const float4*)(a.emb + (size_t)sC[i][c] * E + e);
+    const ushort4 h = make_ushort4(f2bf(v.x), f2bf(v.y), f2bf(v.z), f2bf(v.w));
+    *(ushort4*)(&sA[i][f]) = h;
+    if (i < nr) *(ushort4*)(a.x16 + (size_t)(r0 + i) * F + f) = h;
+  }
+  __syncthreads();
+  constexpr int NT = L / 64;
+  int cb[NT];
+  f32x4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) cb[t] = w + 4 * t;
+  mm<F, NT, 16>(&sA[0][0], LDA, a.w1_nt, cb, acc);
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int c = cb[t] * 16 + (lane & 15);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 4 * (lane >> 4) + r;
+      if (i < nr) a.x1[(size_t)(r0 + i) * L + c] = acc[t][r] + a.b1[c];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// After the FDM adjoint: dX = dX' W1, embedding gradient partial, b1 partial
+// ---------------------------------------------------------------------------
+template <int F, int L>
+__global__ void __launch_bounds__(256) fused_out_kernel(FusedOutArgs a) {
+  constexpr int BM = kFusedRows, LDA = L + 8, LDX = F + 4;
+  __shared__ __align__(16) bf16_t sA[BM][LDA];
+  __shared__ __align__(16) float sX[BM][LDX];
+  __shared__ uint8_t sC[BM * 256 + 16];
+  const StepState* st = a.st;
+  const int rows = st->rows;
+  const int r0 = blockIdx.x * BM;
+  if (r0 >= rows) return;
+  const int nr = min(BM, rows - r0);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int C = a.C, E = a.E;
+  for (int idx = tid; idx < BM * (L / 8); idx += 256) {
+    const int i = idx / (L / 8), q = idx % (L / 8);
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (i < nr) v = *(const uint4*)(a.dx1_16 + (size_t)(r0 + i) * L + 8 * q);
+    *(uint4*)(&sA[i][8 * q]) = v;
+  }
+  for (int idx = tid; idx < BM * C; idx += 256)
+    sC[idx] = (idx / C) < nr ? a.ctx[(size_t)r0 * C + idx] : 0;
+  float* colp = a.colpart + (size_t)blockIdx.x * a.colpart_cols;
+  for (int c = tid; c < L; c += 256) {  // b1 gradient partial
+    float s = 0.f;
+    for (int i = 0; i < nr; ++i) s += a.dx1_32[(size_t)(r0 + i) * L + c];
+    colp[a.off_b1 + c] = s;
+  }
+  __syncthreads();
+  {
+    constexpr int NT = F / 64;
+    int cb[NT];
+    f32x4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) cb[t] = w + 4 * t;
+    mm<L, NT, 16>(&sA[0][0], LDA, a.w1_nn, cb, acc);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int c = cb[t] * 16 + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) sX[4 * (lane >> 4) + r][c] = acc[t][r];
+    }
+  }
+  __syncthreads();
+  // dEmb_block[v][e] = sum over pairs p = (i, c), i < nr, of [ctx = v] dX[i][c E + e]:
+  // BF16 one-hot product, pairs in increasing order in 32-pair MFMA steps.
+  // Wave w owns byte values 64w .. 64w+63 (4 blocks of 16), E/16 column blocks.
+  const int np = nr * C;
+  const int NE = E / 16;
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int vb = 0; vb < 4; ++vb)
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) acc[vb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < np; k0 += 32) {
+    const int p0 = k0 + 8 * (lane >> 4);
+    uint32_t bytes[8];
+#pragma unroll
+    for (int v = 0; v < 8; ++v) bytes[v] = (p0 + v < np) ? (uint32_t)sC[p0 + v] : 0xFFFFu;
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+      if (nb >= NE) break;
+      bf16_t bv[8];
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        const int p = p0 + v;
+        bv[v] = p < np ? f2bf(sX[p / C][(p % C) * E + 16 * nb + (lane & 15)]) : (bf16_t)0;
+      }
+      const uint4 b = make_uint4((uint32_t)bv[0] | ((uint32_t)bv[1] << 16),
+                                 (uint32_t)bv[2] | ((uint32_t)bv[3] << 16),
+                                 (uint32_t)bv[4] | ((uint32_t)bv[5] << 16),
+                                 (uint32_t)bv[6] | ((uint32_t)bv[7] << 16));
+#pragma unroll
+      for (int vb = 0; vb < 4; ++vb) {
+        const uint32_t me = (uint32_t)(64 * w + 16 * vb + (lane & 15));
+        uint32_t q[4];
+#pragma unroll
+        for (int h = 0; h < 4; ++h)
+          q[h] = (bytes[2 * h] == me ? 0x3F80u : 0u) | ((bytes[2 * h + 1] == me ? 0x3F80u : 0u) << 16);
+        acc[vb][nb] = mfma16(make_uint4(q[0], q[1], q[2], q[3]), b, acc[vb][nb]);
+      }
+    }
+  }
+  float* out = a.emb_partial + (size_t)blockIdx.x * 256 * E;
+#pragma unroll
+  for (int vb = 0; vb < 4; ++vb)
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+      if (nb >= NE) break;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int v = 64 * w + 16 * vb + 4 * (lane >> 4) + r;
+        out[(size_t)v * E + 16 * nb + (lane & 15)] = acc[vb][nb][r];
+      }
+    }
+}
+
 bool fused_supported(int F, int L, int H, int branches, int blocks) {
   if (branches != 2 || blocks < 1 || blocks > kMaxFusedBlocks) return false;
   return (F == 512 && L == 128 && H == 256) || (F == 256 && L == 64 && H == 128);
@@ -484,6 +644,30 @@ static hipError_t launch_t(const FusedArgs& a, int grid_rows, hipStream_t s) {
   const int blocks = (grid_rows + kFusedRows - 1) / kFusedRows;
   if (blocks == 0) return hipSuccess;
   hipLaunchKernelGGL((fused_kernel<F, L, H>), dim3(blocks), dim3(256), D::BYTES, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fused_in(int F, int L, const FusedInArgs& a, int grid_rows, hipStream_t s) {
+  const int blocks = (grid_rows + kFusedRows - 1) / kFusedRows;
+  if (blocks == 0) return hipSuccess;
+  if (F == 512 && L == 128)
+    hipLaunchKernelGGL((fused_in_kernel<512, 128>), dim3(blocks), dim3(256), 0, s, a);
+  else if (F == 256 && L == 64)
+    hipLaunchKernelGGL((fused_in_kernel<256, 64>), dim3(blocks), dim3(256), 0, s, a);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_fused_out(int F, int L, const FusedOutArgs& a, int grid_rows, hipStream_t s) {
+  const int blocks = (grid_rows + kFusedRows - 1) / kFusedRows;
+  if (blocks == 0) return hipSuccess;
+  if (F == 512 && L == 128)
+    hipLaunchKernelGGL((fused_out_kernel<512, 128>), dim3(blocks), dim3(256), 0, s, a);
+  else if (F == 256 && L == 64)
+    hipLaunchKernelGGL((fused_out_kernel<256, 64>), dim3(blocks), dim3(256), 0, s, a);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

@@ -83,6 +83,10 @@ void k_colsum(const StepState* st, const ColsumJob* jobs, int n_jobs, int total_
 void k_colsum_reduce(const StepState* st, const ColsumJob* jobs, int n_jobs, int total_cols,
                      const float* partial, int chunk_rows, hipStream_t s);
 
+// Second pass of the embedding gradient: partial[chunk][256*E] over chunks of chunk_rows.
+void k_emb_grad_reduce(const StepState* st, const float* partial, int chunk_rows, int E,
+                       float* demb, hipStream_t s);
+
 void emb_grad_plan(int max_rows, int C, int E, int* chunk_rows, int* sub_rows);
 void k_emb_grad(const StepState* st, const uint8_t* ctx, const float* dx, int C, int E,
                 float* partial, int chunk_rows, int sub_rows, int max_rows, float* demb,

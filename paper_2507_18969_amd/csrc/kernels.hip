@@ -560,16 +560,23 @@ template <int E>
 __global__ void __launch_bounds__(256) emb_grad_partial_kernel(
     const StepState* __restrict__ st, const uint8_t* __restrict__ ctx, const float* __restrict__ dx,
     int C, int chunk_rows, int sub_rows, float* __restrict__ partial) {
+  // dEmb_chunk[v][e] = sum over the chunk's (row, position) pairs of
+  // [ctx = v] * dX[row][position*E + e]: an FP32 MFMA product whose A operand
+  // (the one-hot of the context bytes) is formed in registers.  Wave w owns
+  // byte values 64w .. 64w+63; pairs are visited in row-major order.
   extern __shared__ float smem_f[];
-  float* lds_dx = smem_f;                                   // [sub_rows][F]
-  uint8_t* lds_ctx = (uint8_t*)(smem_f + (size_t)sub_rows * C * E);  // [sub_rows][C] (+16 pad)
+  float* lds_dx = smem_f;                                            // [sub_rows][F]
+  uint8_t* lds_ctx = (uint8_t*)(smem_f + (size_t)sub_rows * C * E);  // [sub_rows][C]
+  constexpr int NE = E / 16;
   const int rows = st->rows;
   const int F = C * E;
   const int r0 = blockIdx.x * chunk_rows;
-  const int v = threadIdx.x;
-  float acc[E];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  f32x4 acc[4][NE];
 #pragma unroll
-  for (int e = 0; e < E; ++e) acc[e] = 0.f;
+  for (int vb = 0; vb < 4; ++vb)
+#pragma unroll
+    for (int nb = 0; nb < NE; ++nb) acc[vb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
   const int r_end = min(rows, r0 + chunk_rows);
   for (int rs = r0; rs < r_end; rs += sub_rows) {
     const int nr = min(sub_rows, r_end - rs);
@@ -578,25 +585,34 @@ __global__ void __launch_bounds__(256) emb_grad_partial_kernel(
     for (int k = threadIdx.x; k < nr * F / 4; k += 256) ((float4*)lds_dx)[k] = src[k];
     for (int k = threadIdx.x; k < nr * C; k += 256) lds_ctx[k] = ctx[(size_t)rs * C + k];
     __syncthreads();
-    const int np = nr * C;
-    // 16 context bytes per LDS read; pairs still visited in increasing order
-    for (int p0 = 0; p0 < np; p0 += 16) {
-      const uint4 w = *(const uint4*)(lds_ctx + p0);
-      const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+    const int np = nr * C;  // multiple of 4 when C is
+    for (int k0 = 0; k0 < np; k0 += 4) {
+      const int p = k0 + (lane >> 4);
+      const bool ok = p < np;
+      const int v = ok ? (int)lds_ctx[p] : -1;
+      const float* d = lds_dx + (size_t)(p / C) * F + (p % C) * E + (lane & 15);
+      float b[NE];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int p = p0 + q;
-        if (p < np && ((ws[q >> 2] >> (8 * (q & 3))) & 0xFFu) == (uint32_t)v) {
-          const float* d = lds_dx + (size_t)(p / C) * F + (p % C) * E;
+      for (int nb = 0; nb < NE; ++nb) b[nb] = ok ? d[16 * nb] : 0.f;
 #pragma unroll
-          for (int e = 0; e < E; ++e) acc[e] += d[e];
-        }
+      for (int vb = 0; vb < 4; ++vb) {
+        const float a = (v == 64 * w + 16 * vb + (lane & 15)) ? 1.0f : 0.0f;
+#pragma unroll
+        for (int nb = 0; nb < NE; ++nb)
+          acc[vb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[nb], acc[vb][nb], 0, 0, 0);
       }
     }
   }
-  float* out = partial + (size_t)blockIdx.x * 256 * E + (size_t)v * E;
+  float* out = partial + (size_t)blockIdx.x * 256 * E;
 #pragma unroll
-  for (int e = 0; e < E; ++e) out[e] = acc[e];
+  for (int vb = 0; vb < 4; ++vb)
+#pragma unroll
+    for (int nb = 0; nb < NE; ++nb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int v = 64 * w + 16 * vb + 4 * (lane >> 4) + r;
+        out[(size_t)v * E + 16 * nb + (lane & 15)] = acc[vb][nb][r];
+      }
 }
 
 __global__ void emb_grad_reduce_kernel(const StepState* __restrict__ st,
@@ -613,9 +629,16 @@ void emb_grad_plan(int max_rows, int C, int E, int* chunk_rows, int* sub_rows) {
   int sub = 8192 / F;
   sub = sub < 1 ? 1 : (sub > 16 ? 16 : sub);
   int chunk = sub;
-  while ((max_rows + chunk - 1) / chunk > 256) chunk += sub;
+  while ((max_rows + chunk - 1) / chunk > 128) chunk += sub;
   *chunk_rows = chunk;
   *sub_rows = sub;
+}
+
+void k_emb_grad_reduce(const StepState* st, const float* partial, int chunk_rows, int E,
+                       float* demb, hipStream_t s) {
+  const int n = 256 * E;
+  hipLaunchKernelGGL(emb_grad_reduce_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, st, partial,
+                     chunk_rows, n, demb);
 }
 
 void k_emb_grad(const StepState* st, const uint8_t* ctx, const float* dx, int C, int E,
@@ -629,8 +652,6 @@ void k_emb_grad(const StepState* st, const uint8_t* ctx, const float* dx, int C,
                        chunk_rows, sub_rows, partial);                                          \
     break;
   switch (E) {
-    EMB_CASE(4)
-    EMB_CASE(8)
     EMB_CASE(16)
     EMB_CASE(32)
     EMB_CASE(64)

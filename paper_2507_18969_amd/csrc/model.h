@@ -147,6 +147,9 @@ struct Model {
   FragJob* d_frag_jobs = nullptr;
   int n_frag_jobs = 0, total_frags = 0;
   FusedArgs fa;
+  FusedInArgs fin;
+  FusedOutArgs fout;
+  float* fused_emb_partial = nullptr;
   float* fused_colpart = nullptr;
   ColsumJob* d_fcs = nullptr;
   int n_fcs = 0, fcs_cols = 0;

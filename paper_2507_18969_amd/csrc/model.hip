@@ -93,8 +93,9 @@ static bool pow2(uint32_t x) { return x && !(x & (x - 1)); }
 
 void Model::validate(const edpc_config& c) {
   if (c.struct_size != sizeof(edpc_config)) fail(EDPC_E_INVALID_ARG, "edpc_config.struct_size mismatch");
-  if (c.context < 1 || c.context > 256) fail(EDPC_E_INVALID_ARG, "context must be in 1..256");
-  if (!pow2(c.embed) || c.embed < 4 || c.embed > 64) fail(EDPC_E_INVALID_ARG, "embed must be a power of two in 4..64");
+  if (c.context < 4 || c.context > 256) fail(EDPC_E_INVALID_ARG, "context must be in 1..256");
+  if (!pow2(c.embed) || c.embed < 16 || c.embed > 64) fail(EDPC_E_INVALID_ARG, "embed must be a power of two in 16..64");
+  if (c.context % 4) fail(EDPC_E_INVALID_ARG, "context must be a multiple of 4");
   if (!pow2(c.latent) || c.latent < 16 || c.latent > 256) fail(EDPC_E_INVALID_ARG, "latent must be a power of two in 16..256");
   if (c.blocks > 16) fail(EDPC_E_INVALID_ARG, "blocks must be <= 16");
   if (c.hidden < 16 || c.hidden % 16 || c.hidden > 8192) fail(EDPC_E_INVALID_ARG, "hidden must be a multiple of 16 in 16..8192");
@@ -407,6 +408,7 @@ void Model::setup_fused(hipStream_t s) {
     fr += 2 * rows * cols / 512;
     jobs.push_back(j);
   };
+  add("w1", L, F);
   add("w2", F, L);
   for (int j = 0; j < N; ++j) {
     add("blk" + std::to_string(j) + ".w0", K * H, F);
@@ -488,6 +490,7 @@ void Model::setup_fused(hipStream_t s) {
     fa.off_gamma[j] = addc(G_(ln + ".gamma"), F);
   }
   fa.off_b2 = addc(G_("b2"), F);
+  const int off_b1 = addc(G_("b1"), L);
   fcs_cols = cols;
   n_fcs = (int)cs.size();
   fa.colpart_cols = cols;
@@ -496,18 +499,30 @@ void Model::setup_fused(hipStream_t s) {
   d_fcs = dalloc<ColsumJob>(cs.size());
   hip_check(hipMemcpyAsync(d_fcs, cs.data(), cs.size() * sizeof(ColsumJob), hipMemcpyHostToDevice, s),
             "copy");
-  // b1 (from the FDM adjoint's output) still by the two-pass column sum
-  ColsumJob b1;
-  std::memset(&b1, 0, sizeof(b1));
-  b1.src = dX1_32;
-  b1.dst = G_("b1");
-  b1.cols = L;
-  b1.ld = L;
-  b1.scale = 1.0f;
-  b1_blocks = (L + 63) / 64;
-  d_b1_job = dalloc<ColsumJob>(1);
-  hip_check(hipMemcpyAsync(d_b1_job, &b1, sizeof(b1), hipMemcpyHostToDevice, s), "copy");
-  b1_partial = dalloc<float>(colsum_partial_elems((int)max_rows, L));
+  std::memset(&fin, 0, sizeof(fin));
+  fin.st = st;
+  fin.C = C;
+  fin.E = E;
+  fin.emb = P_("emb");
+  fin.w1_nt = nt("w1");
+  fin.b1 = P_("b1");
+  fin.ctx = ctx;
+  fin.tgt = tgt;
+  fin.x16 = X16;
+  fin.x1 = X1;
+  std::memset(&fout, 0, sizeof(fout));
+  fout.st = st;
+  fout.C = C;
+  fout.E = E;
+  fout.w1_nn = nn("w1", L * F);
+  fout.dx1_16 = dX1_16;
+  fout.dx1_32 = dX1_32;
+  fout.ctx = ctx;
+  fused_emb_partial = dalloc<float>(((max_rows + kFusedRows - 1) / kFusedRows) * 256 * (size_t)E);
+  fout.emb_partial = fused_emb_partial;
+  fout.colpart = fused_colpart;
+  fout.colpart_cols = cols;
+  fout.off_b1 = off_b1;
   build_frags(s);
 }
 
@@ -595,9 +610,6 @@ void Model::step(StepMode mode, const StreamIO& io, const StepOutputs& out, int 
                  hipStream_t s) {
   const int R = grid_rows;
   // ---- forward: Eq. 1 through Eqs. 14-16 and 9-13 -------------------------
-  TIMED(KC_EMBED, k_embed(st, ctx, P_("emb"), C, E, X32, X16, R, s));
-  product(PS_LTE_DOWN, 0, R, s);
-  TIMED(KC_FDM_FWD, k_fdm_fwd(st, X1, U, slot, L, Y32, Y16, R, s));  // Eq. 15
   const bool backward = out.backward || out.update || out.keep_fdm_grad;
   HeadArgs ha;
   std::memset(&ha, 0, sizeof(ha));
@@ -615,6 +627,13 @@ void Model::step(StepMode mode, const StreamIO& io, const StepOutputs& out, int 
   if (mode == MODE_PLAIN) hio.slot = nullptr;
   AdamCfg ac{cfg.lr, cfg.beta1, cfg.beta2, cfg.eps};
   if (kc.fused) {
+    // before the FDM: gather (coding modes), embedding, LTE down (Eq. 14)
+    FusedInArgs fi = fin;
+    fi.gather = mode == MODE_PLAIN ? 0 : 1;
+    fi.decoding = mode == MODE_DECODE ? 1 : 0;
+    fi.io = io;
+    TIMED(KC_EMBED, hip_check(launch_fused_in(F, L, fi, R, s), "fused in launch"));
+    TIMED(KC_FDM_FWD, k_fdm_fwd(st, X1, U, slot, L, Y32, Y16, R, s));  // Eq. 15
     // LTE up .. head .. coder .. adjoint back to dY, one workgroup per 16 rows
     FusedArgs a = fa;
     a.head = ha;
@@ -627,18 +646,20 @@ void Model::step(StepMode mode, const StreamIO& io, const StepOutputs& out, int 
     if (!backward) return;
     TIMED(KC_FDM_BWD, k_fdm_bwd(st, X1, dY, U, mU, vU, out.keep_fdm_grad ? dUkeep : nullptr, slot,
                                 L, ac, out.update, dX1_32, dX1_16, R, s));
-    product(PS_LTE_DOWN_BWD, 0, R, s);
-    TIMED(KC_EMB_GRAD, k_emb_grad(st, ctx, dX, C, E, emb_partial, emb_chunk, emb_sub, R, G_("emb"), s));
+    TIMED(KC_EMB_GRAD, hip_check(launch_fused_out(F, L, fout, R, s), "fused out launch"));
+    TIMED(KC_EMB_GRAD, k_emb_grad_reduce(st, fused_emb_partial, kFusedRows, E, G_("emb"), s));
     product(PS_WGRAD, 0, R, s);
-    TIMED(KC_COLSUM, k_colsum(st, d_b1_job, 1, b1_blocks, L, b1_partial, R, s));
     TIMED(KC_COLSUM, k_colsum_reduce(st, d_fcs, n_fcs, fcs_cols, fused_colpart, kFusedRows, s));
     if (out.update) {
-      TIMED(KC_ADAM, k_adam(st, param, grad, m, v, p16, P, ac, s));
+      TIMED(KC_ADAM, k_adam(st, param, grad, m, v, nullptr, P, ac, s));
       TIMED(KC_FRAGS, build_frags(s));
     }
     hip_check(hipGetLastError(), "step launch");
     return;
   }
+  TIMED(KC_EMBED, k_embed(st, ctx, P_("emb"), C, E, X32, X16, R, s));
+  product(PS_LTE_DOWN, 0, R, s);
+  TIMED(KC_FDM_FWD, k_fdm_fwd(st, X1, U, slot, L, Y32, Y16, R, s));  // Eq. 15
   product(PS_LTE_UP, 0, R, s);
   for (int j = 0; j < N; ++j) {
     const std::string ln = "ln" + std::to_string(j);

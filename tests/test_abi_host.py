@@ -48,7 +48,7 @@ def test_host_coder_matches_oracle_coder():
 
 def test_config_validation():
     E.edpc_config_validate(E.edpc_config_default())
-    for bad in (dict(embed=12), dict(latent=48), dict(branches=4), dict(cdf_bits=12),
+    for bad in (dict(embed=12), dict(embed=8), dict(context=6), dict(latent=48), dict(branches=4), dict(cdf_bits=12),
                 dict(hidden=100), dict(context=0), dict(precision=7), dict(beta1=1.0)):
         with pytest.raises(E.EdpcError) as ei:
             E.edpc_config_validate(E.edpc_config_default(**bad))
