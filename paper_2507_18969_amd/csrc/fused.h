@@ -32,6 +32,19 @@ struct FragJob {
 };
 void k_build_frags(const FragJob* jobs, int n_jobs, int total_frags, hipStream_t s);
 
+// Adam over the shared parameters fused with the fragment-copy refresh:
+// matrix jobs are walked in 8 x 8 blocks (both fragment orientations written
+// from registers), the other tensors element-wise in groups of 8.
+struct AdamJob {
+  size_t off;        // element offset in the flat parameter buffers
+  int rows, cols;    // matrix (cols > 0) or element range (cols == 0, rows = count)
+  uint4* nt;         // fragment copies (matrix jobs)
+  uint4* nn;
+  int item_begin;    // first work item of this job
+};
+void k_adam_frags(const StepState* st, const AdamJob* jobs, int n_jobs, int total_items,
+                  float* p, const float* g, float* m, float* v, AdamCfg ac, hipStream_t s);
+
 struct FusedArgs {
   const StepState* st;
   int n_blocks;  // refinement blocks

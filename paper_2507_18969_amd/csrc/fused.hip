@@ -51,6 +51,105 @@ void k_build_frags(const FragJob* jobs, int n_jobs, int total_frags, hipStream_t
                      jobs, n_jobs, total_frags);
 }
 
+// in[i] holds 8 bf16 of row i; out[j] receives column j
+__device__ __forceinline__ void transpose8x8(const uint4* in, uint4* out) {
+  const uint32_t* w = (const uint32_t*)in;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int q = j >> 1;
+    const uint32_t sel = (j & 1) ? 0x07060302u : 0x05040100u;
+    uint32_t o[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      o[k] = __builtin_amdgcn_perm(w[4 * (2 * k + 1) + q], w[4 * (2 * k) + q], sel);
+    out[j] = make_uint4(o[0], o[1], o[2], o[3]);
+  }
+}
+
+__device__ __forceinline__ void adam8(float* pp, const float* gp, float* mp, float* vp, float lr_bc,
+                                      float inv_bc2, const AdamCfg& ac, float out[8]) {
+  float4 p4[2], g4[2], m4[2], v4[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    p4[h] = ((const float4*)pp)[h];
+    g4[h] = ((const float4*)gp)[h];
+    m4[h] = ((const float4*)mp)[h];
+    v4[h] = ((const float4*)vp)[h];
+  }
+  float* P = (float*)p4;
+  float* G = (float*)g4;
+  float* M = (float*)m4;
+  float* V = (float*)v4;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    M[k] = ac.beta1 * M[k] + (1.0f - ac.beta1) * G[k];
+    V[k] = ac.beta2 * V[k] + (1.0f - ac.beta2) * G[k] * G[k];
+    P[k] = P[k] - lr_bc * M[k] / (sqrtf(V[k] * inv_bc2) + ac.eps);
+    out[k] = P[k];
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    ((float4*)pp)[h] = p4[h];
+    ((float4*)mp)[h] = m4[h];
+    ((float4*)vp)[h] = v4[h];
+  }
+}
+
+__global__ void __launch_bounds__(256) adam_frags_kernel(const StepState* __restrict__ st,
+                                                         const AdamJob* __restrict__ jobs, int n_jobs,
+                                                         int total_items, float* __restrict__ p,
+                                                         const float* __restrict__ g,
+                                                         float* __restrict__ m, float* __restrict__ v,
+                                                         AdamCfg ac) {
+  const int it = blockIdx.x * blockDim.x + threadIdx.x;
+  if (it >= total_items) return;
+  int j = 0;
+  while (j + 1 < n_jobs && it >= jobs[j + 1].item_begin) ++j;
+  const AdamJob jb = jobs[j];
+  const int local = it - jb.item_begin;
+  const float lr_bc = ac.lr / st->bc1;
+  const float inv_bc2 = 1.0f / st->bc2;
+  float nv[8];
+  if (jb.cols == 0) {  // element range, 8 per item
+    const size_t o = jb.off + (size_t)local * 8;
+    adam8(p + o, g + o, m + o, v + o, lr_bc, inv_bc2, ac, nv);
+    return;
+  }
+  const int cb8 = jb.cols / 8;
+  const int rb = local / cb8, cb = local % cb8;
+  const int r0 = rb * 8, c0 = cb * 8;
+  uint4 rowv[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const size_t o = jb.off + (size_t)(r0 + q) * jb.cols + c0;
+    adam8(p + o, g + o, m + o, v + o, lr_bc, inv_bc2, ac, nv);
+    rowv[q] = make_uint4((uint32_t)f2bf(nv[0]) | ((uint32_t)f2bf(nv[1]) << 16),
+                         (uint32_t)f2bf(nv[2]) | ((uint32_t)f2bf(nv[3]) << 16),
+                         (uint32_t)f2bf(nv[4]) | ((uint32_t)f2bf(nv[5]) << 16),
+                         (uint32_t)f2bf(nv[6]) | ((uint32_t)f2bf(nv[7]) << 16));
+    // nt fragment (nb = row/16, kb = col/32), lane = row%16 + 16*((col%32)/8)
+    const int row = r0 + q;
+    const size_t f = (size_t)(row >> 4) * (jb.cols / 32) + (c0 >> 5);
+    jb.nt[f * 64 + (row & 15) + 16 * ((c0 & 31) >> 3)] = rowv[q];
+  }
+  uint4 colv[8];
+  transpose8x8(rowv, colv);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    // nn fragment (nb = col/16, kb = row/32), lane = col%16 + 16*((row%32)/8)
+    const int col = c0 + q;
+    const size_t f = (size_t)(col >> 4) * (jb.rows / 32) + (r0 >> 5);
+    jb.nn[f * 64 + (col & 15) + 16 * ((r0 & 31) >> 3)] = colv[q];
+  }
+}
+
+void k_adam_frags(const StepState* st, const AdamJob* jobs, int n_jobs, int total_items, float* p,
+                  const float* g, float* m, float* v, AdamCfg ac, hipStream_t s) {
+  if (total_items == 0) return;
+  hipLaunchKernelGGL(adam_frags_kernel, dim3((total_items + 255) / 256), dim3(256), 0, s, st, jobs,
+                     n_jobs, total_items, p, g, m, v, ac);
+}
+
 // ---------------------------------------------------------------------------
 // Row-block products
 // ---------------------------------------------------------------------------

@@ -150,6 +150,8 @@ struct Model {
   FusedInArgs fin;
   FusedOutArgs fout;
   float* fused_emb_partial = nullptr;
+  AdamJob* d_adam_jobs = nullptr;
+  int n_adam_jobs = 0, adam_items = 0;
   float* fused_colpart = nullptr;
   ColsumJob* d_fcs = nullptr;
   int n_fcs = 0, fcs_cols = 0;

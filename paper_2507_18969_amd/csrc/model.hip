@@ -3,6 +3,7 @@
 #include "model.h"
 
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 
 namespace edpc {
@@ -146,7 +147,11 @@ KernelConfig Model::default_config(const edpc_config& c, size_t rows) {
     wg.push_back({KH, F});
   }
   k.tile[PS_WGRAD] = pick_tile(rows, wg, 512);
-  k.fused = c.precision == EDPC_BF16 &&
+  // The row-block fused step streams every weight once per 16-row block; at
+  // these batch sizes that is slower than the layer-by-layer products, so it
+  // is opt-in (EDPC_FUSED=1 in the encoder's environment).
+  const char* env = std::getenv("EDPC_FUSED");
+  k.fused = env && env[0] == '1' && c.precision == EDPC_BF16 &&
             fused_supported(F, L, H, (int)c.branches, (int)c.blocks);
   return k;
 }
@@ -422,6 +427,40 @@ void Model::setup_fused(hipStream_t s) {
   }
   n_frag_jobs = (int)jobs.size();
   total_frags = fr;
+  {  // Adam jobs: matrices with fragment copies in 8 x 8 blocks, the rest by 8s
+    std::vector<AdamJob> aj;
+    int items = 0;
+    std::vector<char> covered(tens.size(), 0);
+    for (const auto& fj : jobs) {
+      AdamJob a;
+      a.off = (size_t)(fj.src - param);
+      a.rows = fj.rows;
+      a.cols = fj.cols;
+      a.nt = fj.nt;
+      a.nn = fj.nn;
+      a.item_begin = items;
+      items += (fj.rows / 8) * (fj.cols / 8);
+      aj.push_back(a);
+      for (size_t t = 0; t < tens.size(); ++t)
+        if (tens[t].off >= a.off && tens[t].off < a.off + (size_t)a.rows * a.cols) covered[t] = 1;
+    }
+    for (size_t t = 0; t < tens.size(); ++t) {
+      if (covered[t]) continue;
+      AdamJob a;
+      a.off = tens[t].off;
+      a.rows = (int)((tens[t].numel + 7) / 8) * 8;  // tensors start 64-aligned: padding is inert
+      a.cols = 0;
+      a.nt = a.nn = nullptr;
+      a.item_begin = items;
+      items += a.rows / 8;
+      aj.push_back(a);
+    }
+    n_adam_jobs = (int)aj.size();
+    adam_items = items;
+    d_adam_jobs = dalloc<AdamJob>(aj.size());
+    hip_check(hipMemcpyAsync(d_adam_jobs, aj.data(), aj.size() * sizeof(AdamJob),
+                             hipMemcpyHostToDevice, s), "copy");
+  }
   d_frag_jobs = dalloc<FragJob>(jobs.size());
   hip_check(hipMemcpyAsync(d_frag_jobs, jobs.data(), jobs.size() * sizeof(FragJob),
                            hipMemcpyHostToDevice, s), "copy");
@@ -650,10 +689,8 @@ void Model::step(StepMode mode, const StreamIO& io, const StepOutputs& out, int 
     TIMED(KC_EMB_GRAD, k_emb_grad_reduce(st, fused_emb_partial, kFusedRows, E, G_("emb"), s));
     product(PS_WGRAD, 0, R, s);
     TIMED(KC_COLSUM, k_colsum_reduce(st, d_fcs, n_fcs, fcs_cols, fused_colpart, kFusedRows, s));
-    if (out.update) {
-      TIMED(KC_ADAM, k_adam(st, param, grad, m, v, nullptr, P, ac, s));
-      TIMED(KC_FRAGS, build_frags(s));
-    }
+    if (out.update)  // Adam fused with the refresh of the fragment copies
+      TIMED(KC_ADAM, k_adam_frags(st, d_adam_jobs, n_adam_jobs, adam_items, param, grad, m, v, ac, s));
     hip_check(hipGetLastError(), "step launch");
     return;
   }

@@ -333,3 +333,18 @@ def test_graph_replay_matches_direct_launches(E, monkeypatch):
     monkeypatch.setenv("EDPC_GRAPH_STEPS", "0")
     out, _ = E.edpc_decode(graph)
     assert out.cpu().numpy().tobytes() == flat.tobytes()
+
+
+def test_fused_rowblock_path_parity(E, monkeypatch):
+    # the opt-in row-block fused BF16 step: one-step parity with the oracle and
+    # a round trip whose container records the fused kernel configuration
+    monkeypatch.setenv("EDPC_FUSED", "1")
+    om, m, ctx, tgt = _step_case(E, SMALL, "bf16", rows=8, pos=16, prefix=17)
+    _compare_step(E, om, m, ctx, tgt, p_tol=2e-3, g_rtol=3e-2)
+    data, lens = gen.make_streams("small", prefix=300, n_streams=8)
+    cont = _encode(E, lib_cfg(E, SMALL, "bf16"), data, lens)
+    kid = int.from_bytes(cont[76:84].cpu().numpy().tobytes(), "little")
+    assert (kid >> 47) & 1 == 1
+    monkeypatch.delenv("EDPC_FUSED")
+    out, _ = E.edpc_decode(cont)
+    assert out.cpu().numpy().tobytes() == data.tobytes()
