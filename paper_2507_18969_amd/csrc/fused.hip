@@ -153,6 +153,10 @@ void k_adam_frags(const StepState* st, const AdamJob* jobs, int n_jobs, int tota
 // ---------------------------------------------------------------------------
 // Row-block products
 // ---------------------------------------------------------------------------
+// Word 3 of a raw buffer resource on gfx9-family GPUs (32-bit data format,
+// no swizzle, no index stride).
+constexpr int kBufferWord3 = 0x00020000;
+
 __device__ __forceinline__ f32x4 mfma16(uint4 a, uint4 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
                                                 __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
@@ -160,38 +164,88 @@ __device__ __forceinline__ f32x4 mfma16(uint4 a, uint4 b, f32x4 c) {
 
 // acc[t] = A (16 rows in LDS, bf16, row stride lda, K columns) x fragments of
 // column block cb[t] (fragment base + cb*K/32*64 uint4), for the NT column
-// blocks of this wave.  Fragments stream through a ring of D registers.
-template <int K, int NT, int D>
+// blocks of this wave (cb must be wave-uniform).  The wave's fragments, taken
+// in the order i = kb * NT + t, stream in batches of B buffer loads issued back
+// to back; batch b + 1 is issued before batch b feeds the MFMAs, so up to 2B
+// loads are in flight.  Each load takes the lane offset from one VGPR and the
+// fragment offset from an SGPR, so in-flight loads cost no address registers.
+// The scheduling barriers keep the compiler from sinking the loads next to
+// their uses.
+template <int K, int NT, int B, typename Between>
 __device__ __forceinline__ void mm(const bf16_t* sA, int lda, const uint4* __restrict__ base,
-                                   const int (&cb)[NT], f32x4 (&acc)[NT]) {
+                                   const int (&cb)[NT], f32x4 (&acc)[NT], Between&& between) {
   constexpr int KB = K / 32;
   constexpr int TOT = KB * NT;
-  constexpr int DD = D < TOT ? D : TOT;
+  constexpr int BB = B < TOT ? B : TOT;
+  constexpr int NBT = (TOT + BB - 1) / BB;
   const int lane = threadIdx.x & 63;
-  const uint4* ptr[NT];
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, 0x7FFFFFFF, kBufferWord3);
+  const int voff = lane * 16;
 #pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    ptr[t] = base + (size_t)cb[t] * KB * 64 + lane;
-    acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-  }
-  uint4 ring[DD];
+  for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  auto frag = [&](int i) -> uint4 {
+    const int soff = (cb[i % NT] * KB + i / NT) * 1024;
+    return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, 0));
+  };
+  const bf16_t* arow = sA + (lane & 15) * lda + 8 * (lane >> 4);
+  uint4 buf[2][BB];
 #pragma unroll
-  for (int i = 0; i < DD; ++i) ring[i] = ptr[i % NT][(i / NT) * 64];
+  for (int q = 0; q < BB; ++q) buf[0][q] = frag(q);
+  // work that only needs the LDS state left by the previous stage (copies of
+  // its results to global memory) goes behind the first batch, so the
+  // fragment waits do not include its stores
+  __builtin_amdgcn_sched_barrier(0);
+  between();
+  __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-  for (int kb = 0; kb < KB; ++kb) {
-    const uint4 a = *(const uint4*)(sA + (lane & 15) * lda + kb * 32 + 8 * (lane >> 4));
+  for (int b = 0; b < NBT; ++b) {
+    if (b + 1 < NBT) {
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const int i = kb * NT + t;
-      acc[t] = mfma16(a, ring[i % DD], acc[t]);
-      if (i + DD < TOT) ring[i % DD] = ptr[(i + DD) % NT][((i + DD) / NT) * 64];
+      for (int q = 0; q < BB; ++q) {
+        const int i = (b + 1) * BB + q;
+        if (i < TOT) buf[(b + 1) & 1][q] = frag(i);
+      }
     }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int q = 0; q < BB; ++q) {
+      const int i = b * BB + q;
+      if (i < TOT) {
+        const uint4 av = *(const uint4*)(arow + (i / NT) * 32);
+        acc[i % NT] = mfma16(av, buf[b & 1][q], acc[i % NT]);
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
+
+template <int K, int NT, int B>
+__device__ __forceinline__ void mm(const bf16_t* sA, int lda, const uint4* __restrict__ base,
+                                   const int (&cb)[NT], f32x4 (&acc)[NT]) {
+  mm<K, NT, B>(sA, lda, base, cb, acc, [] {});
+}
+
+constexpr int kFusedWaves = 8;  // waves of a row-block workgroup
+
+// Coder inputs of one row, staged in LDS at the start of the fused step.
+struct RowCoder {
+  RcEnc enc;       // encoder state (encode)
+  RcDec dec;       // decoder state (decode)
+  uint64_t poff;   // payload offset
+  uint64_t pcap;   // payload capacity / length
+  uint64_t off;    // stream offset (decoder output)
+  uint32_t s;      // stream index
+  int32_t tgt;     // target byte (encode / plain step)
+};
+constexpr int kFusedThreads = 64 * kFusedWaves;
+constexpr int kFusedBatch = 8;  // weight fragments per load batch and wave
 
 template <int F, int L, int H>
 struct FusedDims {
   static constexpr int BM = kFusedRows;
+  static constexpr int NW = kFusedWaves;
+  static constexpr int RPW = BM / NW;  // rows per wave in the row-wise stages
   static constexpr int H2 = 2 * H;
   static constexpr int KM0 = F > H2 ? F : H2;
   static constexpr int KMAX = KM0 > 256 ? KM0 : 256;
@@ -203,131 +257,210 @@ struct FusedDims {
   static constexpr size_t OFF_A = OFF_F + (size_t)BM * LDF * 4;
   static constexpr size_t OFF_B = OFF_A + (size_t)BM * LDA * 2;
   static constexpr size_t OFF_RED = OFF_B + (size_t)BM * LDA * 2;
-  static constexpr size_t OFF_STAT = OFF_RED + 4 * BM * 2 * 4;
-  static constexpr size_t BYTES = OFF_STAT + (size_t)kMaxFusedBlocks * BM * 2 * 4;
+  static constexpr size_t OFF_STAT = OFF_RED + (size_t)NW * BM * 2 * 4;
+  static constexpr size_t OFF_GB = OFF_STAT + (size_t)kMaxFusedBlocks * BM * 2 * 4;
+  static constexpr size_t OFF_CODE = OFF_GB + (size_t)2 * F * 4;
+  static constexpr size_t BYTES = OFF_CODE + (size_t)BM * sizeof(RowCoder);
+  static_assert(BM % NW == 0, "rows per wave");
 };
 
+// Column blocks (16 outputs each) of a product with N outputs, dealt to the
+// waves: wave w takes blocks w, w + NW, ...; a product with fewer blocks than
+// waves leaves the last waves idle.
+template <int N>
+struct ColSplit {
+  static constexpr int NCB = N / 16;
+  static_assert(N % 16 == 0 && (NCB % kFusedWaves == 0 || NCB < kFusedWaves), "column split");
+  static constexpr int NT = NCB >= kFusedWaves ? NCB / kFusedWaves : 1;
+  __device__ static bool active(int w) { return NCB >= kFusedWaves || w < NCB; }
+};
+
+// Rows [0, nr) of an LDS tile (row stride ld_l elements) to global rows
+// r0 .. r0 + nr - 1 (row stride ld_g), in 16-byte pieces over the workgroup.
+template <int COLS, typename T>
+__device__ __forceinline__ void copy_rows(const T* lds, int ld_l, T* g, int ld_g, int r0, int nr) {
+  constexpr int V = 16 / sizeof(T);
+  constexpr int CH = COLS / V;
+  for (int idx = threadIdx.x; idx < nr * CH; idx += kFusedThreads) {
+    const int i = idx / CH, q = idx - i * CH;
+    *(uint4*)(g + (r0 + i) * ld_g + q * V) = *(const uint4*)(lds + i * ld_l + q * V);
+  }
+}
+
+// Column sums over rows [0, nr) of an LDS tile -> one row of partials.
+template <int COLS>
+__device__ __forceinline__ void col_sums(const float* lds, int ld_l, int nr, float* out) {
+  for (int c = threadIdx.x; c < COLS; c += kFusedThreads) {
+    float v[kFusedRows];
+#pragma unroll
+    for (int i = 0; i < kFusedRows; ++i) v[i] = i < nr ? lds[i * ld_l + c] : 0.f;
+    float s = 0.f;
+#pragma unroll
+    for (int i = 0; i < kFusedRows; ++i) s += v[i];  // rows in order
+    out[c] = s;
+  }
+}
+
 template <int F, int L, int H>
-__global__ void __launch_bounds__(256, 1) fused_kernel(FusedArgs a) {
+__global__ void __launch_bounds__(kFusedThreads, 1) fused_kernel(FusedArgs a) {
   typedef FusedDims<F, L, H> D;
-  constexpr int BM = D::BM, H2 = D::H2, LDA = D::LDA, LDF = D::LDF, LDH = D::LDH;
+  constexpr int BM = D::BM, NW = D::NW, RPW = D::RPW, H2 = D::H2, LDA = D::LDA, LDF = D::LDF,
+                LDH = D::LDH;
+  static_assert((H / 16) % NW == 0, "branch columns per wave");
   extern __shared__ __align__(16) char smem[];
   float (*sH)[LDH] = (float (*)[LDH])(smem + D::OFF_H);      // residual stream / its adjoint
-  float (*sF)[LDF] = (float (*)[LDF])(smem + D::OFF_F);      // fp32 scratch (logits, dz, dA)
+  float (*sF)[LDF] = (float (*)[LDF])(smem + D::OFF_F);      // fp32 scratch (branches, logits, dz, dA)
   bf16_t (*sA)[LDA] = (bf16_t (*)[LDA])(smem + D::OFF_A);    // product operand
   bf16_t (*sB)[LDA] = (bf16_t (*)[LDA])(smem + D::OFF_B);    // second product operand
   float (*sRed)[BM][2] = (float (*)[BM][2])(smem + D::OFF_RED);
   float (*sStat)[BM][2] = (float (*)[BM][2])(smem + D::OFF_STAT);
+  float (*sGB)[F] = (float (*)[F])(smem + D::OFF_GB);         // LayerNorm affine gradients
+  RowCoder* sCode = (RowCoder*)(smem + D::OFF_CODE);
 
   const StepState* st = a.st;
   const int rows = st->rows;
   const int r0 = blockIdx.x * BM;
   if (r0 >= rows) return;
   const int nr = min(BM, rows - r0);
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index (uniform)
   const int li = 4 * (lane >> 4), lc = lane & 15;
   float* colp = a.colpart + (size_t)blockIdx.x * a.colpart_cols;
   const int NB = a.n_blocks;
+  const int mode = a.head.mode;
 
   // ---- LTE up-projection (Eq. 16): X'' = W2 Y + b2 -------------------------
-  for (int idx = tid; idx < BM * (L / 8); idx += 256) {
-    const int i = idx / (L / 8), q = idx % (L / 8);
-    uint4 v = make_uint4(0, 0, 0, 0);
-    if (i < nr) v = *(const uint4*)(a.y16 + (size_t)(r0 + i) * L + 8 * q);
-    *(uint4*)(&sA[i][8 * q]) = v;
+  if (w == NW - 1) {
+    // the last wave stages the coder inputs of the block's rows
+    if (lane < BM) {
+      RowCoder rc = {};
+      if (lane < nr) {
+        const int r = r0 + lane;
+        rc.s = a.io.slot ? a.io.slot[r] : 0u;
+        if (mode != 2 && a.head.target) rc.tgt = a.head.target[r];
+        if (mode == 1) {
+          rc.enc = a.io.enc[rc.s];
+          rc.poff = a.io.pay_off[rc.s];
+          rc.pcap = a.io.pay_cap[rc.s];
+        } else if (mode == 2) {
+          rc.dec = a.io.dec[rc.s];
+          rc.poff = a.io.pay_off[rc.s];
+          rc.pcap = a.io.pay_cap[rc.s];
+          rc.off = a.io.off[rc.s];
+        }
+      }
+      sCode[lane] = rc;
+    }
+  } else {
+    // the others stage the FDM output
+    for (int idx = tid; idx < BM * (L / 8); idx += kFusedThreads - 64) {
+      const int i = idx / (L / 8), q = idx % (L / 8);
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (i < nr) v = *(const uint4*)(a.y16 + (r0 + i) * L + 8 * q);
+      *(uint4*)(&sA[i][8 * q]) = v;
+    }
   }
   __syncthreads();
   {
-    constexpr int NT = F / 64;
+    constexpr int NT = ColSplit<F>::NT;
     int cb[NT];
     f32x4 acc[NT];
+    float bias[NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) cb[t] = w + 4 * t;
-    mm<L, NT, 16>(&sA[0][0], LDA, a.w2_nt, cb, acc);
+    for (int t = 0; t < NT; ++t) {
+      cb[t] = w + NW * t;
+      bias[t] = a.b2[cb[t] * 16 + lc];
+    }
+    mm<L, NT, kFusedBatch>(&sA[0][0], LDA, a.w2_nt, cb, acc);
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       const int c = cb[t] * 16 + lc;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = li + r;
-        const float v = acc[t][r] + a.b2[c];
-        sH[i][c] = v;
-        if (i < nr) a.hs[0][(size_t)(r0 + i) * F + c] = v;
-      }
+      for (int r = 0; r < 4; ++r) sH[li + r][c] = acc[t][r] + bias[t];
     }
   }
   __syncthreads();
 
   // ---- refinement blocks (Eqs. 9-13) ----------------------------------------
   for (int j = 0; j < NB; ++j) {
-    // LayerNorm (Eq. 9): wave w normalises rows 4w .. 4w+3
-    for (int q = 0; q < 4; ++q) {
-      const int i = 4 * w + q;
+    // LayerNorm (Eq. 9): wave w normalises rows RPW w .. RPW w + RPW - 1
+    constexpr int FV = F / 64;
+    float gmr[FV], btr[FV];
+#pragma unroll
+    for (int k = 0; k < FV; ++k) {
+      gmr[k] = a.gamma[j][lane + 64 * k];
+      btr[k] = a.beta[j][lane + 64 * k];
+    }
+    for (int q = 0; q < RPW; ++q) {
+      const int i = RPW * w + q;
       float s = 0.f;
-      for (int f = lane; f < F; f += 64) s += sH[i][f];
+#pragma unroll
+      for (int k = 0; k < FV; ++k) s += sH[i][lane + 64 * k];
       const float mu = wave_sum(s) / (float)F;
       float v2 = 0.f;
-      for (int f = lane; f < F; f += 64) {
-        const float d = sH[i][f] - mu;
+#pragma unroll
+      for (int k = 0; k < FV; ++k) {
+        const float d = sH[i][lane + 64 * k] - mu;
         v2 += d * d;
       }
       const float rs = 1.0f / sqrtf(wave_sum(v2) / (float)F + 1e-5f);
-      const float* gm = a.gamma[j];
-      const float* bt = a.beta[j];
-      for (int f = lane; f < F; f += 64) {
-        const bf16_t z = f2bf((sH[i][f] - mu) * rs * gm[f] + bt[f]);
-        sA[i][f] = z;
-        if (i < nr) a.z16[j][(size_t)(r0 + i) * F + f] = z;
+#pragma unroll
+      for (int k = 0; k < FV; ++k) {
+        const int f = lane + 64 * k;
+        sA[i][f] = f2bf((sH[i][f] - mu) * rs * gmr[k] + btr[k]);
       }
       if (lane == 0) {
         sStat[j][i][0] = mu;
         sStat[j][i][1] = rs;
-        if (i < nr) {
-          a.mean[j][r0 + i] = mu;
-          a.rstd[j][r0 + i] = rs;
-        }
       }
     }
     __syncthreads();
     {  // branches (Eq. 10), product fusion (Eq. 11), GeLU (Eq. 12)
-      constexpr int NH = H / 64;
+      constexpr int NH = ColSplit<H>::NT;
       constexpr int NT = 2 * NH;
       int cb[NT];
       f32x4 acc[NT];
+      float bias0[NH], bias1[NH];
 #pragma unroll
       for (int t = 0; t < NH; ++t) {
-        cb[t] = w + 4 * t;
-        cb[NH + t] = H / 16 + w + 4 * t;
+        cb[t] = w + NW * t;
+        cb[NH + t] = H / 16 + w + NW * t;
+        bias0[t] = a.bab[j][cb[t] * 16 + lc];
+        bias1[t] = a.bab[j][H + cb[t] * 16 + lc];
       }
-      mm<F, NT, 16>(&sA[0][0], LDA, a.wab_nt[j], cb, acc);
-      const float* bb = a.bab[j];
+      mm<F, NT, kFusedBatch>(&sA[0][0], LDA, a.wab_nt[j], cb, acc, [&] {
+        copy_rows<F>(&sA[0][0], LDA, a.z16[j], F, r0, nr);   // LayerNorm output
+        copy_rows<F>(&sH[0][0], LDH, a.hs[j], F, r0, nr);    // block input
+      });
 #pragma unroll
       for (int t = 0; t < NH; ++t) {
         const int c = cb[t] * 16 + lc;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int i = li + r;
-          const float a0 = acc[t][r] + bb[c];
-          const float a1 = acc[NH + t][r] + bb[H + c];
-          const bf16_t g = f2bf(gelu_f(a0 * a1));
-          sB[i][c] = g;
-          if (i < nr) {
-            a.abr[j][(size_t)(r0 + i) * H2 + c] = a0;
-            a.abr[j][(size_t)(r0 + i) * H2 + H + c] = a1;
-            a.g16[j][(size_t)(r0 + i) * H + c] = g;
-          }
+          const float a0 = acc[t][r] + bias0[t];
+          const float a1 = acc[NH + t][r] + bias1[t];
+          sB[i][c] = f2bf(gelu_f(a0 * a1));
+          sF[i][c] = a0;
+          sF[i][H + c] = a1;
         }
       }
     }
     __syncthreads();
     {  // output linear + residual (Eq. 13)
-      constexpr int NT = F / 64;
+      constexpr int NT = ColSplit<F>::NT;
       int cb[NT];
       f32x4 acc[NT];
+      float bias[NT];
 #pragma unroll
-      for (int t = 0; t < NT; ++t) cb[t] = w + 4 * t;
-      mm<H, NT, 16>(&sB[0][0], LDA, a.wo_nt[j], cb, acc);
-      const float* bo = a.bo[j];
+      for (int t = 0; t < NT; ++t) {
+        cb[t] = w + NW * t;
+        bias[t] = a.bo[j][cb[t] * 16 + lc];
+      }
+      mm<H, NT, kFusedBatch>(&sB[0][0], LDA, a.wo_nt[j], cb, acc, [&] {
+        copy_rows<H>(&sB[0][0], LDA, a.g16[j], H, r0, nr);     // GeLU output
+        copy_rows<H2>(&sF[0][0], LDF, a.abr[j], H2, r0, nr);   // branch values
+      });
       const bool last = j == NB - 1;
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
@@ -335,14 +468,9 @@ __global__ void __launch_bounds__(256, 1) fused_kernel(FusedArgs a) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int i = li + r;
-          const float v = acc[t][r] + bo[c] + sH[i][c];
+          const float v = acc[t][r] + bias[t] + sH[i][c];
           sH[i][c] = v;
-          if (i < nr) a.hs[j + 1][(size_t)(r0 + i) * F + c] = v;
-          if (last) {
-            const bf16_t hb = f2bf(v);
-            sA[i][c] = hb;
-            if (i < nr) a.hn16[(size_t)(r0 + i) * F + c] = hb;
-          }
+          if (last) sA[i][c] = f2bf(v);
         }
       }
     }
@@ -351,36 +479,54 @@ __global__ void __launch_bounds__(256, 1) fused_kernel(FusedArgs a) {
 
   // ---- head logits ------------------------------------------------------------
   {
-    constexpr int NT = 4;  // 256 outputs
+    constexpr int NT = ColSplit<256>::NT;
     int cb[NT];
     f32x4 acc[NT];
+    float bias[NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) cb[t] = w + 4 * t;
-    mm<F, NT, 16>(&sA[0][0], LDA, a.wh_nt, cb, acc);
+    for (int t = 0; t < NT; ++t) {
+      cb[t] = w + NW * t;
+      bias[t] = a.bh[cb[t] * 16 + lc];
+    }
+    mm<F, NT, kFusedBatch>(&sA[0][0], LDA, a.wh_nt, cb, acc, [&] {
+      copy_rows<F>(&sA[0][0], LDA, a.hn16, F, r0, nr);  // final features
+    });
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       const int c = cb[t] * 16 + lc;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) sF[li + r][c] = acc[t][r] + a.bh[c];
+      for (int r = 0; r < 4; ++r) sF[li + r][c] = acc[t][r] + bias[t];
     }
   }
   __syncthreads();
 
-  // ---- softmax, CDF, coder lane, cross-entropy adjoint (Eqs. 1-2) -------------
+  // ---- softmax, CDF, coder, cross-entropy adjoint (Eqs. 1-2) ------------------
   const bool grad = a.head.want_grad != 0;
-  for (int q = 0; q < 4; ++q) {
-    const int i = 4 * w + q;
+  const bool have_target = mode != 0 || a.head.target != nullptr;
+  int my_cx = 0, my_qx = 0, my_x = 0;
+  for (int q = 0; q < RPW; ++q) {
+    const int i = RPW * w + q;
     float d[4] = {0.f, 0.f, 0.f, 0.f};
     if (i < nr) {
       const float z[4] = {sF[i][4 * lane], sF[i][4 * lane + 1], sF[i][4 * lane + 2],
                           sF[i][4 * lane + 3]};
-      float p[4];
-      int x = 0;
-      const bool have = head_row(st, a.head, a.io, r0 + i, lane, z, p, &x);
-      if (have && grad) {
+      RowCdf c;
+      row_cdf(lane, z, c);
+      const int x = mode == 2 ? row_decode_symbol(c, sCode[i].dec.d, sCode[i].dec.range) : sCode[i].tgt;
+      int cx, qx;
+      float zx;
+      row_pick(c, z, x, &cx, &qx, &zx);
+      if (lane == q) {
+        my_cx = cx;
+        my_qx = qx;
+        my_x = x;
+        if (have_target && a.head.loss_rows) a.head.loss_rows[r0 + i] = logf(c.S) - (zx - c.m);
+      }
+      row_outputs(a.head, r0 + i, lane, c);
+      if (have_target && grad) {
         const float ir = st->inv_rows;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) d[k] = (p[k] - (4 * lane + k == x ? 1.0f : 0.0f)) * ir;
+        for (int k = 0; k < 4; ++k) d[k] = (c.p[k] - (4 * lane + k == x ? 1.0f : 0.0f)) * ir;
       }
     }
 #pragma unroll
@@ -388,24 +534,35 @@ __global__ void __launch_bounds__(256, 1) fused_kernel(FusedArgs a) {
       sF[i][4 * lane + k] = d[k];
       sA[i][4 * lane + k] = f2bf(d[k]);
     }
-    if (i < nr && grad)
-      *(ushort4*)(a.dz16 + (size_t)(r0 + i) * 256 + 4 * lane) =
-          make_ushort4(f2bf(d[0]), f2bf(d[1]), f2bf(d[2]), f2bf(d[3]));
+  }
+  // range-coder lanes: lane q of wave w codes row RPW w + q
+  const int my_i = RPW * w + lane;
+  if (lane < RPW && my_i < nr && mode != 0) {
+    const RowCoder& rc = sCode[my_i];
+    if (mode == 1) {
+      RcEnc en = rc.enc;
+      rc_encode(en, a.io.pay + rc.poff, rc.pcap, (uint32_t)my_cx, (uint32_t)my_qx);
+      a.io.enc[rc.s] = en;
+    } else {
+      RcDec de = rc.dec;
+      rc_consume(de, a.io.pay_in + rc.poff, rc.pcap, (uint32_t)my_cx, (uint32_t)(my_cx + my_qx));
+      a.io.dec[rc.s] = de;
+      a.io.dst[rc.off + (uint64_t)st->step] = (uint8_t)my_x;
+      if (a.head.target_out) a.head.target_out[r0 + my_i] = (uint8_t)my_x;
+    }
   }
   if (!grad) return;
   __syncthreads();
-  {  // bias gradient of the head: column sums of dz over this block's rows
-    float s = 0.f;
-    for (int i = 0; i < nr; ++i) s += sF[i][tid];
-    colp[a.off_bh + tid] = s;
-  }
   {  // dH_N = dz Wh
-    constexpr int NT = F / 64;
+    constexpr int NT = ColSplit<F>::NT;
     int cb[NT];
     f32x4 acc[NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) cb[t] = w + 4 * t;
-    mm<256, NT, 16>(&sA[0][0], LDA, a.wh_nn, cb, acc);
+    for (int t = 0; t < NT; ++t) cb[t] = w + NW * t;
+    mm<256, NT, kFusedBatch>(&sA[0][0], LDA, a.wh_nn, cb, acc, [&] {
+      copy_rows<256>(&sA[0][0], LDA, a.dz16, 256, r0, nr);      // logit adjoint
+      col_sums<256>(&sF[0][0], LDF, nr, colp + a.off_bh);       // head bias gradient
+    });
     __syncthreads();  // every wave is done reading sA / sF
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
@@ -414,68 +571,80 @@ __global__ void __launch_bounds__(256, 1) fused_kernel(FusedArgs a) {
       for (int r = 0; r < 4; ++r) {
         const int i = li + r;
         sH[i][c] = acc[t][r];
-        const bf16_t hb = f2bf(acc[t][r]);
-        sA[i][c] = hb;
-        if (i < nr) a.dh16[NB][(size_t)(r0 + i) * F + c] = hb;
+        sA[i][c] = f2bf(acc[t][r]);
       }
     }
   }
   __syncthreads();
 
   for (int j = NB - 1; j >= 0; --j) {
-    // bias gradient of the block's output linear: column sums of dH_{j+1}
-    for (int c = tid; c < F; c += 256) {
-      float s = 0.f;
-      for (int i = 0; i < nr; ++i) s += sH[i][c];
-      colp[a.off_bo[j] + c] = s;
-    }
     {  // dX_ff = dH Wo; through GeLU and the branch product (adjoint of Eqs. 11-13)
-      constexpr int NH = H / 64;
+      constexpr int NH = ColSplit<H>::NT;
       int cb[NH];
       f32x4 acc[NH];
+      float sa0[NH][4], sa1[NH][4];  // saved branch values (Eq. 10)
 #pragma unroll
-      for (int t = 0; t < NH; ++t) cb[t] = w + 4 * t;
-      mm<F, NH, 16>(&sA[0][0], LDA, a.wo_nn[j], cb, acc);
+      for (int t = 0; t < NH; ++t) {
+        cb[t] = w + NW * t;
+        const int c = cb[t] * 16 + lc;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = li + r;
+          sa0[t][r] = 0.f;
+          sa1[t][r] = 0.f;
+          if (i < nr) {
+            sa0[t][r] = a.abr[j][(r0 + i) * H2 + c];
+            sa1[t][r] = a.abr[j][(r0 + i) * H2 + H + c];
+          }
+        }
+      }
+      mm<F, NH, kFusedBatch>(&sA[0][0], LDA, a.wo_nn[j], cb, acc, [&] {
+        copy_rows<F>(&sA[0][0], LDA, a.dh16[j + 1], F, r0, nr);  // adjoint of the block output
+        col_sums<F>(&sH[0][0], LDH, nr, colp + a.off_bo[j]);     // output bias gradient
+        if (j + 1 < NB) {  // affine gradients of the LayerNorm of block j + 1
+          for (int c = tid; c < F; c += kFusedThreads) {
+            colp[a.off_beta[j + 1] + c] = sGB[0][c];
+            colp[a.off_gamma[j + 1] + c] = sGB[1][c];
+          }
+        }
+      });
 #pragma unroll
       for (int t = 0; t < NH; ++t) {
         const int c = cb[t] * 16 + lc;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int i = li + r;
-          float a0 = 0.f, a1 = 0.f;
-          if (i < nr) {
-            a0 = a.abr[j][(size_t)(r0 + i) * H2 + c];
-            a1 = a.abr[j][(size_t)(r0 + i) * H2 + H + c];
-          }
+          const float a0 = sa0[t][r], a1 = sa1[t][r];
           const float dp = acc[t][r] * gelu_grad_f(a0 * a1);
           const float d0 = dp * a1, d1 = dp * a0;
           sF[i][c] = d0;
           sF[i][H + c] = d1;
-          const bf16_t h0 = f2bf(d0), h1 = f2bf(d1);
-          sB[i][c] = h0;
-          sB[i][H + c] = h1;
-          if (i < nr) {
-            a.da16[j][(size_t)(r0 + i) * H2 + c] = h0;
-            a.da16[j][(size_t)(r0 + i) * H2 + H + c] = h1;
-          }
+          sB[i][c] = f2bf(d0);
+          sB[i][H + c] = f2bf(d1);
         }
       }
     }
     __syncthreads();
-    for (int c = tid; c < H2; c += 256) {  // branch bias gradients
-      float s = 0.f;
-      for (int i = 0; i < nr; ++i) s += sF[i][c];
-      colp[a.off_bab[j] + c] = s;
-    }
     {  // dX0 = sum_i dX_i W_i, then the LayerNorm adjoint (Eq. 9)
-      constexpr int NT = F / 64;
+      constexpr int NT = ColSplit<F>::NT;
       int cb[NT];
       f32x4 acc[NT];
+      float xh[NT][4], gmr[NT];
 #pragma unroll
-      for (int t = 0; t < NT; ++t) cb[t] = w + 4 * t;
-      mm<H2, NT, 16>(&sB[0][0], LDA, a.wab_nn[j], cb, acc);
-      const float* gm = a.gamma[j];
-      float xh[NT][4];
+      for (int t = 0; t < NT; ++t) {
+        cb[t] = w + NW * t;
+        const int c = cb[t] * 16 + lc;
+        gmr[t] = a.gamma[j][c];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = li + r;
+          xh[t][r] = i < nr ? a.hs[j][(r0 + i) * F + c] : 0.f;
+        }
+      }
+      mm<H2, NT, kFusedBatch>(&sB[0][0], LDA, a.wab_nn[j], cb, acc, [&] {
+        copy_rows<H2>(&sB[0][0], LDA, a.da16[j], H2, r0, nr);  // branch adjoints
+        col_sums<H2>(&sF[0][0], LDF, nr, colp + a.off_bab[j]);  // branch bias gradients
+      });
       float s1[4] = {0.f, 0.f, 0.f, 0.f}, s2[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
@@ -486,11 +655,11 @@ __global__ void __launch_bounds__(256, 1) fused_kernel(FusedArgs a) {
           const int i = li + r;
           float x = 0.f, dz = 0.f;
           if (i < nr) {
-            x = (a.hs[j][(size_t)(r0 + i) * F + c] - sStat[j][i][0]) * sStat[j][i][1];
+            x = (xh[t][r] - sStat[j][i][0]) * sStat[j][i][1];
             dz = acc[t][r];
           }
           xh[t][r] = x;
-          acc[t][r] = dz * gm[c];  // dxhat
+          acc[t][r] = dz * gmr[t];  // dxhat
           s1[r] += acc[t][r];
           s2[r] += acc[t][r] * x;
           cz += dz;
@@ -502,8 +671,8 @@ __global__ void __launch_bounds__(256, 1) fused_kernel(FusedArgs a) {
         czx += __shfl_xor(czx, 16, 64);
         czx += __shfl_xor(czx, 32, 64);
         if (lane < 16) {
-          colp[a.off_beta[j] + c] = cz;
-          colp[a.off_gamma[j] + c] = czx;
+          sGB[0][c] = cz;
+          sGB[1][c] = czx;
         }
       }
 #pragma unroll
@@ -522,8 +691,14 @@ __global__ void __launch_bounds__(256, 1) fused_kernel(FusedArgs a) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int i = li + r;
-        const float m1 = ((sRed[0][i][0] + sRed[1][i][0]) + (sRed[2][i][0] + sRed[3][i][0])) / (float)F;
-        const float m2 = ((sRed[0][i][1] + sRed[1][i][1]) + (sRed[2][i][1] + sRed[3][i][1])) / (float)F;
+        float m1 = 0.f, m2 = 0.f;
+#pragma unroll
+        for (int u = 0; u < NW; ++u) {  // waves in a fixed order
+          m1 += sRed[u][i][0];
+          m2 += sRed[u][i][1];
+        }
+        m1 /= (float)F;
+        m2 /= (float)F;
         const float rs = sStat[j][i][1];
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
@@ -531,9 +706,7 @@ __global__ void __launch_bounds__(256, 1) fused_kernel(FusedArgs a) {
           float dh = 0.f;
           if (i < nr) dh = sH[i][c] + rs * (acc[t][r] - m1 - xh[t][r] * m2);
           sH[i][c] = dh;
-          const bf16_t hb = f2bf(dh);
-          sA[i][c] = hb;
-          if (i < nr) a.dh16[j][(size_t)(r0 + i) * F + c] = hb;
+          sA[i][c] = f2bf(dh);
         }
       }
     }
@@ -541,27 +714,32 @@ __global__ void __launch_bounds__(256, 1) fused_kernel(FusedArgs a) {
   }
 
   // ---- adjoint of Eq. 16 ---------------------------------------------------------
-  for (int c = tid; c < F; c += 256) {
-    float s = 0.f;
-    for (int i = 0; i < nr; ++i) s += sH[i][c];
-    colp[a.off_b2 + c] = s;
-  }
-  {
-    constexpr int NT = L / 64;
+  auto tail = [&] {
+    copy_rows<F>(&sA[0][0], LDA, a.dh16[0], F, r0, nr);  // adjoint of the LTE output
+    col_sums<F>(&sH[0][0], LDH, nr, colp + a.off_b2);    // b2 gradient
+    for (int c = tid; c < F; c += kFusedThreads) {       // LayerNorm of block 0
+      colp[a.off_beta[0] + c] = sGB[0][c];
+      colp[a.off_gamma[0] + c] = sGB[1][c];
+    }
+  };
+  if (ColSplit<L>::active(w)) {
+    constexpr int NT = ColSplit<L>::NT;
     int cb[NT];
     f32x4 acc[NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) cb[t] = w + 4 * t;
-    mm<F, NT, 16>(&sA[0][0], LDA, a.w2_nn, cb, acc);
+    for (int t = 0; t < NT; ++t) cb[t] = w + NW * t;
+    mm<F, NT, kFusedBatch>(&sA[0][0], LDA, a.w2_nn, cb, acc, tail);
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       const int c = cb[t] * 16 + lc;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int i = li + r;
-        if (i < nr) a.dy[(size_t)(r0 + i) * L + c] = acc[t][r];
+        if (i < nr) a.dy[(r0 + i) * L + c] = acc[t][r];
       }
     }
+  } else {
+    tail();
   }
 }
 
@@ -578,7 +756,8 @@ __global__ void __launch_bounds__(256) fused_in_kernel(FusedInArgs a) {
   const int r0 = blockIdx.x * BM;
   if (r0 >= rows) return;
   const int nr = min(BM, rows - r0);
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index (uniform)
   const int C = a.C, E = a.E;
   for (int idx = tid; idx < BM * C; idx += 256) {
     const int i = idx / C, c = idx % C;
@@ -614,14 +793,17 @@ __global__ void __launch_bounds__(256) fused_in_kernel(FusedInArgs a) {
   f32x4 acc[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) cb[t] = w + 4 * t;
-  mm<F, NT, 16>(&sA[0][0], LDA, a.w1_nt, cb, acc);
+  float bias[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) bias[t] = a.b1[cb[t] * 16 + (lane & 15)];
+  mm<F, NT, 8>(&sA[0][0], LDA, a.w1_nt, cb, acc);
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const int c = cb[t] * 16 + (lane & 15);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = 4 * (lane >> 4) + r;
-      if (i < nr) a.x1[(size_t)(r0 + i) * L + c] = acc[t][r] + a.b1[c];
+      if (i < nr) a.x1[(size_t)(r0 + i) * L + c] = acc[t][r] + bias[t];
     }
   }
 }
@@ -640,7 +822,8 @@ __global__ void __launch_bounds__(256) fused_out_kernel(FusedOutArgs a) {
   const int r0 = blockIdx.x * BM;
   if (r0 >= rows) return;
   const int nr = min(BM, rows - r0);
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index (uniform)
   const int C = a.C, E = a.E;
   for (int idx = tid; idx < BM * (L / 8); idx += 256) {
     const int i = idx / (L / 8), q = idx % (L / 8);
@@ -663,7 +846,7 @@ __global__ void __launch_bounds__(256) fused_out_kernel(FusedOutArgs a) {
     f32x4 acc[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) cb[t] = w + 4 * t;
-    mm<L, NT, 16>(&sA[0][0], LDA, a.w1_nn, cb, acc);
+    mm<L, NT, 8>(&sA[0][0], LDA, a.w1_nn, cb, acc);
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       const int c = cb[t] * 16 + (lane & 15);
@@ -742,7 +925,7 @@ static hipError_t launch_t(const FusedArgs& a, int grid_rows, hipStream_t s) {
   }
   const int blocks = (grid_rows + kFusedRows - 1) / kFusedRows;
   if (blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL((fused_kernel<F, L, H>), dim3(blocks), dim3(256), D::BYTES, s, a);
+  hipLaunchKernelGGL((fused_kernel<F, L, H>), dim3(blocks), dim3(kFusedThreads), D::BYTES, s, a);
   return hipGetLastError();
 }
 

@@ -147,11 +147,12 @@ KernelConfig Model::default_config(const edpc_config& c, size_t rows) {
     wg.push_back({KH, F});
   }
   k.tile[PS_WGRAD] = pick_tile(rows, wg, 512);
-  // The row-block fused step streams every weight once per 16-row block; at
-  // these batch sizes that is slower than the layer-by-layer products, so it
-  // is opt-in (EDPC_FUSED=1 in the encoder's environment).
+  // BF16 shapes with a row-block kernel take the fused step (one workgroup per
+  // 16 rows runs LTE up .. head .. coder .. adjoint); EDPC_FUSED=0 in the
+  // encoder's environment selects the layer-by-layer products instead.  The
+  // row-block kernels index activations with 32-bit offsets.
   const char* env = std::getenv("EDPC_FUSED");
-  k.fused = env && env[0] == '1' && c.precision == EDPC_BF16 &&
+  k.fused = !(env && env[0] == '0') && c.precision == EDPC_BF16 && rows <= (1u << 20) &&
             fused_supported(F, L, H, (int)c.branches, (int)c.blocks);
   return k;
 }
@@ -181,7 +182,7 @@ Model::Model(const edpc_config& c, size_t nslots, size_t rows, const KernelConfi
   K = c.branches;
   bf16 = c.precision == EDPC_BF16;
   kc = kcfg ? *kcfg : default_config(c, rows);
-  if (kc.fused && !(bf16 && fused_supported(F, L, H, K, N)))
+  if (kc.fused && !(bf16 && fused_supported(F, L, H, K, N) && rows <= (1u << 20)))
     fail(EDPC_E_UNSUPPORTED, "fused step requested for an unsupported shape");
 
   // Flat layout of the shared parameters; each tensor starts 64-aligned.
