@@ -33,11 +33,15 @@ struct FragJob {
 void k_build_frags(const FragJob* jobs, int n_jobs, int total_frags, hipStream_t s);
 
 // Adam over the shared parameters fused with the fragment-copy refresh:
-// matrix jobs are walked in 8 x 8 blocks (both fragment orientations written
-// from registers), the other tensors element-wise in groups of 8.
+// matrix jobs are walked in 32 x 64 tiles (rows a multiple of 32, columns a
+// multiple of 64), the other tensors in items of 2048 elements; one
+// workgroup per item.
+constexpr int kAdamTileRows = 32;
+constexpr int kAdamTileCols = 64;
+constexpr int kAdamVecItem = 2048;
 struct AdamJob {
   size_t off;        // element offset in the flat parameter buffers
-  int rows, cols;    // matrix (cols > 0) or element range (cols == 0, rows = count)
+  int rows, cols;    // matrix (cols > 0) or element range (cols == 0, rows = count, a multiple of 8)
   uint4* nt;         // fragment copies (matrix jobs)
   uint4* nn;
   int item_begin;    // first work item of this job

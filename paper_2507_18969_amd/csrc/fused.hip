@@ -66,24 +66,24 @@ __device__ __forceinline__ void transpose8x8(const uint4* in, uint4* out) {
   }
 }
 
-__device__ __forceinline__ void adam8(float* pp, const float* gp, float* mp, float* vp, float lr_bc,
+// Adam (Kingma & Ba 2015, bias-corrected) on 8 consecutive parameters with
+// gradients gv; the updated values are returned in out.
+__device__ __forceinline__ void adam8(float* pp, const float gv[8], float* mp, float* vp, float lr_bc,
                                       float inv_bc2, const AdamCfg& ac, float out[8]) {
-  float4 p4[2], g4[2], m4[2], v4[2];
+  float4 p4[2], m4[2], v4[2];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     p4[h] = ((const float4*)pp)[h];
-    g4[h] = ((const float4*)gp)[h];
     m4[h] = ((const float4*)mp)[h];
     v4[h] = ((const float4*)vp)[h];
   }
   float* P = (float*)p4;
-  float* G = (float*)g4;
   float* M = (float*)m4;
   float* V = (float*)v4;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    M[k] = ac.beta1 * M[k] + (1.0f - ac.beta1) * G[k];
-    V[k] = ac.beta2 * V[k] + (1.0f - ac.beta2) * G[k] * G[k];
+    M[k] = ac.beta1 * M[k] + (1.0f - ac.beta1) * gv[k];
+    V[k] = ac.beta2 * V[k] + (1.0f - ac.beta2) * gv[k] * gv[k];
     P[k] = P[k] - lr_bc * M[k] / (sqrtf(V[k] * inv_bc2) + ac.eps);
     out[k] = P[k];
   }
@@ -95,59 +95,71 @@ __device__ __forceinline__ void adam8(float* pp, const float* gp, float* mp, flo
   }
 }
 
+__device__ __forceinline__ void load8(const float* q, float out[8]) {
+  const float4 a = ((const float4*)q)[0], b = ((const float4*)q)[1];
+  out[0] = a.x; out[1] = a.y; out[2] = a.z; out[3] = a.w;
+  out[4] = b.x; out[5] = b.y; out[6] = b.z; out[7] = b.w;
+}
+
+// One workgroup per work item: a 32 x 64 tile of a matrix (one thread per
+// row chunk of 8; the nt copy is written straight from registers, the nn copy
+// after a transpose through LDS) or 2048 elements of another tensor.
 __global__ void __launch_bounds__(256) adam_frags_kernel(const StepState* __restrict__ st,
                                                          const AdamJob* __restrict__ jobs, int n_jobs,
-                                                         int total_items, float* __restrict__ p,
+                                                         float* __restrict__ p,
                                                          const float* __restrict__ g,
                                                          float* __restrict__ m, float* __restrict__ v,
                                                          AdamCfg ac) {
-  const int it = blockIdx.x * blockDim.x + threadIdx.x;
-  if (it >= total_items) return;
+  __shared__ __align__(16) bf16_t tile[kAdamTileRows][kAdamTileCols + 8];
+  const int it = blockIdx.x;
   int j = 0;
   while (j + 1 < n_jobs && it >= jobs[j + 1].item_begin) ++j;
   const AdamJob jb = jobs[j];
   const int local = it - jb.item_begin;
   const float lr_bc = ac.lr / st->bc1;
   const float inv_bc2 = 1.0f / st->bc2;
-  float nv[8];
-  if (jb.cols == 0) {  // element range, 8 per item
-    const size_t o = jb.off + (size_t)local * 8;
-    adam8(p + o, g + o, m + o, v + o, lr_bc, inv_bc2, ac, nv);
+  const int t = threadIdx.x;
+  float gv[8], nv[8];
+  if (jb.cols == 0) {  // element range
+    const size_t e = (size_t)local * kAdamVecItem + (size_t)t * 8;
+    if (e < (size_t)jb.rows) {
+      load8(g + jb.off + e, gv);
+      adam8(p + jb.off + e, gv, m + jb.off + e, v + jb.off + e, lr_bc, inv_bc2, ac, nv);
+    }
     return;
   }
-  const int cb8 = jb.cols / 8;
-  const int rb = local / cb8, cb = local % cb8;
-  const int r0 = rb * 8, c0 = cb * 8;
-  uint4 rowv[8];
+  const int tiles_c = jb.cols / kAdamTileCols;
+  const int r0 = (local / tiles_c) * kAdamTileRows, c0 = (local % tiles_c) * kAdamTileCols;
+  const int tr = t >> 3, tc = 8 * (t & 7);
+  const int row = r0 + tr, col = c0 + tc;
+  const size_t o = jb.off + (size_t)row * jb.cols + col;
+  load8(g + o, gv);
+  adam8(p + o, gv, m + o, v + o, lr_bc, inv_bc2, ac, nv);
+  const uint4 pk = make_uint4((uint32_t)f2bf(nv[0]) | ((uint32_t)f2bf(nv[1]) << 16),
+                              (uint32_t)f2bf(nv[2]) | ((uint32_t)f2bf(nv[3]) << 16),
+                              (uint32_t)f2bf(nv[4]) | ((uint32_t)f2bf(nv[5]) << 16),
+                              (uint32_t)f2bf(nv[6]) | ((uint32_t)f2bf(nv[7]) << 16));
+  // nt fragment (nb = row/16, kb = col/32), lane = row%16 + 16*((col%32)/8)
+  jb.nt[((size_t)(row >> 4) * (jb.cols / 32) + (col >> 5)) * 64 + (row & 15) + 16 * ((col & 31) >> 3)] = pk;
+  *(uint4*)&tile[tr][tc] = pk;
+  __syncthreads();
+  // nn fragment (nb = col/16, kb = row/32), lane = col%16 + 16*((row%32)/8):
+  // the tile holds kb = r0/32 of column blocks c0/16 .. c0/16 + 3
+  const int f = t >> 6, l = t & 63;
+  const int cc = 16 * f + (l & 15), rr = 8 * (l >> 4);
+  uint32_t w[4];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const size_t o = jb.off + (size_t)(r0 + q) * jb.cols + c0;
-    adam8(p + o, g + o, m + o, v + o, lr_bc, inv_bc2, ac, nv);
-    rowv[q] = make_uint4((uint32_t)f2bf(nv[0]) | ((uint32_t)f2bf(nv[1]) << 16),
-                         (uint32_t)f2bf(nv[2]) | ((uint32_t)f2bf(nv[3]) << 16),
-                         (uint32_t)f2bf(nv[4]) | ((uint32_t)f2bf(nv[5]) << 16),
-                         (uint32_t)f2bf(nv[6]) | ((uint32_t)f2bf(nv[7]) << 16));
-    // nt fragment (nb = row/16, kb = col/32), lane = row%16 + 16*((col%32)/8)
-    const int row = r0 + q;
-    const size_t f = (size_t)(row >> 4) * (jb.cols / 32) + (c0 >> 5);
-    jb.nt[f * 64 + (row & 15) + 16 * ((c0 & 31) >> 3)] = rowv[q];
-  }
-  uint4 colv[8];
-  transpose8x8(rowv, colv);
-#pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    // nn fragment (nb = col/16, kb = row/32), lane = col%16 + 16*((row%32)/8)
-    const int col = c0 + q;
-    const size_t f = (size_t)(col >> 4) * (jb.rows / 32) + (r0 >> 5);
-    jb.nn[f * 64 + (col & 15) + 16 * ((r0 & 31) >> 3)] = colv[q];
-  }
+  for (int k = 0; k < 4; ++k)
+    w[k] = (uint32_t)tile[rr + 2 * k][cc] | ((uint32_t)tile[rr + 2 * k + 1][cc] << 16);
+  jb.nn[((size_t)((c0 + cc) >> 4) * (jb.rows / 32) + (r0 >> 5)) * 64 + l] =
+      make_uint4(w[0], w[1], w[2], w[3]);
 }
 
 void k_adam_frags(const StepState* st, const AdamJob* jobs, int n_jobs, int total_items, float* p,
                   const float* g, float* m, float* v, AdamCfg ac, hipStream_t s) {
   if (total_items == 0) return;
-  hipLaunchKernelGGL(adam_frags_kernel, dim3((total_items + 255) / 256), dim3(256), 0, s, st, jobs,
-                     n_jobs, total_items, p, g, m, v, ac);
+  hipLaunchKernelGGL(adam_frags_kernel, dim3(total_items), dim3(256), 0, s, st, jobs, n_jobs, p, g,
+                     m, v, ac);
 }
 
 // ---------------------------------------------------------------------------
@@ -746,8 +758,9 @@ __global__ void __launch_bounds__(kFusedThreads, 1) fused_kernel(FusedArgs a) {
 // ---------------------------------------------------------------------------
 // Before the FDM: gather, embedding, LTE down-projection
 // ---------------------------------------------------------------------------
-template <int F, int L>
+template <int F, int L, int E>
 __global__ void __launch_bounds__(256) fused_in_kernel(FusedInArgs a) {
+  constexpr int C = F / E;
   constexpr int BM = kFusedRows, LDA = F + 8;
   __shared__ __align__(16) bf16_t sA[BM][LDA];
   __shared__ uint8_t sC[BM][256];
@@ -758,7 +771,6 @@ __global__ void __launch_bounds__(256) fused_in_kernel(FusedInArgs a) {
   const int nr = min(BM, rows - r0);
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index (uniform)
-  const int C = a.C, E = a.E;
   for (int idx = tid; idx < BM * C; idx += 256) {
     const int i = idx / C, c = idx % C;
     uint8_t v = 0;
@@ -811,12 +823,13 @@ __global__ void __launch_bounds__(256) fused_in_kernel(FusedInArgs a) {
 // ---------------------------------------------------------------------------
 // After the FDM adjoint: dX = dX' W1, embedding gradient partial, b1 partial
 // ---------------------------------------------------------------------------
-template <int F, int L>
+template <int F, int L, int E>
 __global__ void __launch_bounds__(256) fused_out_kernel(FusedOutArgs a) {
+  constexpr int C = F / E;
   constexpr int BM = kFusedRows, LDA = L + 8, LDX = F + 4;
   __shared__ __align__(16) bf16_t sA[BM][LDA];
   __shared__ __align__(16) float sX[BM][LDX];
-  __shared__ uint8_t sC[BM * 256 + 16];
+  __shared__ __align__(16) uint8_t sC[BM * 256 + 16];
   const StepState* st = a.st;
   const int rows = st->rows;
   const int r0 = blockIdx.x * BM;
@@ -824,7 +837,6 @@ __global__ void __launch_bounds__(256) fused_out_kernel(FusedOutArgs a) {
   const int nr = min(BM, rows - r0);
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index (uniform)
-  const int C = a.C, E = a.E;
   for (int idx = tid; idx < BM * (L / 8); idx += 256) {
     const int i = idx / (L / 8), q = idx % (L / 8);
     uint4 v = make_uint4(0, 0, 0, 0);
@@ -834,9 +846,13 @@ __global__ void __launch_bounds__(256) fused_out_kernel(FusedOutArgs a) {
   for (int idx = tid; idx < BM * C; idx += 256)
     sC[idx] = (idx / C) < nr ? a.ctx[(size_t)r0 * C + idx] : 0;
   float* colp = a.colpart + (size_t)blockIdx.x * a.colpart_cols;
-  for (int c = tid; c < L; c += 256) {  // b1 gradient partial
+  for (int c = tid; c < L; c += 256) {  // b1 gradient partial, rows in order
+    float v[BM];
+#pragma unroll
+    for (int i = 0; i < BM; ++i) v[i] = i < nr ? a.dx1_32[(size_t)(r0 + i) * L + c] : 0.f;
     float s = 0.f;
-    for (int i = 0; i < nr; ++i) s += a.dx1_32[(size_t)(r0 + i) * L + c];
+#pragma unroll
+    for (int i = 0; i < BM; ++i) s += v[i];
     colp[a.off_b1 + c] = s;
   }
   __syncthreads();
@@ -865,19 +881,34 @@ __global__ void __launch_bounds__(256) fused_out_kernel(FusedOutArgs a) {
   for (int vb = 0; vb < 4; ++vb)
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb) acc[vb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // With C a multiple of 32 every 32-pair step lies inside one row, so the
+  // row bound is the only (wave-uniform) guard.
+  constexpr bool kRowSteps = C % 32 == 0;
   for (int k0 = 0; k0 < np; k0 += 32) {
     const int p0 = k0 + 8 * (lane >> 4);
     uint32_t bytes[8];
+    if constexpr (kRowSteps) {
+      const uint2 b8 = *(const uint2*)&sC[p0];
 #pragma unroll
-    for (int v = 0; v < 8; ++v) bytes[v] = (p0 + v < np) ? (uint32_t)sC[p0 + v] : 0xFFFFu;
+      for (int v = 0; v < 8; ++v) bytes[v] = ((v < 4 ? b8.x : b8.y) >> (8 * (v & 3))) & 0xFFu;
+    } else {
+#pragma unroll
+      for (int v = 0; v < 8; ++v) bytes[v] = (p0 + v < np) ? (uint32_t)sC[p0 + v] : 0xFFFFu;
+    }
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb) {
       if (nb >= NE) break;
       bf16_t bv[8];
+      if constexpr (kRowSteps) {
+        const float* xr = &sX[k0 / C][(p0 % C) * E + 16 * nb + (lane & 15)];
 #pragma unroll
-      for (int v = 0; v < 8; ++v) {
-        const int p = p0 + v;
-        bv[v] = p < np ? f2bf(sX[p / C][(p % C) * E + 16 * nb + (lane & 15)]) : (bf16_t)0;
+        for (int v = 0; v < 8; ++v) bv[v] = f2bf(xr[v * E]);
+      } else {
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+          const int p = p0 + v;
+          bv[v] = p < np ? f2bf(sX[p / C][(p % C) * E + 16 * nb + (lane & 15)]) : (bf16_t)0;
+        }
       }
       const uint4 b = make_uint4((uint32_t)bv[0] | ((uint32_t)bv[1] << 16),
                                  (uint32_t)bv[2] | ((uint32_t)bv[3] << 16),
@@ -929,28 +960,37 @@ static hipError_t launch_t(const FusedArgs& a, int grid_rows, hipStream_t s) {
   return hipGetLastError();
 }
 
+// (F, L) of the fused shapes and the byte-embedding width E: C = F / E
+// context bytes, known at compile time.
+#define EDPC_FUSED_IO_SHAPES(X) \
+  X(512, 128, 16) X(512, 128, 32) X(512, 128, 64) X(256, 64, 16) X(256, 64, 32) X(256, 64, 64)
+
 hipError_t launch_fused_in(int F, int L, const FusedInArgs& a, int grid_rows, hipStream_t s) {
   const int blocks = (grid_rows + kFusedRows - 1) / kFusedRows;
   if (blocks == 0) return hipSuccess;
-  if (F == 512 && L == 128)
-    hipLaunchKernelGGL((fused_in_kernel<512, 128>), dim3(blocks), dim3(256), 0, s, a);
-  else if (F == 256 && L == 64)
-    hipLaunchKernelGGL((fused_in_kernel<256, 64>), dim3(blocks), dim3(256), 0, s, a);
-  else
-    return hipErrorInvalidValue;
-  return hipGetLastError();
+  if (a.C * a.E != F) return hipErrorInvalidValue;
+#define X(FF, LL, EE)                                                                         \
+  if (F == FF && L == LL && a.E == EE) {                                                      \
+    hipLaunchKernelGGL((fused_in_kernel<FF, LL, EE>), dim3(blocks), dim3(256), 0, s, a);      \
+    return hipGetLastError();                                                                 \
+  }
+  EDPC_FUSED_IO_SHAPES(X)
+#undef X
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_fused_out(int F, int L, const FusedOutArgs& a, int grid_rows, hipStream_t s) {
   const int blocks = (grid_rows + kFusedRows - 1) / kFusedRows;
   if (blocks == 0) return hipSuccess;
-  if (F == 512 && L == 128)
-    hipLaunchKernelGGL((fused_out_kernel<512, 128>), dim3(blocks), dim3(256), 0, s, a);
-  else if (F == 256 && L == 64)
-    hipLaunchKernelGGL((fused_out_kernel<256, 64>), dim3(blocks), dim3(256), 0, s, a);
-  else
-    return hipErrorInvalidValue;
-  return hipGetLastError();
+  if (a.C * a.E != F) return hipErrorInvalidValue;
+#define X(FF, LL, EE)                                                                         \
+  if (F == FF && L == LL && a.E == EE) {                                                      \
+    hipLaunchKernelGGL((fused_out_kernel<FF, LL, EE>), dim3(blocks), dim3(256), 0, s, a);     \
+    return hipGetLastError();                                                                 \
+  }
+  EDPC_FUSED_IO_SHAPES(X)
+#undef X
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_fused(int F, int L, int H, const FusedArgs& a, int grid_rows, hipStream_t s) {

@@ -106,6 +106,9 @@ void k_embed(const StepState* st, const uint8_t* ctx, const float* emb, int C, i
                      x32, x16);
 }
 
+// Rows of U_s whose loads are issued together in the FDM kernels.
+constexpr int kFdmBatch = 4;
+
 // ---------------------------------------------------------------------------
 // Feature Distribution Matrix (Eq. 15): y_s = x'_s U_s, one workgroup per row.
 // Thread (g, t): t covers columns 4t..4t+3, group g rows l = g, g+G, ...
@@ -127,7 +130,22 @@ __global__ void __launch_bounds__(256) fdm_fwd_kernel(const StepState* __restric
   const float* Us = U + (size_t)slot[r] * L * L;
   float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
   if (g < G) {
-    for (int l = g; l < L; l += G) {
+    // rows l = g, g + G, ... in order; loads issued kFdmBatch rows at a time
+    int l = g;
+    for (; l + (kFdmBatch - 1) * G < L; l += kFdmBatch * G) {
+      float4 u[kFdmBatch];
+#pragma unroll
+      for (int q = 0; q < kFdmBatch; ++q) u[q] = *(const float4*)(Us + (size_t)(l + q * G) * L + 4 * t);
+#pragma unroll
+      for (int q = 0; q < kFdmBatch; ++q) {
+        const float xv = xs[l + q * G];
+        acc.x += xv * u[q].x;
+        acc.y += xv * u[q].y;
+        acc.z += xv * u[q].z;
+        acc.w += xv * u[q].w;
+      }
+    }
+    for (; l < L; l += G) {
       const float4 u = *(const float4*)(Us + (size_t)l * L + 4 * t);
       const float xv = xs[l];
       acc.x += xv * u.x;
@@ -175,9 +193,9 @@ __global__ void __launch_bounds__(256) fdm_bwd_kernel(
   const float b1 = ac.beta1, b2 = ac.beta2;
   const float lr_bc = ac.lr / st->bc1;
   const float inv_bc2 = 1.0f / st->bc2;
-  for (int l = g; l < L; l += G) {
+  // one row l of U_s: dx'[l] (from U before the update), dU, Adam
+  auto row = [&](int l, float4 u, float4 m, float4 v) {
     const size_t idx = base_s + (size_t)l * L + 4 * t;
-    float4 u = *(const float4*)(U + idx);
     float part = u.x * d4.x + u.y * d4.y + u.z * d4.z + u.w * d4.w;
     for (int o = tpr >> 1; o >= 1; o >>= 1) part += __shfl_xor(part, o, 64);
     if (t == 0) {
@@ -188,8 +206,6 @@ __global__ void __launch_bounds__(256) fdm_bwd_kernel(
     const float gr[4] = {xv * d4.x, xv * d4.y, xv * d4.z, xv * d4.w};
     if (dU_keep) *(float4*)(dU_keep + idx) = make_float4(gr[0], gr[1], gr[2], gr[3]);
     if (update) {
-      float4 m = *(const float4*)(mU + idx);
-      float4 v = *(const float4*)(vU + idx);
       float* up = (float*)&u;
       float* mp = (float*)&m;
       float* vp = (float*)&v;
@@ -203,6 +219,11 @@ __global__ void __launch_bounds__(256) fdm_bwd_kernel(
       *(float4*)(mU + idx) = m;
       *(float4*)(vU + idx) = v;
     }
+  };
+  for (int l = g; l < L; l += G) {
+    const size_t idx = base_s + (size_t)l * L + 4 * t;
+    row(l, *(const float4*)(U + idx), update ? *(const float4*)(mU + idx) : make_float4(0.f, 0.f, 0.f, 0.f),
+        update ? *(const float4*)(vU + idx) : make_float4(0.f, 0.f, 0.f, 0.f));
   }
 }
 
@@ -463,16 +484,16 @@ void k_head(const StepState* st, HeadArgs a, StreamIO io, int max_rows, hipStrea
 constexpr int kColChunk = 64;
 
 // p[0] + p[stride] + ... + p[(n-1) stride], added strictly in index order;
-// the loads are issued 16 at a time so their latencies overlap.
+// the loads are issued 32 at a time so their latencies overlap.
 __device__ __forceinline__ float ordered_sum(const float* __restrict__ p, size_t stride, int n) {
   float s = 0.f;
   int k = 0;
-  for (; k + 16 <= n; k += 16) {
-    float v[16];
+  for (; k + 32 <= n; k += 32) {
+    float v[32];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) v[q] = p[(size_t)(k + q) * stride];
+    for (int q = 0; q < 32; ++q) v[q] = p[(size_t)(k + q) * stride];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) s += v[q];
+    for (int q = 0; q < 32; ++q) s += v[q];
   }
   for (; k < n; ++k) s += p[(size_t)k * stride];
   return s;

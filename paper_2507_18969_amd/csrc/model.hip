@@ -440,7 +440,9 @@ void Model::setup_fused(hipStream_t s) {
       a.nt = fj.nt;
       a.nn = fj.nn;
       a.item_begin = items;
-      items += (fj.rows / 8) * (fj.cols / 8);
+      if (fj.rows % kAdamTileRows || fj.cols % kAdamTileCols)
+        fail(EDPC_E_UNSUPPORTED, "matrix shape of the fused step's Adam tiles");
+      items += (fj.rows / kAdamTileRows) * (fj.cols / kAdamTileCols);
       aj.push_back(a);
       for (size_t t = 0; t < tens.size(); ++t)
         if (tens[t].off >= a.off && tens[t].off < a.off + (size_t)a.rows * a.cols) covered[t] = 1;
@@ -453,7 +455,7 @@ void Model::setup_fused(hipStream_t s) {
       a.cols = 0;
       a.nt = a.nn = nullptr;
       a.item_begin = items;
-      items += a.rows / 8;
+      items += (a.rows + kAdamVecItem - 1) / kAdamVecItem;
       aj.push_back(a);
     }
     n_adam_jobs = (int)aj.size();
