@@ -68,4 +68,19 @@ __device__ __forceinline__ uint32_t wave_max_u(uint32_t v) {
   return v;
 }
 
+// p[0] + p[stride] + ... + p[(n-1) stride], added strictly in index order;
+// the loads are issued 32 at a time so their latencies overlap (slots past n
+// add an exact zero).
+__device__ __forceinline__ float ordered_sum(const float* __restrict__ p, size_t stride, int n) {
+  float s = 0.f;
+  for (int k = 0; k < n; k += 32) {
+    float v[32];
+#pragma unroll
+    for (int q = 0; q < 32; ++q) v[q] = k + q < n ? p[(size_t)(k + q) * stride] : 0.f;
+#pragma unroll
+    for (int q = 0; q < 32; ++q) s += v[q];
+  }
+  return s;
+}
+
 }  // namespace edpc

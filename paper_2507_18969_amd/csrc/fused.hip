@@ -103,11 +103,11 @@ __device__ __forceinline__ void load8(const float* q, float out[8]) {
 
 // One workgroup per work item: a 32 x 64 tile of a matrix (one thread per
 // row chunk of 8; the nt copy is written straight from registers, the nn copy
-// after a transpose through LDS) or 2048 elements of another tensor.
+// after a transpose through LDS) or 256 elements of another tensor.
 __global__ void __launch_bounds__(256) adam_frags_kernel(const StepState* __restrict__ st,
                                                          const AdamJob* __restrict__ jobs, int n_jobs,
                                                          float* __restrict__ p,
-                                                         const float* __restrict__ g,
+                                                         float* __restrict__ g,
                                                          float* __restrict__ m, float* __restrict__ v,
                                                          AdamCfg ac) {
   __shared__ __align__(16) bf16_t tile[kAdamTileRows][kAdamTileCols + 8];
@@ -120,12 +120,22 @@ __global__ void __launch_bounds__(256) adam_frags_kernel(const StepState* __rest
   const float inv_bc2 = 1.0f / st->bc2;
   const int t = threadIdx.x;
   float gv[8], nv[8];
-  if (jb.cols == 0) {  // element range
-    const size_t e = (size_t)local * kAdamVecItem + (size_t)t * 8;
-    if (e < (size_t)jb.rows) {
-      load8(g + jb.off + e, gv);
-      adam8(p + jb.off + e, gv, m + jb.off + e, v + jb.off + e, lr_bc, inv_bc2, ac, nv);
+  if (jb.cols == 0) {  // element range, one element a thread
+    const int e = local * kAdamVecItem + t;
+    if (e >= jb.rows) return;
+    const size_t o = jb.off + e;
+    float gr;
+    if (jb.red) {
+      gr = ordered_sum(jb.red + e, (size_t)jb.red_ld, (st->rows + kFusedRows - 1) / kFusedRows);
+      g[o] = gr;
+    } else {
+      gr = g[o];
     }
+    const float mm = ac.beta1 * m[o] + (1.0f - ac.beta1) * gr;
+    const float vv = ac.beta2 * v[o] + (1.0f - ac.beta2) * gr * gr;
+    p[o] -= lr_bc * mm / (sqrtf(vv * inv_bc2) + ac.eps);
+    m[o] = mm;
+    v[o] = vv;
     return;
   }
   const int tiles_c = jb.cols / kAdamTileCols;
@@ -156,7 +166,7 @@ __global__ void __launch_bounds__(256) adam_frags_kernel(const StepState* __rest
 }
 
 void k_adam_frags(const StepState* st, const AdamJob* jobs, int n_jobs, int total_items, float* p,
-                  const float* g, float* m, float* v, AdamCfg ac, hipStream_t s) {
+                  float* g, float* m, float* v, AdamCfg ac, hipStream_t s) {
   if (total_items == 0) return;
   hipLaunchKernelGGL(adam_frags_kernel, dim3(total_items), dim3(256), 0, s, st, jobs, n_jobs, p, g,
                      m, v, ac);

@@ -483,22 +483,6 @@ void k_head(const StepState* st, HeadArgs a, StreamIO io, int max_rows, hipStrea
 // ---------------------------------------------------------------------------
 constexpr int kColChunk = 64;
 
-// p[0] + p[stride] + ... + p[(n-1) stride], added strictly in index order;
-// the loads are issued 32 at a time so their latencies overlap.
-__device__ __forceinline__ float ordered_sum(const float* __restrict__ p, size_t stride, int n) {
-  float s = 0.f;
-  int k = 0;
-  for (; k + 32 <= n; k += 32) {
-    float v[32];
-#pragma unroll
-    for (int q = 0; q < 32; ++q) v[q] = p[(size_t)(k + q) * stride];
-#pragma unroll
-    for (int q = 0; q < 32; ++q) s += v[q];
-  }
-  for (; k < n; ++k) s += p[(size_t)k * stride];
-  return s;
-}
-
 __global__ void __launch_bounds__(256) colsum_partial_kernel(const StepState* __restrict__ st,
                                                              const ColsumJob* __restrict__ jobs,
                                                              int n_jobs, int total_cols,

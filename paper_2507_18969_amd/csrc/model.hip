@@ -428,8 +428,10 @@ void Model::setup_fused(hipStream_t s) {
   }
   n_frag_jobs = (int)jobs.size();
   total_frags = fr;
-  {  // Adam jobs: matrices with fragment copies in 8 x 8 blocks, the rest by 8s
-    std::vector<AdamJob> aj;
+  std::vector<AdamJob> aj;
+  std::vector<std::string> aj_name;  // tensor of each element-range job
+  {  // Adam jobs: matrices with fragment copies by tiles, the other tensors by element
+
     int items = 0;
     std::vector<char> covered(tens.size(), 0);
     for (const auto& fj : jobs) {
@@ -439,11 +441,14 @@ void Model::setup_fused(hipStream_t s) {
       a.cols = fj.cols;
       a.nt = fj.nt;
       a.nn = fj.nn;
+      a.red = nullptr;
+      a.red_ld = 0;
       a.item_begin = items;
       if (fj.rows % kAdamTileRows || fj.cols % kAdamTileCols)
         fail(EDPC_E_UNSUPPORTED, "matrix shape of the fused step's Adam tiles");
       items += (fj.rows / kAdamTileRows) * (fj.cols / kAdamTileCols);
       aj.push_back(a);
+      aj_name.push_back("");
       for (size_t t = 0; t < tens.size(); ++t)
         if (tens[t].off >= a.off && tens[t].off < a.off + (size_t)a.rows * a.cols) covered[t] = 1;
     }
@@ -451,18 +456,18 @@ void Model::setup_fused(hipStream_t s) {
       if (covered[t]) continue;
       AdamJob a;
       a.off = tens[t].off;
-      a.rows = (int)((tens[t].numel + 7) / 8) * 8;  // tensors start 64-aligned: padding is inert
+      a.rows = (int)tens[t].numel;
       a.cols = 0;
       a.nt = a.nn = nullptr;
+      a.red = nullptr;
+      a.red_ld = 0;
       a.item_begin = items;
       items += (a.rows + kAdamVecItem - 1) / kAdamVecItem;
       aj.push_back(a);
+      aj_name.push_back(tens[t].name);
     }
     n_adam_jobs = (int)aj.size();
     adam_items = items;
-    d_adam_jobs = dalloc<AdamJob>(aj.size());
-    hip_check(hipMemcpyAsync(d_adam_jobs, aj.data(), aj.size() * sizeof(AdamJob),
-                             hipMemcpyHostToDevice, s), "copy");
   }
   d_frag_jobs = dalloc<FragJob>(jobs.size());
   hip_check(hipMemcpyAsync(d_frag_jobs, jobs.data(), jobs.size() * sizeof(FragJob),
@@ -563,6 +568,25 @@ void Model::setup_fused(hipStream_t s) {
   fused_emb_partial = dalloc<float>(((max_rows + kFusedRows - 1) / kFusedRows) * 256 * (size_t)E);
   fout.emb_partial = fused_emb_partial;
   fout.colpart = fused_colpart;
+  // element-range Adam jobs take their gradients from the row-block partials
+  for (size_t k = 0; k < aj.size(); ++k) {
+    if (aj[k].cols != 0) continue;
+    if (aj_name[k] == "emb") {
+      aj[k].red = fused_emb_partial;
+      aj[k].red_ld = 256 * E;
+      continue;
+    }
+    const float* dst = G_(aj_name[k]);
+    for (const ColsumJob& j : cs)  // a job may span several tensors (the branch biases)
+      if (dst >= j.dst && dst + aj[k].rows <= j.dst + j.cols) {
+        aj[k].red = fused_colpart + j.col_offset + (dst - j.dst);
+        aj[k].red_ld = fcs_cols;
+      }
+    if (!aj[k].red) fail(EDPC_E_DEVICE, "no gradient partials for " + aj_name[k]);
+  }
+  d_adam_jobs = dalloc<AdamJob>(aj.size());
+  hip_check(hipMemcpyAsync(d_adam_jobs, aj.data(), aj.size() * sizeof(AdamJob),
+                           hipMemcpyHostToDevice, s), "copy");
   fout.colpart_cols = cols;
   fout.off_b1 = off_b1;
   build_frags(s);
@@ -689,11 +713,15 @@ void Model::step(StepMode mode, const StreamIO& io, const StepOutputs& out, int 
     TIMED(KC_FDM_BWD, k_fdm_bwd(st, X1, dY, U, mU, vU, out.keep_fdm_grad ? dUkeep : nullptr, slot,
                                 L, ac, out.update, dX1_32, dX1_16, R, s));
     TIMED(KC_EMB_GRAD, hip_check(launch_fused_out(F, L, fout, R, s), "fused out launch"));
-    TIMED(KC_EMB_GRAD, k_emb_grad_reduce(st, fused_emb_partial, kFusedRows, E, G_("emb"), s));
     product(PS_WGRAD, 0, R, s);
-    TIMED(KC_COLSUM, k_colsum_reduce(st, d_fcs, n_fcs, fcs_cols, fused_colpart, kFusedRows, s));
-    if (out.update)  // Adam fused with the refresh of the fragment copies
+    if (out.update) {
+      // Adam fused with the refresh of the fragment copies and with the sums
+      // of the bias / embedding gradient partials
       TIMED(KC_ADAM, k_adam_frags(st, d_adam_jobs, n_adam_jobs, adam_items, param, grad, m, v, ac, s));
+    } else {
+      TIMED(KC_EMB_GRAD, k_emb_grad_reduce(st, fused_emb_partial, kFusedRows, E, G_("emb"), s));
+      TIMED(KC_COLSUM, k_colsum_reduce(st, d_fcs, n_fcs, fcs_cols, fused_colpart, kFusedRows, s));
+    }
     hip_check(hipGetLastError(), "step launch");
     return;
   }
