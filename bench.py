@@ -37,6 +37,10 @@ sys.path.insert(0, ROOT)
 METRIC = ("encode/decode MB/s on 1 MI355X (BF16 vs FP32 path) at compressed bits/byte "
           "within 0.5% of oracle")
 HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3}  # dense MFMA peaks of MI355X
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_mid_1024x64KiB.txt")
+KERNEL_SOURCES = ["fused.hip", "fused.h", "kernels.hip", "kernels.h", "common.h", "head_row.h",
+                  "rangecoder.h"]
 
 
 def log(msg):
@@ -141,6 +145,32 @@ def extra_workload(torch, E, name, warmup, steps):
     return res
 
 
+def source_digest():
+    """Digest of the kernel sources the stored counter readings belong to."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2507_18969_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE readings (already scaled by the copy-kernel factor), or None if
+    there are none or the kernel sources changed since they were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            kv = dict(line.strip().split("=", 1) for line in f
+                      if "=" in line and not line.startswith("#"))
+    except OSError:
+        return None
+    if kv.get("source_digest") != source_digest():
+        return None
+    v = kv.get(f"{kernel}.hbm_bytes_per_launch")
+    return int(float(v)) if v else None
+
+
 def fdm_roofline(w, kern, rows):
     """FDM adjoint + Adam kernel: U, m, v read and written per step (24 B per
     element of the active streams' L x L slices) plus the x', dy rows read and
@@ -152,8 +182,39 @@ def fdm_roofline(w, kern, rows):
     gbs = algo / per_launch_s / 1e9
     return {"kernel": "fdm_bwd_adam", "bound": "hbm", "achieved": round(gbs, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
-            "traffic": None, "algorithmic_bytes_per_launch": algo,
+            "traffic": stored_traffic("fdm_bwd_adam"), "algorithmic_bytes_per_launch": algo,
             "avg_launch_us": round(per_launch_s * 1e6, 2)}
+
+
+def dense_flops_per_row(m):
+    """Multiply-adds per row of one pass through the shared dense layers the
+    row-block step runs: LTE up, the blocks' branch and output linears, the head."""
+    F, L, H, N, K = (m["context"] * m["embed"], m["latent"], m["hidden"], m["blocks"],
+                     m["branches"])
+    return F * L + N * (K * H * F + F * H) + 256 * F
+
+
+def fused_roofline(w, kern, rows, precision):
+    """Row-block fused step: forward products and the input adjoints of the
+    same layers (2 passes x 2 flops per multiply-add) for every active row."""
+    ms, launches = kern["fused_rowblock_step"]
+    per_launch_s = ms / launches * 1e-3
+    flops = rows * 4 * dense_flops_per_row(w.model)
+    tf = flops / per_launch_s / 1e12
+    peak = MFMA_PEAK_TFLOPS[precision]
+    return {"kernel": "fused_rowblock_step", "bound": "mfma", "achieved": round(tf, 2),
+            "peak": peak, "unit": "TFLOP/s", "frac": round(tf / peak, 4),
+            "traffic": stored_traffic("fused_rowblock_step"),
+            "algorithmic_flops_per_launch": flops, "avg_launch_us": round(per_launch_s * 1e6, 2)}
+
+
+def dominant_roofline(w, kern, rows, precision):
+    """Roofline of the kernel with the largest share of the step."""
+    share = {k: v[0] for k, v in kern.items() if v[1]}
+    top = max(share, key=share.get)
+    if top == "fused_rowblock_step":
+        return fused_roofline(w, kern, rows, precision)
+    return fdm_roofline(w, kern, rows)
 
 
 def cpu_baseline(w, data, lens, n_model_steps):
@@ -192,13 +253,17 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=16)
     ap.add_argument("--precisions", default="bf16,fp32")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after timing, run a 256 MiB device copy (the reference kernel for "
+                         "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE readings)")
     ap.add_argument("--extra", default="",
                     help="comma list of further workloads measured after the main one "
                          "(ragged, large); reported under extra_workloads")
     a = ap.parse_args()
     if a.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (sharding the "
+              "streams needs a fixed-order exchange of the shared-weight gradients every step, "
+              "which is not implemented)", file=sys.stderr)
         sys.exit(2)
     import torch
 
@@ -230,7 +295,8 @@ def main():
         "decode_MBps": {p: round(v["decode"], 4) for p, v in res.items()},
         "ms_per_step_by_precision": {p: round(v["ms_per_step"], 4) for p, v in res.items()},
         "kernels_ms_per_step": kern,
-        "roofline": fdm_roofline(w, r["kernels"], rows),
+        "roofline": dominant_roofline(w, r["kernels"], rows, main_p),
+        "roofline_hbm": fdm_roofline(w, r["kernels"], rows),
     }
     if "bf16" in res and "fp32" in res:
         line["bf16_over_fp32_encode"] = round(res["bf16"]["encode"] / res["fp32"]["encode"], 3)
@@ -241,6 +307,13 @@ def main():
         line["extra_workloads"] = extra
     if a.full:
         line["full_job"] = {p: full_job(torch, E, w, d_in, lens, p) for p in res}
+    if a.copy_probe:
+        src = torch.ones(1 << 26, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if not a.no_cpu:
         log("CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline(w, data, lens, a.cpu_steps)
