@@ -68,10 +68,33 @@ __device__ __forceinline__ uint32_t wave_max_u(uint32_t v) {
   return v;
 }
 
+// Global-memory view of a generic pointer.  Pointers read from device memory
+// (job tables) are generic to the compiler, which then emits flat accesses;
+// flat loads also count against the LDS wait counter, so every LDS access
+// after them waits for the loads.  Accessing through this view gives global
+// loads and stores.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gl(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
+// 16-byte global loads and stores through the global view (HIP's vector
+// classes cannot be assigned across address spaces, so the data moves as a
+// native 4 x 32-bit vector).
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint4 ld_global16(const void* p) {
+  const u32x4 v = *(const __attribute__((address_space(1))) u32x4*)p;
+  return __builtin_bit_cast(uint4, v);
+}
+__device__ __forceinline__ void st_global16(void* p, uint4 x) {
+  *(__attribute__((address_space(1))) u32x4*)p = __builtin_bit_cast(u32x4, x);
+}
+
 // p[0] + p[stride] + ... + p[(n-1) stride], added strictly in index order;
 // the loads are issued 32 at a time so their latencies overlap (slots past n
 // add an exact zero).
-__device__ __forceinline__ float ordered_sum(const float* __restrict__ p, size_t stride, int n) {
+__device__ __forceinline__ float ordered_sum(const float* __restrict__ pg, size_t stride, int n) {
+  const auto p = gl(pg);
   float s = 0.f;
   for (int k = 0; k < n; k += 32) {
     float v[32];

@@ -23,12 +23,13 @@ __global__ void __launch_bounds__(256) build_frags_kernel(const FragJob* __restr
     const int KB = jb.cols / 32;
     const int nb = local / KB, kb = local % KB;
     const float* s = jb.src + (size_t)(nb * 16 + (lane & 15)) * jb.cols + kb * 32 + 8 * (lane >> 4);
-    const float4 a = *(const float4*)s, b = *(const float4*)(s + 4);
+    const float4 a = __builtin_bit_cast(float4, ld_global16(s));
+    const float4 b = __builtin_bit_cast(float4, ld_global16(s + 4));
     w[0] = (uint32_t)f2bf(a.x) | ((uint32_t)f2bf(a.y) << 16);
     w[1] = (uint32_t)f2bf(a.z) | ((uint32_t)f2bf(a.w) << 16);
     w[2] = (uint32_t)f2bf(b.x) | ((uint32_t)f2bf(b.y) << 16);
     w[3] = (uint32_t)f2bf(b.z) | ((uint32_t)f2bf(b.w) << 16);
-    jb.nt[(size_t)local * 64 + lane] = make_uint4(w[0], w[1], w[2], w[3]);
+    st_global16(jb.nt + (size_t)local * 64 + lane, make_uint4(w[0], w[1], w[2], w[3]));
   } else {  // nn
     local -= nfr;
     const int KB = jb.rows / 32;
@@ -37,10 +38,10 @@ __global__ void __launch_bounds__(256) build_frags_kernel(const FragJob* __restr
     const int k0 = kb * 32 + 8 * (lane >> 4);
     bf16_t h[8];
 #pragma unroll
-    for (int v = 0; v < 8; ++v) h[v] = f2bf(jb.src[(size_t)(k0 + v) * jb.cols + col]);
+    for (int v = 0; v < 8; ++v) h[v] = f2bf(gl(jb.src)[(size_t)(k0 + v) * jb.cols + col]);
 #pragma unroll
     for (int q = 0; q < 4; ++q) w[q] = (uint32_t)h[2 * q] | ((uint32_t)h[2 * q + 1] << 16);
-    jb.nn[(size_t)local * 64 + lane] = make_uint4(w[0], w[1], w[2], w[3]);
+    st_global16(jb.nn + (size_t)local * 64 + lane, make_uint4(w[0], w[1], w[2], w[3]));
   }
 }
 
@@ -150,7 +151,8 @@ __global__ void __launch_bounds__(256) adam_frags_kernel(const StepState* __rest
                               (uint32_t)f2bf(nv[4]) | ((uint32_t)f2bf(nv[5]) << 16),
                               (uint32_t)f2bf(nv[6]) | ((uint32_t)f2bf(nv[7]) << 16));
   // nt fragment (nb = row/16, kb = col/32), lane = row%16 + 16*((col%32)/8)
-  jb.nt[((size_t)(row >> 4) * (jb.cols / 32) + (col >> 5)) * 64 + (row & 15) + 16 * ((col & 31) >> 3)] = pk;
+  st_global16(jb.nt + ((size_t)(row >> 4) * (jb.cols / 32) + (col >> 5)) * 64 + (row & 15) +
+                  16 * ((col & 31) >> 3), pk);
   *(uint4*)&tile[tr][tc] = pk;
   __syncthreads();
   // nn fragment (nb = col/16, kb = row/32), lane = col%16 + 16*((row%32)/8):
@@ -161,8 +163,8 @@ __global__ void __launch_bounds__(256) adam_frags_kernel(const StepState* __rest
 #pragma unroll
   for (int k = 0; k < 4; ++k)
     w[k] = (uint32_t)tile[rr + 2 * k][cc] | ((uint32_t)tile[rr + 2 * k + 1][cc] << 16);
-  jb.nn[((size_t)((c0 + cc) >> 4) * (jb.rows / 32) + (r0 >> 5)) * 64 + l] =
-      make_uint4(w[0], w[1], w[2], w[3]);
+  st_global16(jb.nn + ((size_t)((c0 + cc) >> 4) * (jb.rows / 32) + (r0 >> 5)) * 64 + l,
+              make_uint4(w[0], w[1], w[2], w[3]));
 }
 
 void k_adam_frags(const StepState* st, const AdamJob* jobs, int n_jobs, int total_items, float* p,

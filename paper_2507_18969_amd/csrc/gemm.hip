@@ -111,7 +111,7 @@ struct Stage {
           const int gk = k0 + kb * 8 + i;
           uint4 val = make_uint4(0, 0, 0, 0);
           if (b < NBLK && gr < rows_valid && gk < K)
-            val = *(const uint4*)(src + ((long long)gk * ld + gr) * esz);
+            val = ld_global16(src + ((long long)gk * ld + gr) * esz);
           reg[8 * p + i] = val;
         }
       }
@@ -126,12 +126,12 @@ struct Stage {
           const int row = v / (BK / VEC), kq = v % (BK / VEC);
           const int gr = row0 + row, gk = k0 + kq * VEC;
           if (gr < rows_valid && gk < K)
-            val = *(const uint4*)(src + ((long long)gr * ld + gk) * esz);
+            val = ld_global16(src + ((long long)gr * ld + gk) * esz);
         } else {
           const int k = v / (ROWS / VEC), rq = v % (ROWS / VEC);
           const int gr = row0 + rq * VEC, gk = k0 + k;
           if (gr < rows_valid && gk < K)
-            val = *(const uint4*)(src + ((long long)gk * ld + gr) * esz);
+            val = ld_global16(src + ((long long)gk * ld + gr) * esz);
         }
       }
       reg[p] = val;
@@ -367,7 +367,7 @@ __global__ void __launch_bounds__(kThreads) wgrad_kernel(const WgradProblem* __r
       for (int r = 0; r < TC::Op::NACC; ++r) {
         const int m = m0 + (wm * T::TM + i) * T::MB + acc_row<T::MB>(r, lane);
         const int n = n0 + (wn * T::TN + j) * T::MB + acc_col<T::MB>(lane);
-        if (m < pr.M && n < pr.N) pr.dw[(long long)m * pr.N + n] = tc.acc[0][i][j][r];
+        if (m < pr.M && n < pr.N) gl(pr.dw)[(long long)m * pr.N + n] = tc.acc[0][i][j][r];
       }
 }
 

@@ -497,16 +497,18 @@ __global__ void __launch_bounds__(256) colsum_partial_kernel(const StepState* __
   const int slice = threadIdx.x >> 6;
   const int r1 = min(rows, r0 + kColChunk);
   float acc = 0.f;
+  const auto src = gl(jb.src);
   if (lc < jb.cols) {
     if (jb.h) {
+      const auto h = gl(jb.h), mean = gl(jb.mean), rstd = gl(jb.rstd);
 #pragma unroll 4
       for (int r = r0 + slice; r < r1; r += 4) {
-        const float xh = (jb.h[(size_t)r * jb.ld + lc] - jb.mean[r]) * jb.rstd[r];
-        acc += jb.src[(size_t)r * jb.ld + lc] * xh;
+        const float xh = (h[(size_t)r * jb.ld + lc] - mean[r]) * rstd[r];
+        acc += src[(size_t)r * jb.ld + lc] * xh;
       }
     } else {
 #pragma unroll 4
-      for (int r = r0 + slice; r < r1; r += 4) acc += jb.src[(size_t)r * jb.ld + lc];
+      for (int r = r0 + slice; r < r1; r += 4) acc += src[(size_t)r * jb.ld + lc];
     }
   }
   __shared__ float part[4][64];
@@ -530,7 +532,7 @@ __global__ void colsum_reduce_kernel(const StepState* __restrict__ st,
   const ColsumJob& jb = jobs[j];
   const int nch = (st->rows + chunk - 1) / chunk;
   const float s = ordered_sum(partial + c, (size_t)total_cols, nch);
-  jb.dst[c - jb.col_offset] = s * (jb.scale == 0.0f ? st->inv_rows : jb.scale);
+  gl(jb.dst)[c - jb.col_offset] = s * (jb.scale == 0.0f ? st->inv_rows : jb.scale);
 }
 
 size_t colsum_partial_elems(int max_rows, int total_cols) {
