@@ -655,6 +655,9 @@ void k_emb_grad(const StepState* st, const uint8_t* ctx, const float* dx, int C,
   const size_t smem = (size_t)sub_rows * C * E * sizeof(float) + (size_t)sub_rows * C + 32;
 #define EMB_CASE(EE)                                                                            \
   case EE:                                                                                      \
+    if (smem > 65536)  /* the widest feature vectors need more than the default LDS */          \
+      (void)hipFuncSetAttribute((const void*)emb_grad_partial_kernel<EE>,                       \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);         \
     hipLaunchKernelGGL(emb_grad_partial_kernel<EE>, dim3(nb), dim3(256), smem, s, st, ctx, dx, C, \
                        chunk_rows, sub_rows, partial);                                          \
     break;

@@ -94,7 +94,7 @@ static bool pow2(uint32_t x) { return x && !(x & (x - 1)); }
 
 void Model::validate(const edpc_config& c) {
   if (c.struct_size != sizeof(edpc_config)) fail(EDPC_E_INVALID_ARG, "edpc_config.struct_size mismatch");
-  if (c.context < 4 || c.context > 256) fail(EDPC_E_INVALID_ARG, "context must be in 1..256");
+  if (c.context < 4 || c.context > 256) fail(EDPC_E_INVALID_ARG, "context must be in 4..256");
   if (!pow2(c.embed) || c.embed < 16 || c.embed > 64) fail(EDPC_E_INVALID_ARG, "embed must be a power of two in 16..64");
   if (c.context % 4) fail(EDPC_E_INVALID_ARG, "context must be a multiple of 4");
   if (!pow2(c.latent) || c.latent < 16 || c.latent > 256) fail(EDPC_E_INVALID_ARG, "latent must be a power of two in 16..256");
