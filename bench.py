@@ -273,7 +273,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--full", action="store_true", help="also time a whole encode + decode")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-steps", type=int, default=16)
+    ap.add_argument("--cpu-steps", type=int, default=64)
     ap.add_argument("--precisions", default="bf16,fp32")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after timing, run a 256 MiB device copy (the reference kernel for "

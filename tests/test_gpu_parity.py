@@ -406,3 +406,23 @@ def test_extreme_shapes_one_step_and_roundtrip(E, shape, precision):
     cont = _encode(E, lib_cfg(E, model, precision), flat, lens)
     out, _ = E.edpc_decode(cont)
     assert out.cpu().numpy().tobytes() == flat.tobytes()
+
+
+@pytest.mark.parametrize("branches", [1, 3])
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_branch_count_variants(E, branches, precision):
+    # refinement blocks with one or three branches (Eq. 11 with k = 1, 3; the
+    # paper's three-branch ablation); BF16 runs the layer-by-layer products
+    model = dict(SMALL, branches=branches)
+    C = model["context"]
+    om, m, ctx, tgt = _step_case(E, model, precision, rows=8, pos=C + 8, om_steps=8, prefix=C + 9)
+    if precision == "fp32":
+        _, g_o, dU_o = _compare_step(E, om, m, ctx, tgt, p_tol=1e-5, g_rtol=1e-4)
+        _compare_update(E, om, m, ctx, tgt, g_o, dU_o, tol=1e-6)
+    else:
+        _compare_step(E, om, m, ctx, tgt, p_tol=2e-3, g_rtol=3e-2)
+    del m
+    data, lens = gen.make_streams("small", prefix=200, n_streams=4)
+    cont = _encode(E, lib_cfg(E, model, precision), data, lens)
+    out, _ = E.edpc_decode(cont)
+    assert out.cpu().numpy().tobytes() == data.tobytes()
