@@ -592,15 +592,22 @@ __global__ void __launch_bounds__(256) emb_grad_partial_kernel(
     for (int k = threadIdx.x; k < nr * F / 4; k += 256) ((float4*)lds_dx)[k] = src[k];
     for (int k = threadIdx.x; k < nr * C; k += 256) lds_ctx[k] = ctx[(size_t)rs * C + k];
     __syncthreads();
-    const int np = nr * C;  // multiple of 4 when C is
+    // pairs p = i C + c in row-major order, 4 per MFMA step; C is a multiple
+    // of 4, so a step stays inside row i and p / C, p % C follow incrementally
+    const int np = nr * C;
+    int pi = 0, pc = 0;
     for (int k0 = 0; k0 < np; k0 += 4) {
       const int p = k0 + (lane >> 4);
-      const bool ok = p < np;
-      const int v = ok ? (int)lds_ctx[p] : -1;
-      const float* d = lds_dx + (size_t)(p / C) * F + (p % C) * E + (lane & 15);
+      const int v = (int)lds_ctx[p];
+      const float* d = lds_dx + (size_t)pi * F + (pc + (lane >> 4)) * E + (lane & 15);
+      pc += 4;
+      if (pc == C) {
+        pc = 0;
+        ++pi;
+      }
       float b[NE];
 #pragma unroll
-      for (int nb = 0; nb < NE; ++nb) b[nb] = ok ? d[16 * nb] : 0.f;
+      for (int nb = 0; nb < NE; ++nb) b[nb] = d[16 * nb];
 #pragma unroll
       for (int vb = 0; vb < 4; ++vb) {
         const float a = (v == 64 * w + 16 * vb + (lane & 15)) ? 1.0f : 0.0f;
@@ -636,7 +643,7 @@ void emb_grad_plan(int max_rows, int C, int E, int* chunk_rows, int* sub_rows) {
   int sub = 8192 / F;
   sub = sub < 1 ? 1 : (sub > 16 ? 16 : sub);
   int chunk = sub;
-  while ((max_rows + chunk - 1) / chunk > 128) chunk += sub;
+  while ((max_rows + chunk - 1) / chunk > 256) chunk += sub;
   *chunk_rows = chunk;
   *sub_rows = sub;
 }
