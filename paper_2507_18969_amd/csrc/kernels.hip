@@ -106,6 +106,20 @@ void k_embed(const StepState* st, const uint8_t* ctx, const float* emb, int C, i
                      x32, x16);
 }
 
+// Streaming (non-temporal) 16-byte accesses for the Adam moments of the FDM:
+// every element of m_U, v_U is read and written once per step, while U is
+// read again by the next step's forward product and keeps normal caching.
+__device__ __forceinline__ float4 nt_load4(const float* p) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  const f4 v = __builtin_nontemporal_load((const f4*)p);
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void nt_store4(float* p, float4 x) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  const f4 v = {x.x, x.y, x.z, x.w};
+  __builtin_nontemporal_store(v, (f4*)p);
+}
+
 // Rows of U_s whose loads are issued together in the FDM kernels.
 constexpr int kFdmBatch = 4;
 
@@ -216,14 +230,14 @@ __global__ void __launch_bounds__(256) fdm_bwd_kernel(
         up[j] -= lr_bc * mp[j] / (sqrtf(vp[j] * inv_bc2) + ac.eps);
       }
       *(float4*)(U + idx) = u;
-      *(float4*)(mU + idx) = m;
-      *(float4*)(vU + idx) = v;
+      nt_store4(mU + idx, m);
+      nt_store4(vU + idx, v);
     }
   };
   for (int l = g; l < L; l += G) {
     const size_t idx = base_s + (size_t)l * L + 4 * t;
-    row(l, *(const float4*)(U + idx), update ? *(const float4*)(mU + idx) : make_float4(0.f, 0.f, 0.f, 0.f),
-        update ? *(const float4*)(vU + idx) : make_float4(0.f, 0.f, 0.f, 0.f));
+    row(l, *(const float4*)(U + idx), update ? nt_load4(mU + idx) : make_float4(0.f, 0.f, 0.f, 0.f),
+        update ? nt_load4(vU + idx) : make_float4(0.f, 0.f, 0.f, 0.f));
   }
 }
 
