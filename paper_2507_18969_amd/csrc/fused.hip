@@ -71,12 +71,15 @@ __device__ __forceinline__ void transpose8x8(const uint4* in, uint4* out) {
 // gradients gv; the updated values are returned in out.
 __device__ __forceinline__ void adam8(float* pp, const float gv[8], float* mp, float* vp, float lr_bc,
                                       float inv_bc2, const AdamCfg& ac, float out[8]) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
   float4 p4[2], m4[2], v4[2];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     p4[h] = ((const float4*)pp)[h];
-    m4[h] = ((const float4*)mp)[h];
-    v4[h] = ((const float4*)vp)[h];
+    const f4 mv = __builtin_nontemporal_load((const f4*)mp + h);  // moments: once per step
+    const f4 vv = __builtin_nontemporal_load((const f4*)vp + h);
+    m4[h] = make_float4(mv.x, mv.y, mv.z, mv.w);
+    v4[h] = make_float4(vv.x, vv.y, vv.z, vv.w);
   }
   float* P = (float*)p4;
   float* M = (float*)m4;
@@ -91,8 +94,8 @@ __device__ __forceinline__ void adam8(float* pp, const float gv[8], float* mp, f
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     ((float4*)pp)[h] = p4[h];
-    ((float4*)mp)[h] = m4[h];
-    ((float4*)vp)[h] = v4[h];
+    __builtin_nontemporal_store(f4{m4[h].x, m4[h].y, m4[h].z, m4[h].w}, (f4*)mp + h);
+    __builtin_nontemporal_store(f4{v4[h].x, v4[h].y, v4[h].z, v4[h].w}, (f4*)vp + h);
   }
 }
 
