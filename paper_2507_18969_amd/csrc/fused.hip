@@ -198,16 +198,43 @@ __device__ __forceinline__ f32x4 mfma16(uint4 a, uint4 b, f32x4 c) {
 // fragment offset from an SGPR, so in-flight loads cost no address registers.
 // The scheduling barriers keep the compiler from sinking the loads next to
 // their uses.
+template <int K, int NT, int B>
+struct MmShape {
+  static constexpr int KB = K / 32;
+  static constexpr int TOT = KB * NT;
+  static constexpr int BB = B < TOT ? B : TOT;
+  static constexpr int NBT = (TOT + BB - 1) / BB;
+};
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t frag_rsrc(const uint4* base) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, 0x7FFFFFFF, kBufferWord3);
+}
+
+// First batch of a product's fragment loads, into buf[0 .. BB-1]; issued
+// ahead of the product (before the previous stage's epilogue) so that its
+// latency overlaps that work.
+template <int K, int NT, int B>
+__device__ __forceinline__ void mm_first(const uint4* __restrict__ base, const int (&cb)[NT],
+                                         uint4 (&buf)[B]) {
+  typedef MmShape<K, NT, B> S;
+  const __amdgpu_buffer_rsrc_t rs = frag_rsrc(base);
+  const int voff = (threadIdx.x & 63) * 16;
+#pragma unroll
+  for (int q = 0; q < S::BB; ++q) {
+    const int soff = (cb[q % NT] * S::KB + q / NT) * 1024;
+    buf[q] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, 0));
+  }
+}
+
+// The product, its first batch already in first[] (see mm_first).
 template <int K, int NT, int B, typename Between>
-__device__ __forceinline__ void mm(const bf16_t* sA, int lda, const uint4* __restrict__ base,
-                                   const int (&cb)[NT], f32x4 (&acc)[NT], Between&& between) {
-  constexpr int KB = K / 32;
-  constexpr int TOT = KB * NT;
-  constexpr int BB = B < TOT ? B : TOT;
-  constexpr int NBT = (TOT + BB - 1) / BB;
+__device__ __forceinline__ void mm_rest(const bf16_t* sA, int lda, const uint4* __restrict__ base,
+                                        const int (&cb)[NT], f32x4 (&acc)[NT],
+                                        const uint4 (&first)[B], Between&& between) {
+  typedef MmShape<K, NT, B> S;
+  constexpr int KB = S::KB, TOT = S::TOT, BB = S::BB, NBT = S::NBT;
   const int lane = threadIdx.x & 63;
-  const __amdgpu_buffer_rsrc_t rs =
-      __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, 0x7FFFFFFF, kBufferWord3);
+  const __amdgpu_buffer_rsrc_t rs = frag_rsrc(base);
   const int voff = lane * 16;
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -218,7 +245,7 @@ __device__ __forceinline__ void mm(const bf16_t* sA, int lda, const uint4* __res
   const bf16_t* arow = sA + (lane & 15) * lda + 8 * (lane >> 4);
   uint4 buf[2][BB];
 #pragma unroll
-  for (int q = 0; q < BB; ++q) buf[0][q] = frag(q);
+  for (int q = 0; q < BB; ++q) buf[0][q] = first[q];
   // work that only needs the LDS state left by the previous stage (copies of
   // its results to global memory) goes behind the first batch, so the
   // fragment waits do not include its stores
@@ -247,10 +274,35 @@ __device__ __forceinline__ void mm(const bf16_t* sA, int lda, const uint4* __res
   }
 }
 
+// acc[t] = A (16 rows in LDS, bf16, row stride lda, K columns) x fragments of
+// column block cb[t] (fragment base + cb*K/32*64 uint4), for the NT column
+// blocks of this wave (cb must be wave-uniform).  The wave's fragments, taken
+// in the order i = kb * NT + t, stream in batches of B buffer loads issued back
+// to back; batch b + 1 is issued before batch b feeds the MFMAs, so up to 2B
+// loads are in flight.  Each load takes the lane offset from one VGPR and the
+// fragment offset from an SGPR, so in-flight loads cost no address registers.
+// The scheduling barriers keep the compiler from sinking the loads next to
+// their uses.
+template <int K, int NT, int B, typename Between>
+__device__ __forceinline__ void mm(const bf16_t* sA, int lda, const uint4* __restrict__ base,
+                                   const int (&cb)[NT], f32x4 (&acc)[NT], Between&& between) {
+  uint4 first[B];
+  mm_first<K, NT, B>(base, cb, first);
+  mm_rest<K, NT, B>(sA, lda, base, cb, acc, first, between);
+}
+
 template <int K, int NT, int B>
 __device__ __forceinline__ void mm(const bf16_t* sA, int lda, const uint4* __restrict__ base,
                                    const int (&cb)[NT], f32x4 (&acc)[NT]) {
   mm<K, NT, B>(sA, lda, base, cb, acc, [] {});
+}
+
+// Barrier for LDS traffic only: waits for the wave's LDS accesses, not for its
+// outstanding global loads and stores.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 constexpr int kFusedWaves = 8;  // waves of a row-block workgroup
@@ -355,6 +407,21 @@ __global__ void __launch_bounds__(kFusedThreads, 1) fused_kernel(FusedArgs a) {
   float* colp = a.colpart + (size_t)blockIdx.x * a.colpart_cols;
   const int NB = a.n_blocks;
   const int mode = a.head.mode;
+  // next product's first batch of weight fragments, issued before the
+  // current stage's epilogue
+  uint4 pf[kFusedBatch];
+  constexpr int NTF = ColSplit<F>::NT, NHH = ColSplit<H>::NT;
+  auto cb_cols = [&](auto& cb) {  // column blocks w, w + NW, ...
+#pragma unroll
+    for (int t = 0; t < (int)(sizeof(cb) / sizeof(cb[0])); ++t) cb[t] = w + NW * t;
+  };
+  auto cb_branches = [&](int (&cb)[2 * NHH]) {  // both branches' blocks
+#pragma unroll
+    for (int t = 0; t < NHH; ++t) {
+      cb[t] = w + NW * t;
+      cb[NHH + t] = H / 16 + w + NW * t;
+    }
+  };
 
   // ---- LTE up-projection (Eq. 16): X'' = W2 Y + b2 -------------------------
   if (w == NW - 1) {
@@ -399,6 +466,11 @@ __global__ void __launch_bounds__(kFusedThreads, 1) fused_kernel(FusedArgs a) {
       bias[t] = a.b2[cb[t] * 16 + lc];
     }
     mm<L, NT, kFusedBatch>(&sA[0][0], LDA, a.w2_nt, cb, acc);
+    {
+      int cbn[2 * NHH];
+      cb_branches(cbn);
+      mm_first<F, 2 * NHH, kFusedBatch>(a.wab_nt[0], cbn, pf);
+    }
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       const int c = cb[t] * 16 + lc;
@@ -406,7 +478,7 @@ __global__ void __launch_bounds__(kFusedThreads, 1) fused_kernel(FusedArgs a) {
       for (int r = 0; r < 4; ++r) sH[li + r][c] = acc[t][r] + bias[t];
     }
   }
-  __syncthreads();
+  lds_barrier();
 
   // ---- refinement blocks (Eqs. 9-13) ----------------------------------------
   for (int j = 0; j < NB; ++j) {
@@ -441,7 +513,7 @@ __global__ void __launch_bounds__(kFusedThreads, 1) fused_kernel(FusedArgs a) {
         sStat[j][i][1] = rs;
       }
     }
-    __syncthreads();
+    lds_barrier();
     {  // branches (Eq. 10), product fusion (Eq. 11), GeLU (Eq. 12)
       constexpr int NH = ColSplit<H>::NT;
       constexpr int NT = 2 * NH;
@@ -455,10 +527,15 @@ __global__ void __launch_bounds__(kFusedThreads, 1) fused_kernel(FusedArgs a) {
         bias0[t] = a.bab[j][cb[t] * 16 + lc];
         bias1[t] = a.bab[j][H + cb[t] * 16 + lc];
       }
-      mm<F, NT, kFusedBatch>(&sA[0][0], LDA, a.wab_nt[j], cb, acc, [&] {
+      mm_rest<F, NT, kFusedBatch>(&sA[0][0], LDA, a.wab_nt[j], cb, acc, pf, [&] {
         copy_rows<F>(&sA[0][0], LDA, a.z16[j], F, r0, nr);   // LayerNorm output
         copy_rows<F>(&sH[0][0], LDH, a.hs[j], F, r0, nr);    // block input
       });
+      {
+        int cbn[NTF];
+        cb_cols(cbn);
+        mm_first<H, NTF, kFusedBatch>(a.wo_nt[j], cbn, pf);
+      }
 #pragma unroll
       for (int t = 0; t < NH; ++t) {
         const int c = cb[t] * 16 + lc;
@@ -473,7 +550,7 @@ __global__ void __launch_bounds__(kFusedThreads, 1) fused_kernel(FusedArgs a) {
         }
       }
     }
-    __syncthreads();
+    lds_barrier();
     {  // output linear + residual (Eq. 13)
       constexpr int NT = ColSplit<F>::NT;
       int cb[NT];
@@ -484,10 +561,19 @@ __global__ void __launch_bounds__(kFusedThreads, 1) fused_kernel(FusedArgs a) {
         cb[t] = w + NW * t;
         bias[t] = a.bo[j][cb[t] * 16 + lc];
       }
-      mm<H, NT, kFusedBatch>(&sB[0][0], LDA, a.wo_nt[j], cb, acc, [&] {
+      mm_rest<H, NT, kFusedBatch>(&sB[0][0], LDA, a.wo_nt[j], cb, acc, pf, [&] {
         copy_rows<H>(&sB[0][0], LDA, a.g16[j], H, r0, nr);     // GeLU output
         copy_rows<H2>(&sF[0][0], LDF, a.abr[j], H2, r0, nr);   // branch values
       });
+      if (j + 1 < NB) {
+        int cbn[2 * NHH];
+        cb_branches(cbn);
+        mm_first<F, 2 * NHH, kFusedBatch>(a.wab_nt[j + 1], cbn, pf);
+      } else {
+        int cbn[ColSplit<256>::NT];
+        cb_cols(cbn);
+        mm_first<F, ColSplit<256>::NT, kFusedBatch>(a.wh_nt, cbn, pf);
+      }
       const bool last = j == NB - 1;
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
@@ -501,7 +587,7 @@ __global__ void __launch_bounds__(kFusedThreads, 1) fused_kernel(FusedArgs a) {
         }
       }
     }
-    __syncthreads();
+    lds_barrier();
   }
 
   // ---- head logits ------------------------------------------------------------
@@ -515,9 +601,14 @@ __global__ void __launch_bounds__(kFusedThreads, 1) fused_kernel(FusedArgs a) {
       cb[t] = w + NW * t;
       bias[t] = a.bh[cb[t] * 16 + lc];
     }
-    mm<F, NT, kFusedBatch>(&sA[0][0], LDA, a.wh_nt, cb, acc, [&] {
+    mm_rest<F, NT, kFusedBatch>(&sA[0][0], LDA, a.wh_nt, cb, acc, pf, [&] {
       copy_rows<F>(&sA[0][0], LDA, a.hn16, F, r0, nr);  // final features
     });
+    if (a.head.want_grad) {
+      int cbn[NTF];
+      cb_cols(cbn);
+      mm_first<256, NTF, kFusedBatch>(a.wh_nn, cbn, pf);
+    }
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       const int c = cb[t] * 16 + lc;
@@ -525,7 +616,7 @@ __global__ void __launch_bounds__(kFusedThreads, 1) fused_kernel(FusedArgs a) {
       for (int r = 0; r < 4; ++r) sF[li + r][c] = acc[t][r] + bias[t];
     }
   }
-  __syncthreads();
+  lds_barrier();
 
   // ---- softmax, CDF, coder, cross-entropy adjoint (Eqs. 1-2) ------------------
   const bool grad = a.head.want_grad != 0;
@@ -586,11 +677,16 @@ __global__ void __launch_bounds__(kFusedThreads, 1) fused_kernel(FusedArgs a) {
     f32x4 acc[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) cb[t] = w + NW * t;
-    mm<256, NT, kFusedBatch>(&sA[0][0], LDA, a.wh_nn, cb, acc, [&] {
+    mm_rest<256, NT, kFusedBatch>(&sA[0][0], LDA, a.wh_nn, cb, acc, pf, [&] {
       copy_rows<256>(&sA[0][0], LDA, a.dz16, 256, r0, nr);      // logit adjoint
       col_sums<256>(&sF[0][0], LDF, nr, colp + a.off_bh);       // head bias gradient
     });
-    __syncthreads();  // every wave is done reading sA / sF
+    {
+      int cbn[NHH];
+      cb_cols(cbn);
+      mm_first<F, NHH, kFusedBatch>(a.wo_nn[NB - 1], cbn, pf);
+    }
+    lds_barrier();  // every wave is done reading sA / sF
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       const int c = cb[t] * 16 + lc;
@@ -602,7 +698,7 @@ __global__ void __launch_bounds__(kFusedThreads, 1) fused_kernel(FusedArgs a) {
       }
     }
   }
-  __syncthreads();
+  lds_barrier();
 
   for (int j = NB - 1; j >= 0; --j) {
     {  // dX_ff = dH Wo; through GeLU and the branch product (adjoint of Eqs. 11-13)
@@ -625,7 +721,7 @@ __global__ void __launch_bounds__(kFusedThreads, 1) fused_kernel(FusedArgs a) {
           }
         }
       }
-      mm<F, NH, kFusedBatch>(&sA[0][0], LDA, a.wo_nn[j], cb, acc, [&] {
+      mm_rest<F, NH, kFusedBatch>(&sA[0][0], LDA, a.wo_nn[j], cb, acc, pf, [&] {
         copy_rows<F>(&sA[0][0], LDA, a.dh16[j + 1], F, r0, nr);  // adjoint of the block output
         col_sums<F>(&sH[0][0], LDH, nr, colp + a.off_bo[j]);     // output bias gradient
         if (j + 1 < NB) {  // affine gradients of the LayerNorm of block j + 1
@@ -635,6 +731,11 @@ __global__ void __launch_bounds__(kFusedThreads, 1) fused_kernel(FusedArgs a) {
           }
         }
       });
+      {
+        int cbn[NTF];
+        cb_cols(cbn);
+        mm_first<H2, NTF, kFusedBatch>(a.wab_nn[j], cbn, pf);
+      }
 #pragma unroll
       for (int t = 0; t < NH; ++t) {
         const int c = cb[t] * 16 + lc;
@@ -651,7 +752,7 @@ __global__ void __launch_bounds__(kFusedThreads, 1) fused_kernel(FusedArgs a) {
         }
       }
     }
-    __syncthreads();
+    lds_barrier();
     {  // dX0 = sum_i dX_i W_i, then the LayerNorm adjoint (Eq. 9)
       constexpr int NT = ColSplit<F>::NT;
       int cb[NT];
@@ -668,10 +769,19 @@ __global__ void __launch_bounds__(kFusedThreads, 1) fused_kernel(FusedArgs a) {
           xh[t][r] = i < nr ? a.hs[j][(r0 + i) * F + c] : 0.f;
         }
       }
-      mm<H2, NT, kFusedBatch>(&sB[0][0], LDA, a.wab_nn[j], cb, acc, [&] {
+      mm_rest<H2, NT, kFusedBatch>(&sB[0][0], LDA, a.wab_nn[j], cb, acc, pf, [&] {
         copy_rows<H2>(&sB[0][0], LDA, a.da16[j], H2, r0, nr);  // branch adjoints
         col_sums<H2>(&sF[0][0], LDF, nr, colp + a.off_bab[j]);  // branch bias gradients
       });
+      if (j > 0) {
+        int cbn[NHH];
+        cb_cols(cbn);
+        mm_first<F, NHH, kFusedBatch>(a.wo_nn[j - 1], cbn, pf);
+      } else if (ColSplit<L>::active(w)) {
+        int cbn[ColSplit<L>::NT];
+        cb_cols(cbn);
+        mm_first<F, ColSplit<L>::NT, kFusedBatch>(a.w2_nn, cbn, pf);
+      }
       float s1[4] = {0.f, 0.f, 0.f, 0.f}, s2[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
@@ -714,7 +824,7 @@ __global__ void __launch_bounds__(kFusedThreads, 1) fused_kernel(FusedArgs a) {
           sRed[w][li + r][1] = s2[r];
         }
       }
-      __syncthreads();
+      lds_barrier();
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int i = li + r;
@@ -737,7 +847,7 @@ __global__ void __launch_bounds__(kFusedThreads, 1) fused_kernel(FusedArgs a) {
         }
       }
     }
-    __syncthreads();
+    lds_barrier();
   }
 
   // ---- adjoint of Eq. 16 ---------------------------------------------------------
@@ -755,7 +865,7 @@ __global__ void __launch_bounds__(kFusedThreads, 1) fused_kernel(FusedArgs a) {
     f32x4 acc[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) cb[t] = w + NW * t;
-    mm<F, NT, kFusedBatch>(&sA[0][0], LDA, a.w2_nn, cb, acc, tail);
+    mm_rest<F, NT, kFusedBatch>(&sA[0][0], LDA, a.w2_nn, cb, acc, pf, tail);
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       const int c = cb[t] * 16 + lc;
