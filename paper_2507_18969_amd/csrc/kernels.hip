@@ -9,17 +9,30 @@ static inline unsigned blocks_for(size_t n, unsigned per) { return (unsigned)((n
 // ---------------------------------------------------------------------------
 // Step state
 // ---------------------------------------------------------------------------
-__global__ void step_schedule_kernel(StepState* st, Schedule sc, int step) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// rows = number of streams with length > step (lens sorted decreasing).  A
+// 256-way search: each round every thread tests one of 256 evenly spaced
+// positions of the open range and the count of true tests narrows the range to
+// one gap between positions, so n streams take ceil(log_256 n) rounds of one
+// load each instead of log_2 n dependent loads.
+constexpr int kScheduleThreads = 256;
+
+__global__ void __launch_bounds__(kScheduleThreads) step_schedule_kernel(StepState* st, Schedule sc,
+                                                                         int step) {
   if (step < 0) step = st->step + 1;
-  // rows = number of streams with length > step (lens sorted decreasing)
-  int lo = 0, hi = sc.n;
+  const int64_t t = threadIdx.x;
+  int64_t lo = 0, hi = sc.n;  // the count lies in [lo, hi]
   while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (sc.lens_sorted[mid] > (int64_t)step) lo = mid + 1; else hi = mid;
+    const int64_t chunk = (hi - lo + kScheduleThreads - 1) / kScheduleThreads;
+    const int64_t i = lo + t * chunk;
+    const int c = __syncthreads_count(i < hi && sc.lens_sorted[i] > (int64_t)step);
+    const int64_t nlo = c == 0 ? lo : lo + (c - 1) * chunk + 1;
+    hi = min(lo + c * chunk, hi);
+    lo = nlo;
   }
+  __syncthreads();  // every thread has read st->step
+  if (t != 0) return;
   st->step = step;
-  st->rows = lo;
+  st->rows = (int)lo;
   st->inv_rows = lo > 0 ? 1.0f / (float)lo : 0.0f;
   st->model = step >= sc.context ? 1 : 0;
   const uint32_t tau = step >= sc.context ? (uint32_t)(step - sc.context + 1) : 0u;
@@ -29,7 +42,7 @@ __global__ void step_schedule_kernel(StepState* st, Schedule sc, int step) {
 }
 
 void k_step_schedule(StepState* st, Schedule sc, int step, hipStream_t s) {
-  hipLaunchKernelGGL(step_schedule_kernel, dim3(1), dim3(64), 0, s, st, sc, step);
+  hipLaunchKernelGGL(step_schedule_kernel, dim3(1), dim3(kScheduleThreads), 0, s, st, sc, step);
 }
 
 __global__ void step_set_kernel(StepState* st, int step) {

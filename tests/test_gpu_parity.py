@@ -285,6 +285,23 @@ def test_roundtrip_ragged_empty_short(E):
         assert len(p) == 0 if len(s) == 0 else abs(len(p) - len(po)) <= 2
 
 
+def test_roundtrip_many_ragged_streams(E):
+    # 600 streams of 91 different lengths (0 .. 90): the per-step count of
+    # active streams takes more than one round of the schedule's 256-way search
+    data, lens = gen.make_streams("mid_fp32", prefix=90, n_streams=600)
+    cuts = np.random.default_rng(1031).integers(0, 91, size=600)
+    st = [s[:c] for s, c in zip(split_streams(data, lens), cuts)]
+    flat = np.frombuffer(b"".join(st), dtype=np.uint8)
+    cont = _encode(E, lib_cfg(E, SMALL), flat, cuts)
+    out, lens_back = E.edpc_decode(cont)
+    assert list(lens_back) == list(cuts)
+    assert out.cpu().numpy().tobytes() == b"".join(st)
+    _, pays = parse_container(cont.cpu().numpy().tobytes())
+    pay_o, _ = oracle.encode(st, oracle_cfg(SMALL))
+    for s, p, po in zip(st, pays, pay_o):
+        assert len(p) == 0 if len(s) == 0 else abs(len(p) - len(po)) <= 2
+
+
 def test_small_full_roundtrip_determinism_and_size(E):
     data, lens = gen.make_streams("small")
     cfg = lib_cfg(E, SMALL)
