@@ -9,6 +9,9 @@ Test infrastructure only.  Follows the paper's equations in their order:
   (Eq. 14), per-instance Feature Distribution Matrix Y = bmm(X', U)
   (Eq. 15, row vector times matrix, U of shape [b, F', F']), up-projection
   X'' = W2 Y + b2 (Eq. 16); no activation inside the LTE;
+* the "w/o LTE" ablation (Table 4, Sec. 4.4.1), ``lte=False``: no W1, b1, W2,
+  b2; the per-instance FDM acts on the F-wide features directly, Y = bmm(X, U)
+  with U of shape [b, F, F], and Y feeds the first block (latent must be F);
 * ``blocks`` Multi-path Byte Refinement Blocks (Sec. 3.1.2, Eqs. 9-13):
   X0 = LN(X); X_i = Linear_i(X0), i = 1..k; X_fused = X_1 * ... * X_k;
   X_ff = GeLU(X_fused) (exact erf form); X_out = Linear_out(X_ff) + X;
@@ -25,7 +28,10 @@ Parity pins (tests/test_oracle_model.py): forward against PyTorch's own FP64
 modules (layer_norm, gelu, softmax, linear) on random weights; special cases
 (one-hot FDM, constant-row LayerNorm, zero head); the adjoint against central
 finite differences and against torch.autograd in FP64; Adam against the
-first-step closed form and against torch.optim.Adam.
+first-step closed form and against torch.optim.Adam.  The "w/o LTE" ablation:
+forward and adjoint against the same PyTorch modules, one step against the LTE
+model with identity W1, W2 and zero biases, and its parameter count against
+the difference printed in Table 4.
 """
 
 from __future__ import annotations
@@ -76,6 +82,11 @@ class Config:
     seed: int = 0
     cdf_bits: int = 16
     zero_head: bool = False  # test special case: head weights and bias start at 0
+    lte: bool = True  # False: the "w/o LTE" ablation (Table 4), latent == feat
+
+    def __post_init__(self):
+        if not self.lte and self.latent != self.feat:
+            raise ValueError("without the LTE the FDM is F x F: latent must equal feat")
 
     @property
     def feat(self) -> int:
@@ -93,13 +104,14 @@ class Config:
 def param_specs(cfg: Config):
     """(name, shape, tensor_id or None, bound or constant) in storage order."""
     F, E, L, H = cfg.feat, cfg.embed, cfg.latent, cfg.hidden
-    specs = [
-        ("emb", (V, E), TID_EMB, math.sqrt(3.0)),
-        ("w1", (L, F), TID_W1, 1.0 / math.sqrt(F)),
-        ("b1", (L,), TID_B1, 1.0 / math.sqrt(F)),
-        ("w2", (F, L), TID_W2, 1.0 / math.sqrt(L)),
-        ("b2", (F,), TID_B2, 1.0 / math.sqrt(L)),
-    ]
+    specs = [("emb", (V, E), TID_EMB, math.sqrt(3.0))]
+    if cfg.lte:
+        specs += [
+            ("w1", (L, F), TID_W1, 1.0 / math.sqrt(F)),
+            ("b1", (L,), TID_B1, 1.0 / math.sqrt(F)),
+            ("w2", (F, L), TID_W2, 1.0 / math.sqrt(L)),
+            ("b2", (F,), TID_B2, 1.0 / math.sqrt(L)),
+        ]
     for j in range(cfg.blocks):
         specs.append((f"ln{j}.gamma", (F,), None, 1.0))
         specs.append((f"ln{j}.beta", (F,), None, 0.0))
@@ -192,10 +204,10 @@ class Model:
         n = ctx.shape[0]
         c = {"ctx": ctx, "slots": np.asarray(slots)}
         X = P["emb"][ctx].reshape(n, cfg.feat)                       # embed, oldest first
-        X1 = X @ P["w1"].T + P["b1"]                                 # Eq. 14
+        X1 = X @ P["w1"].T + P["b1"] if cfg.lte else X               # Eq. 14
         Us = self.U[c["slots"]]
         Y = np.matmul(X1[:, None, :], Us)[:, 0, :]                   # Eq. 15
-        H = Y @ P["w2"].T + P["b2"]                                  # Eq. 16
+        H = Y @ P["w2"].T + P["b2"] if cfg.lte else Y                # Eq. 16
         c.update(X=X, X1=X1, Y=Y, H0=H)
         blocks = []
         for j in range(cfg.blocks):
@@ -251,15 +263,20 @@ class Model:
             dln = b["rstd"] * (dxhat - dxhat.mean(1, keepdims=True)
                                - b["xhat"] * (dxhat * b["xhat"]).mean(1, keepdims=True))
             dH = dH + dln                                           # residual path of Eq. 13
-        g["w2"] = dH.T @ c["Y"]
-        g["b2"] = dH.sum(0)
-        dY = dH @ P["w2"]
+        if cfg.lte:
+            g["w2"] = dH.T @ c["Y"]
+            g["b2"] = dH.sum(0)
+            dY = dH @ P["w2"]
+        else:
+            dY = dH
         Us = self.U[c["slots"]]
         dU = c["X1"][:, :, None] * dY[:, None, :]                    # dU_s = x'_s (x) dy_s
         dX1 = np.matmul(Us, dY[:, :, None])[:, :, 0]                  # U_s dy_s
-        g["w1"] = dX1.T @ c["X"]
-        g["b1"] = dX1.sum(0)
-        dX = (dX1 @ P["w1"]).reshape(n, cfg.context, cfg.embed)
+        if cfg.lte:
+            g["w1"] = dX1.T @ c["X"]
+            g["b1"] = dX1.sum(0)
+            dX1 = dX1 @ P["w1"]
+        dX = dX1.reshape(n, cfg.context, cfg.embed)
         dEmb = np.zeros_like(P["emb"])
         np.add.at(dEmb, c["ctx"], dX)
         g["emb"] = dEmb

@@ -118,9 +118,12 @@ def test_lte_shapes_against_paper_table4():
     m = Model(cfg, 1)
     fdm_per_stream = m.U[0].size
     sizes = {name: int(np.prod(shape)) for name, shape, _, _ in param_specs(cfg)}
-    lte_shared = sizes["w1"] + sizes["b1"] + sizes["w2"] + sizes["b2"]
-    # "w/o LTE": a per-instance F x F FDM replaces (W1, b1, per-instance U, W2, b2)
-    delta_no_lte = b * (F * F - fdm_per_stream) - lte_shared
+    # "w/o LTE": the oracle's ablation model, a per-instance F x F FDM in place
+    # of (W1, b1, per-instance U, W2, b2)
+    cfg_n = cfg.with_(latent=F, lte=False)
+    sizes_n = {name: int(np.prod(shape)) for name, shape, _, _ in param_specs(cfg_n)}
+    delta_no_lte = (b * Model(cfg_n, 1).U[0].size + sum(sizes_n.values())
+                    - b * fdm_per_stream - sum(sizes.values()))
     printed = g["params_without_lte"] - g["params_edpc"]
     assert abs(delta_no_lte - printed) / printed < 3e-3
     # "low-rank factorization": W1, U, W2 all per instance

@@ -18,6 +18,8 @@ import torch.nn.functional as Fnn
 from oracle.model import Config, Model, gelu, gelu_grad, layer_norm, softmax
 
 TINY = Config(context=3, embed=4, latent=5, blocks=2, hidden=6, branches=2)
+# the "w/o LTE" ablation of Table 4: F x F FDM, no W1 / W2
+TINY_NO_LTE = Config(context=3, embed=4, latent=12, blocks=2, hidden=6, branches=2, lte=False)
 
 
 def _rand_model(cfg, n_slots, seed=0, scale=0.5):
@@ -36,9 +38,9 @@ def _torch_forward(m: Model, ctx, slots, targets):
     c = torch.tensor(ctx, dtype=torch.long)
     n = c.shape[0]
     X = Fnn.embedding(c, P["emb"]).reshape(n, cfg.feat)
-    X1 = Fnn.linear(X, P["w1"], P["b1"])
+    X1 = Fnn.linear(X, P["w1"], P["b1"]) if cfg.lte else X
     Y = torch.bmm(X1[:, None, :], U[torch.tensor(slots)].contiguous())[:, 0, :]
-    H = Fnn.linear(Y, P["w2"], P["b2"])
+    H = Fnn.linear(Y, P["w2"], P["b2"]) if cfg.lte else Y
     for j in range(cfg.blocks):
         X0 = Fnn.layer_norm(H, (cfg.feat,), P[f"ln{j}.gamma"], P[f"ln{j}.beta"], eps=1e-5)
         Xf = None
@@ -85,6 +87,54 @@ def test_adjoint_matches_torch_autograd(branches):
     np.testing.assert_allclose(dU, full[slots], rtol=1e-9, atol=1e-13)
     others = np.setdiff1d(np.arange(6), slots)
     assert not full[others].any()
+
+
+def test_without_lte_matches_torch_fp64():
+    cfg = TINY_NO_LTE
+    m = _rand_model(cfg, 4, seed=21)
+    assert not any(k in m.p for k in ("w1", "b1", "w2", "b2"))
+    assert m.U.shape == (4, cfg.feat, cfg.feat)
+    r = np.random.default_rng(4)
+    ctx = r.integers(0, 256, size=(5, cfg.context))
+    ctx = ctx[:4]
+    ctx[3] = ctx[1]  # repeated bytes exercise the embedding scatter-add
+    slots, tgt = np.array([3, 0, 2, 1]), r.integers(0, 256, size=4)
+    c = m.forward(ctx, slots)
+    g, dU = m.backward(c, tgt)
+    P, U, p_t, loss_t = _torch_forward(m, ctx, slots, tgt)
+    np.testing.assert_allclose(c["p"], p_t.detach().numpy(), rtol=1e-12, atol=1e-15)
+    loss_t.backward()
+    for k in m.p:
+        np.testing.assert_allclose(g[k], P[k].grad.numpy(), rtol=1e-9, atol=1e-13, err_msg=k)
+    np.testing.assert_allclose(dU, U.grad.numpy()[slots], rtol=1e-9, atol=1e-13)
+
+
+def test_without_lte_is_the_lte_with_identity_maps():
+    # Eqs. 14 and 16 with W1 = W2 = I and zero biases leave the features
+    # unchanged, so the F x F ablation must reproduce that model exactly
+    cfg_n = TINY_NO_LTE
+    cfg_l = cfg_n.with_(lte=True)
+    n = _rand_model(cfg_n, 3, seed=5)
+    lte = Model(cfg_l, 3, shared=dict(n.p, w1=np.eye(cfg_l.feat), b1=np.zeros(cfg_l.feat),
+                                      w2=np.eye(cfg_l.feat), b2=np.zeros(cfg_l.feat)),
+                fdm=n.U)
+    r = np.random.default_rng(6)
+    ctx = r.integers(0, 256, size=(3, cfg_n.context))
+    slots, tgt = np.array([2, 0, 1]), r.integers(0, 256, size=3)
+    # one step: the update moves W1, W2 away from the identity afterwards
+    cn, _, gn, dUn = n.step(ctx, tgt, slots)
+    cl, _, gl, dUl = lte.step(ctx, tgt, slots)
+    np.testing.assert_array_equal(cn["p"], cl["p"])
+    np.testing.assert_array_equal(dUn, dUl)
+    for k in n.p:
+        np.testing.assert_array_equal(gn[k], gl[k], err_msg=k)
+        np.testing.assert_array_equal(n.p[k], lte.p[k], err_msg=k)
+    np.testing.assert_array_equal(n.U, lte.U)
+
+
+def test_without_lte_requires_square_fdm():
+    with pytest.raises(ValueError):
+        TINY_NO_LTE.with_(latent=5)
 
 
 def test_adjoint_matches_central_differences():
