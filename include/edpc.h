@@ -71,6 +71,12 @@ typedef enum { EDPC_FP32 = 0, EDPC_BF16 = 1 } edpc_precision;
                                    the container (so two encodes may pick
                                    different, equally valid, summation orders).
                                    Without it a fixed default is used. */
+#define EDPC_CFG_NO_LTE 0x4u    /* the "w/o LTE" ablation (Table 4): no W1, b1,
+                                   W2, b2; the per-stream FDM U_s is F x F and
+                                   acts on the embedded features directly
+                                   (Eq. 15 with x' = x, Eq. 16 with y = x'').
+                                   latent must equal context * embed.  Runs the
+                                   layer-by-layer step in both precisions. */
 
 typedef struct {
   uint32_t struct_size; /* sizeof(edpc_config) */

@@ -103,6 +103,7 @@ struct Model {
   edpc_config cfg;
   int C, E, F, L, N, H, K;
   bool bf16;
+  bool lte = true;  // false: the F x F FDM ablation (EDPC_CFG_NO_LTE)
   size_t n_slots, max_rows;
   KernelConfig kc;
   std::vector<TensorInfo> tens;

@@ -103,7 +103,10 @@ void Model::validate(const edpc_config& c) {
   if (c.branches < 1 || c.branches > 3) fail(EDPC_E_INVALID_ARG, "branches must be 1..3");
   if (c.cdf_bits != 16) fail(EDPC_E_INVALID_ARG, "only 16-bit CDFs are supported");
   if (c.precision != EDPC_FP32 && c.precision != EDPC_BF16) fail(EDPC_E_INVALID_ARG, "unknown precision");
-  if (c.flags & ~(EDPC_CFG_ZERO_HEAD | EDPC_CFG_AUTOTUNE)) fail(EDPC_E_INVALID_ARG, "unknown config flags");
+  if (c.flags & ~(EDPC_CFG_ZERO_HEAD | EDPC_CFG_AUTOTUNE | EDPC_CFG_NO_LTE))
+    fail(EDPC_E_INVALID_ARG, "unknown config flags");
+  if ((c.flags & EDPC_CFG_NO_LTE) && c.latent != c.context * c.embed)
+    fail(EDPC_E_INVALID_ARG, "without the LTE the FDM is F x F: latent must equal context * embed");
   if ((c.context * c.embed) % 8) fail(EDPC_E_INVALID_ARG, "context * embed must be a multiple of 8");
   if ((uint64_t)c.context * c.embed > 16384) fail(EDPC_E_INVALID_ARG, "context * embed must be <= 16384");
   if (!(c.lr >= 0.f) || !(c.beta1 >= 0.f && c.beta1 < 1.f) || !(c.beta2 >= 0.f && c.beta2 < 1.f) || !(c.eps > 0.f))
@@ -153,6 +156,7 @@ KernelConfig Model::default_config(const edpc_config& c, size_t rows) {
   // row-block kernels index activations with 32-bit offsets.
   const char* env = std::getenv("EDPC_FUSED");
   k.fused = !(env && env[0] == '0') && c.precision == EDPC_BF16 && rows <= (1u << 20) &&
+            !(c.flags & EDPC_CFG_NO_LTE) &&
             fused_supported(F, L, H, (int)c.branches, (int)c.blocks);
   return k;
 }
@@ -182,7 +186,8 @@ Model::Model(const edpc_config& c, size_t nslots, size_t rows, const KernelConfi
   K = c.branches;
   bf16 = c.precision == EDPC_BF16;
   kc = kcfg ? *kcfg : default_config(c, rows);
-  if (kc.fused && !(bf16 && fused_supported(F, L, H, K, N) && rows <= (1u << 20)))
+  lte = !(c.flags & EDPC_CFG_NO_LTE);
+  if (kc.fused && !(bf16 && lte && fused_supported(F, L, H, K, N) && rows <= (1u << 20)))
     fail(EDPC_E_UNSUPPORTED, "fused step requested for an unsupported shape");
 
   // Flat layout of the shared parameters; each tensor starts 64-aligned.
@@ -193,10 +198,12 @@ Model::Model(const edpc_config& c, size_t nslots, size_t rows, const KernelConfi
   const double bF = 1.0 / std::sqrt((double)F), bL = 1.0 / std::sqrt((double)L),
                bH = 1.0 / std::sqrt((double)H);
   add("emb", 256 * (size_t)E, 1, std::sqrt(3.0));
-  add("w1", (size_t)L * F, 2, bF);
-  add("b1", L, 3, bF);
-  add("w2", (size_t)F * L, 5, bL);
-  add("b2", F, 6, bL);
+  if (lte) {
+    add("w1", (size_t)L * F, 2, bF);
+    add("b1", L, 3, bF);
+    add("w2", (size_t)F * L, 5, bL);
+    add("b2", F, 6, bL);
+  }
   for (int j = 0; j < N; ++j) {
     add("ln" + std::to_string(j) + ".gamma", F, 0, 1.0);
     add("ln" + std::to_string(j) + ".beta", F, 0, 0.0);
@@ -237,10 +244,17 @@ Model::Model(const edpc_config& c, size_t nslots, size_t rows, const KernelConfi
   ctx = dalloc<uint8_t>(R * C);
   tgt = dalloc<uint8_t>(R);
   slot = dalloc<uint32_t>(R);
-  if (bf16) X16 = dalloc<bf16_t>(R * F); else X32 = dalloc<float>(R * F);
-  X1 = dalloc<float>(R * L);
-  if (bf16) Y16 = dalloc<bf16_t>(R * L); else Y32 = dalloc<float>(R * L);
+  // without the LTE the FDM reads the FP32 embedding (x' = x) and writes the
+  // first block's input (x'' = y) directly
+  if (bf16 && lte) X16 = dalloc<bf16_t>(R * F);
+  if (!bf16 || !lte) X32 = dalloc<float>(R * F);
+  X1 = lte ? dalloc<float>(R * L) : X32;
   for (int j = 0; j <= N; ++j) Hs.push_back(dalloc<float>(R * F));
+  if (lte) {
+    if (bf16) Y16 = dalloc<bf16_t>(R * L); else Y32 = dalloc<float>(R * L);
+  } else {
+    Y32 = Hs[0];
+  }
   if (bf16) HN16 = dalloc<bf16_t>(R * F);
   for (int j = 0; j < N; ++j) {
     if (bf16) Z16.push_back(dalloc<bf16_t>(R * F)); else Z32.push_back(dalloc<float>(R * F));
@@ -261,10 +275,15 @@ Model::Model(const edpc_config& c, size_t nslots, size_t rows, const KernelConfi
   if (bf16) dz16 = dalloc<bf16_t>(R * 256);
   loss_rows = dalloc<float>(R);
   loss_out = dalloc<float>(1);
-  dY = dalloc<float>(R * L);
-  dX1_32 = dalloc<float>(R * L);
-  if (bf16) dX1_16 = dalloc<bf16_t>(R * L);
   dX = dalloc<float>(R * F);
+  if (lte) {
+    dY = dalloc<float>(R * L);
+    dX1_32 = dalloc<float>(R * L);
+    if (bf16) dX1_16 = dalloc<bf16_t>(R * L);
+  } else {  // dy = dx'' and dx = dx'
+    dY = dH32[0];
+    dX1_32 = dX;
+  }
   emb_grad_plan((int)R, C, E, &emb_chunk, &emb_sub);
   emb_partial = dalloc<float>(((R + emb_chunk - 1) / emb_chunk) * 256 * (size_t)E);
 }
@@ -331,10 +350,12 @@ void Model::build_tables(hipStream_t s) {
       addw(bf16 ? (const void*)dA16[j] : (const void*)dA32[j],
            bf16 ? (const void*)Z16[j] : (const void*)Z32[j], G_(b + ".w0"), K * H, F);
     }
-    addw(bf16 ? (const void*)dH16[0] : (const void*)dH32[0],
-         bf16 ? (const void*)Y16 : (const void*)Y32, G_("w2"), F, L);
-    addw(bf16 ? (const void*)dX1_16 : (const void*)dX1_32,
-         bf16 ? (const void*)X16 : (const void*)X32, G_("w1"), L, F);
+    if (lte) {
+      addw(bf16 ? (const void*)dH16[0] : (const void*)dH32[0],
+           bf16 ? (const void*)Y16 : (const void*)Y32, G_("w2"), F, L);
+      addw(bf16 ? (const void*)dX1_16 : (const void*)dX1_32,
+           bf16 ? (const void*)X16 : (const void*)X32, G_("w1"), L, F);
+    }
     WgTable& t = wg_tab[tile];
     t.n = (int)wg.size();
     t.tiles = tiles;
@@ -370,8 +391,10 @@ void Model::build_tables(hipStream_t s) {
     addc(dZ[j], F, F, G_("ln" + std::to_string(j) + ".beta"), nullptr, nullptr, nullptr);
     addc(dZ[j], F, F, G_("ln" + std::to_string(j) + ".gamma"), Hs[j], mean[j], rstd[j]);
   }
-  addc(dH32[0], F, F, G_("b2"), nullptr, nullptr, nullptr);
-  addc(dX1_32, L, L, G_("b1"), nullptr, nullptr, nullptr);
+  if (lte) {
+    addc(dH32[0], F, F, G_("b2"), nullptr, nullptr, nullptr);
+    addc(dX1_32, L, L, G_("b1"), nullptr, nullptr, nullptr);
+  }
   n_cs = (int)cs.size();
   d_cs = dalloc<ColsumJob>(cs.size());
   cs_partial = dalloc<float>(colsum_partial_elems((int)max_rows, cs_cols));
@@ -726,9 +749,9 @@ void Model::step(StepMode mode, const StreamIO& io, const StepOutputs& out, int 
     return;
   }
   TIMED(KC_EMBED, k_embed(st, ctx, P_("emb"), C, E, X32, X16, R, s));
-  product(PS_LTE_DOWN, 0, R, s);
+  if (lte) product(PS_LTE_DOWN, 0, R, s);
   TIMED(KC_FDM_FWD, k_fdm_fwd(st, X1, U, slot, L, Y32, Y16, R, s));  // Eq. 15
-  product(PS_LTE_UP, 0, R, s);
+  if (lte) product(PS_LTE_UP, 0, R, s);
   for (int j = 0; j < N; ++j) {
     const std::string ln = "ln" + std::to_string(j);
     TIMED(KC_LN_FWD, k_ln_fwd(st, Hs[j], P_(ln + ".gamma"), P_(ln + ".beta"), F,
@@ -754,11 +777,11 @@ void Model::step(StepMode mode, const StreamIO& io, const StepOutputs& out, int 
     TIMED(KC_LN_BWD, k_ln_bwd(st, Hs[j], mean[j], rstd[j], P_(ln + ".gamma"), dZ[j],
                               dH32[j + 1], F, dH32[j], bf16 ? dH16[j] : nullptr, R, s));
   }
-  product(PS_LTE_UP_BWD, 0, R, s);
+  if (lte) product(PS_LTE_UP_BWD, 0, R, s);
   // adjoint of Eq. 15, fused with Adam on U_s
   TIMED(KC_FDM_BWD, k_fdm_bwd(st, X1, dY, U, mU, vU, out.keep_fdm_grad ? dUkeep : nullptr, slot,
                               L, ac, out.update, dX1_32, dX1_16, R, s));
-  product(PS_LTE_DOWN_BWD, 0, R, s);
+  if (lte) product(PS_LTE_DOWN_BWD, 0, R, s);
   TIMED(KC_EMB_GRAD, k_emb_grad(st, ctx, dX, C, E, emb_partial, emb_chunk, emb_sub, R, G_("emb"), s));
   product(PS_WGRAD, 0, R, s);
   TIMED(KC_COLSUM, k_colsum(st, d_cs, n_cs, cs_blocks, cs_cols, cs_partial, R, s));
@@ -780,6 +803,9 @@ void Model::autotune(hipStream_t s) {
   for (int ps = 0; ps < PS_COUNT; ++ps) {
     const bool per_block = ps == PS_GATE || ps == PS_OUT || ps == PS_GATE_BWD || ps == PS_DZ;
     if (per_block && N == 0) continue;
+    const bool lte_ps = ps == PS_LTE_DOWN || ps == PS_LTE_UP || ps == PS_LTE_UP_BWD ||
+                        ps == PS_LTE_DOWN_BWD;
+    if (lte_ps && !lte) continue;
     int best = kc.tile[ps];
     float best_ms = 1e30f;
     for (int t = 0; t < TILE_COUNT; ++t) {

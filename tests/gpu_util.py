@@ -22,7 +22,7 @@ def lib_cfg(E, model: dict, precision: str = "fp32", **over):
     kw = {k: d[k] for k in ("context", "embed", "latent", "blocks", "hidden", "branches", "lr",
                             "beta1", "beta2", "eps", "seed") if k in d}
     return E.edpc_config_default(precision=precision, zero_head=d.get("zero_head", False),
-                                 autotune=d.get("autotune", False), **kw)
+                                 autotune=d.get("autotune", False), lte=d.get("lte", True), **kw)
 
 
 def oracle_cfg(model: dict, **over) -> Config:

@@ -443,3 +443,37 @@ def test_branch_count_variants(E, branches, precision):
     cont = _encode(E, lib_cfg(E, model, precision), data, lens)
     out, _ = E.edpc_decode(cont)
     assert out.cpu().numpy().tobytes() == data.tobytes()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_without_lte_variant(E, precision):
+    # the "w/o LTE" ablation of Table 4: a per-stream F x F FDM on the embedded
+    # features (F = 256), no W1 / W2; BF16 runs the layer-by-layer products
+    model = dict(SMALL, latent=256, lte=False)
+    C = model["context"]
+    m0 = E.Model(lib_cfg(E, model, precision), 3, 3)
+    for k, v in init_shared(oracle_cfg(model)).items():
+        assert np.array_equal(m0.edpc_model_read(k), v.reshape(-1)), k
+    assert np.array_equal(m0.edpc_model_read("U"), init_fdm(oracle_cfg(model), range(3)).reshape(-1))
+    del m0
+    om, m, ctx, tgt = _step_case(E, model, precision, rows=8, pos=C + 8, om_steps=8, prefix=C + 9)
+    assert om.U.shape[1:] == (256, 256)
+    if precision == "fp32":
+        _, g_o, dU_o = _compare_step(E, om, m, ctx, tgt, p_tol=1e-5, g_rtol=1e-4)
+        _compare_update(E, om, m, ctx, tgt, g_o, dU_o, tol=1e-6)
+    else:
+        _compare_step(E, om, m, ctx, tgt, p_tol=2e-3, g_rtol=3e-2)
+    del m
+    data, lens = gen.make_streams("small", prefix=200, n_streams=4)
+    cont = _encode(E, lib_cfg(E, model, precision), data, lens)
+    out, _ = E.edpc_decode(cont)
+    assert out.cpu().numpy().tobytes() == data.tobytes()
+    _, pays = parse_container(cont.cpu().numpy().tobytes())
+    pay_o, _ = oracle.encode(split_streams(data, lens), oracle_cfg(model))
+    for p, po in zip(pays, pay_o):
+        assert abs(len(p) - len(po)) <= 2
+
+
+def test_without_lte_rejects_non_square_fdm(E):
+    with pytest.raises(Exception):
+        E.edpc_config_validate(lib_cfg(E, dict(SMALL, lte=False)))
