@@ -12,6 +12,14 @@ Test infrastructure only.  Follows the paper's equations in their order:
 * the "w/o LTE" ablation (Table 4, Sec. 4.4.1), ``lte=False``: no W1, b1, W2,
   b2; the per-instance FDM acts on the F-wide features directly, Y = bmm(X, U)
   with U of shape [b, F, F], and Y feeds the first block (latent must be F);
+* the "low-rank factorization" ablation (Table 4), ``low_rank=True``: the
+  per-instance F x F matrix of "w/o LTE" is replaced by three per-instance
+  factors, X' = X A_s (A_s: [F, F']), Y = X' U_s, X'' = Y B_s (B_s: [F', F]),
+  with no shared W1, b1, W2, b2 and no biases; A_s and B_s are updated only on
+  steps where their stream is in the batch, like U_s.  Reading: the shared LTE
+  is made per instance and loses its biases, which the parameter count of
+  Table 4 fixes (4096 * (2 * 256 * 64 + 64 * 64) more than the shared part,
+  with per-instance biases it would be 1.3e6 more);
 * ``blocks`` Multi-path Byte Refinement Blocks (Sec. 3.1.2, Eqs. 9-13):
   X0 = LN(X); X_i = Linear_i(X0), i = 1..k; X_fused = X_1 * ... * X_k;
   X_ff = GeLU(X_fused) (exact erf form); X_out = Linear_out(X_ff) + X;
@@ -31,7 +39,9 @@ finite differences and against torch.autograd in FP64; Adam against the
 first-step closed form and against torch.optim.Adam.  The "w/o LTE" ablation:
 forward and adjoint against the same PyTorch modules, one step against the LTE
 model with identity W1, W2 and zero biases, and its parameter count against
-the difference printed in Table 4.
+the difference printed in Table 4.  The low-rank ablation: forward and
+adjoint against torch.autograd in FP64, one step against the "w/o LTE" model
+with identity factors (latent = F), and its parameter count against Table 4.
 """
 
 from __future__ import annotations
@@ -49,6 +59,7 @@ V = 256  # alphabet size
 
 # Tensor ids used by the counter-based initialiser.
 TID_EMB, TID_W1, TID_B1, TID_U, TID_W2, TID_B2, TID_WH, TID_BH = 1, 2, 3, 4, 5, 6, 7, 8
+TID_LR_A, TID_LR_B = 9, 10  # per-instance factors of the low-rank ablation
 
 
 def tid_branch_w(j, i):
@@ -83,10 +94,13 @@ class Config:
     cdf_bits: int = 16
     zero_head: bool = False  # test special case: head weights and bias start at 0
     lte: bool = True  # False: the "w/o LTE" ablation (Table 4), latent == feat
+    low_rank: bool = False  # True: the "low-rank factorization" ablation (Table 4)
 
     def __post_init__(self):
         if not self.lte and self.latent != self.feat:
             raise ValueError("without the LTE the FDM is F x F: latent must equal feat")
+        if self.low_rank and not self.lte:
+            raise ValueError("the low-rank ablation factorises the LTE: lte must be set")
 
     @property
     def feat(self) -> int:
@@ -105,7 +119,7 @@ def param_specs(cfg: Config):
     """(name, shape, tensor_id or None, bound or constant) in storage order."""
     F, E, L, H = cfg.feat, cfg.embed, cfg.latent, cfg.hidden
     specs = [("emb", (V, E), TID_EMB, math.sqrt(3.0))]
-    if cfg.lte:
+    if cfg.lte and not cfg.low_rank:
         specs += [
             ("w1", (L, F), TID_W1, 1.0 / math.sqrt(F)),
             ("b1", (L,), TID_B1, 1.0 / math.sqrt(F)),
@@ -144,6 +158,19 @@ def init_fdm(cfg: Config, slots) -> np.ndarray:
     for r, s in enumerate(slots):
         out[r] = rng.init_tensor(cfg.seed, TID_U, (L, L), bound, start=int(s) * L * L)
     return out
+
+
+def init_low_rank(cfg: Config, slots):
+    """FP32 per-instance factors (A_s [F, L], U(+-1/sqrt(F)); B_s [L, F],
+    U(+-1/sqrt(L))) of the low-rank ablation, slot s drawing the counter range
+    that starts at s times the factor's size (the layout of U)."""
+    F, L = cfg.feat, cfg.latent
+    A = np.empty((len(slots), F, L), dtype=np.float32)
+    B = np.empty((len(slots), L, F), dtype=np.float32)
+    for r, s in enumerate(slots):
+        A[r] = rng.init_tensor(cfg.seed, TID_LR_A, (F, L), 1.0 / math.sqrt(F), start=int(s) * F * L)
+        B[r] = rng.init_tensor(cfg.seed, TID_LR_B, (L, F), 1.0 / math.sqrt(L), start=int(s) * L * F)
+    return A, B
 
 
 # --------------------------------------------------------------------------
@@ -196,6 +223,12 @@ class Model:
         self.v = {k: np.zeros_like(v) for k, v in self.p.items()}
         self.mU = np.zeros_like(self.U)
         self.vU = np.zeros_like(self.U)
+        if cfg.low_rank:
+            A, B = init_low_rank(cfg, range(n_slots))
+            self.A = np.asarray(A, dtype=np.float64)
+            self.B = np.asarray(B, dtype=np.float64)
+            self.mA, self.vA = np.zeros_like(self.A), np.zeros_like(self.A)
+            self.mB, self.vB = np.zeros_like(self.B), np.zeros_like(self.B)
         self.tau = 0
 
     # ---- forward: Eq. 1 via Eqs. 14-16 and 9-13 ------------------------
@@ -204,10 +237,16 @@ class Model:
         n = ctx.shape[0]
         c = {"ctx": ctx, "slots": np.asarray(slots)}
         X = P["emb"][ctx].reshape(n, cfg.feat)                       # embed, oldest first
-        X1 = X @ P["w1"].T + P["b1"] if cfg.lte else X               # Eq. 14
+        if cfg.low_rank:
+            X1 = np.matmul(X[:, None, :], self.A[c["slots"]])[:, 0, :]   # X A_s
+        else:
+            X1 = X @ P["w1"].T + P["b1"] if cfg.lte else X           # Eq. 14
         Us = self.U[c["slots"]]
         Y = np.matmul(X1[:, None, :], Us)[:, 0, :]                   # Eq. 15
-        H = Y @ P["w2"].T + P["b2"] if cfg.lte else Y                # Eq. 16
+        if cfg.low_rank:
+            H = np.matmul(Y[:, None, :], self.B[c["slots"]])[:, 0, :]    # Y B_s
+        else:
+            H = Y @ P["w2"].T + P["b2"] if cfg.lte else Y            # Eq. 16
         c.update(X=X, X1=X1, Y=Y, H0=H)
         blocks = []
         for j in range(cfg.blocks):
@@ -263,7 +302,10 @@ class Model:
             dln = b["rstd"] * (dxhat - dxhat.mean(1, keepdims=True)
                                - b["xhat"] * (dxhat * b["xhat"]).mean(1, keepdims=True))
             dH = dH + dln                                           # residual path of Eq. 13
-        if cfg.lte:
+        if cfg.low_rank:
+            g["B"] = c["Y"][:, :, None] * dH[:, None, :]            # dB_s = y_s (x) dx''_s
+            dY = np.matmul(self.B[c["slots"]], dH[:, :, None])[:, :, 0]
+        elif cfg.lte:
             g["w2"] = dH.T @ c["Y"]
             g["b2"] = dH.sum(0)
             dY = dH @ P["w2"]
@@ -272,7 +314,10 @@ class Model:
         Us = self.U[c["slots"]]
         dU = c["X1"][:, :, None] * dY[:, None, :]                    # dU_s = x'_s (x) dy_s
         dX1 = np.matmul(Us, dY[:, :, None])[:, :, 0]                  # U_s dy_s
-        if cfg.lte:
+        if cfg.low_rank:
+            g["A"] = c["X"][:, :, None] * dX1[:, None, :]           # dA_s = x_s (x) dx'_s
+            dX1 = np.matmul(self.A[c["slots"]], dX1[:, :, None])[:, :, 0]
+        elif cfg.lte:
             g["w1"] = dX1.T @ c["X"]
             g["b1"] = dX1.sum(0)
             dX1 = dX1 @ P["w1"]
@@ -303,6 +348,13 @@ class Model:
         Us, mU, vU = self.U[slots], self.mU[slots], self.vU[slots]
         upd(Us, mU, vU, dU)
         self.U[slots], self.mU[slots], self.vU[slots] = Us, mU, vU
+        if cfg.low_rank:
+            for name, key in (("A", "A"), ("B", "B")):
+                th, m, v = (getattr(self, n)[slots] for n in (name, "m" + name, "v" + name))
+                upd(th, m, v, g[key])
+                getattr(self, name)[slots] = th
+                getattr(self, "m" + name)[slots] = m
+                getattr(self, "v" + name)[slots] = v
 
     def step(self, ctx, target, slots, update: bool = True):
         """forward -> loss -> adjoint -> (Adam); returns (cache, loss, grads, dU)."""
@@ -322,6 +374,11 @@ class Model:
         out["param.U"] = self.U.astype(np.float32)
         out["m.U"] = self.mU.astype(np.float32)
         out["v.U"] = self.vU.astype(np.float32)
+        if self.cfg.low_rank:
+            for n in ("A", "B"):
+                out[f"param.{n}"] = getattr(self, n).astype(np.float32)
+                out[f"m.{n}"] = getattr(self, "m" + n).astype(np.float32)
+                out[f"v.{n}"] = getattr(self, "v" + n).astype(np.float32)
         return out
 
     def round_to_f32(self):
@@ -329,7 +386,10 @@ class Model:
         for d in (self.p, self.m, self.v):
             for k in d:
                 d[k] = d[k].astype(np.float32).astype(np.float64)
-        for name in ("U", "mU", "vU"):
+        names = ["U", "mU", "vU"]
+        if self.cfg.low_rank:
+            names += ["A", "mA", "vA", "B", "mB", "vB"]
+        for name in names:
             setattr(self, name, getattr(self, name).astype(np.float32).astype(np.float64))
 
     def n_shared_params(self) -> int:

@@ -20,6 +20,9 @@ from oracle.model import Config, Model, gelu, gelu_grad, layer_norm, softmax
 TINY = Config(context=3, embed=4, latent=5, blocks=2, hidden=6, branches=2)
 # the "w/o LTE" ablation of Table 4: F x F FDM, no W1 / W2
 TINY_NO_LTE = Config(context=3, embed=4, latent=12, blocks=2, hidden=6, branches=2, lte=False)
+# the "low-rank factorization" ablation of Table 4: per-instance A_s, U_s, B_s
+TINY_LOW_RANK = Config(context=3, embed=4, latent=5, blocks=2, hidden=6, branches=2,
+                       low_rank=True)
 
 
 def _rand_model(cfg, n_slots, seed=0, scale=0.5):
@@ -28,6 +31,9 @@ def _rand_model(cfg, n_slots, seed=0, scale=0.5):
     for k in m.p:
         m.p[k] = m.p[k] + scale * r.standard_normal(m.p[k].shape) * 0.3
     m.U = m.U + 0.3 * r.standard_normal(m.U.shape)
+    if cfg.low_rank:
+        m.A = m.A + 0.3 * r.standard_normal(m.A.shape)
+        m.B = m.B + 0.3 * r.standard_normal(m.B.shape)
     return m
 
 
@@ -37,10 +43,19 @@ def _torch_forward(m: Model, ctx, slots, targets):
     U = torch.tensor(m.U, dtype=torch.float64, requires_grad=True)
     c = torch.tensor(ctx, dtype=torch.long)
     n = c.shape[0]
+    sl = torch.tensor(slots)
     X = Fnn.embedding(c, P["emb"]).reshape(n, cfg.feat)
-    X1 = Fnn.linear(X, P["w1"], P["b1"]) if cfg.lte else X
-    Y = torch.bmm(X1[:, None, :], U[torch.tensor(slots)].contiguous())[:, 0, :]
-    H = Fnn.linear(Y, P["w2"], P["b2"]) if cfg.lte else Y
+    if cfg.low_rank:
+        P["A"] = torch.tensor(m.A, dtype=torch.float64, requires_grad=True)
+        P["B"] = torch.tensor(m.B, dtype=torch.float64, requires_grad=True)
+        X1 = torch.bmm(X[:, None, :], P["A"][sl].contiguous())[:, 0, :]
+    else:
+        X1 = Fnn.linear(X, P["w1"], P["b1"]) if cfg.lte else X
+    Y = torch.bmm(X1[:, None, :], U[sl].contiguous())[:, 0, :]
+    if cfg.low_rank:
+        H = torch.bmm(Y[:, None, :], P["B"][sl].contiguous())[:, 0, :]
+    else:
+        H = Fnn.linear(Y, P["w2"], P["b2"]) if cfg.lte else Y
     for j in range(cfg.blocks):
         X0 = Fnn.layer_norm(H, (cfg.feat,), P[f"ln{j}.gamma"], P[f"ln{j}.beta"], eps=1e-5)
         Xf = None
@@ -130,6 +145,57 @@ def test_without_lte_is_the_lte_with_identity_maps():
         np.testing.assert_array_equal(gn[k], gl[k], err_msg=k)
         np.testing.assert_array_equal(n.p[k], lte.p[k], err_msg=k)
     np.testing.assert_array_equal(n.U, lte.U)
+
+
+def test_low_rank_matches_torch_fp64():
+    cfg = TINY_LOW_RANK
+    m = _rand_model(cfg, 5, seed=31)
+    assert not any(k in m.p for k in ("w1", "b1", "w2", "b2"))
+    assert m.A.shape == (5, cfg.feat, cfg.latent) and m.B.shape == (5, cfg.latent, cfg.feat)
+    r = np.random.default_rng(8)
+    ctx = r.integers(0, 256, size=(4, cfg.context))
+    ctx[2] = ctx[0]
+    slots, tgt = np.array([4, 1, 0, 2]), r.integers(0, 256, size=4)
+    c = m.forward(ctx, slots)
+    g, dU = m.backward(c, tgt)
+    P, U, p_t, loss_t = _torch_forward(m, ctx, slots, tgt)
+    np.testing.assert_allclose(c["p"], p_t.detach().numpy(), rtol=1e-12, atol=1e-15)
+    loss_t.backward()
+    for k in m.p:
+        np.testing.assert_allclose(g[k], P[k].grad.numpy(), rtol=1e-9, atol=1e-13, err_msg=k)
+    np.testing.assert_allclose(dU, U.grad.numpy()[slots], rtol=1e-9, atol=1e-13)
+    for k in ("A", "B"):
+        full = P[k].grad.numpy()
+        np.testing.assert_allclose(g[k], full[slots], rtol=1e-9, atol=1e-13, err_msg=k)
+        assert not full[3].any()  # slot 3 is not in the batch
+
+
+def test_low_rank_with_identity_factors_is_without_lte():
+    # with latent = F and A_s = B_s = I the three factors collapse to the
+    # per-instance F x F matrix U_s of the "w/o LTE" ablation; the Adam step
+    # on A_s, B_s must leave U_s's trajectory unchanged in the first step
+    cfg_n = TINY_NO_LTE
+    cfg_r = cfg_n.with_(lte=True, low_rank=True)
+    n = _rand_model(cfg_n, 3, seed=9)
+    lr = Model(cfg_r, 3, shared=dict(n.p), fdm=n.U)
+    eye = np.broadcast_to(np.eye(cfg_n.feat), (3, cfg_n.feat, cfg_n.feat))
+    lr.A, lr.B = eye.copy(), eye.copy()
+    r = np.random.default_rng(12)
+    ctx = r.integers(0, 256, size=(3, cfg_n.context))
+    slots, tgt = np.array([1, 2, 0]), r.integers(0, 256, size=3)
+    cn, ln_, gn, dUn = n.step(ctx, tgt, slots)
+    cr, lr_, gr, dUr = lr.step(ctx, tgt, slots)
+    np.testing.assert_array_equal(cn["p"], cr["p"])
+    assert ln_ == lr_
+    np.testing.assert_array_equal(dUn, dUr)
+    for k in n.p:
+        np.testing.assert_array_equal(n.p[k], lr.p[k], err_msg=k)
+    np.testing.assert_array_equal(n.U, lr.U)
+
+
+def test_low_rank_requires_lte():
+    with pytest.raises(ValueError):
+        TINY_LOW_RANK.with_(lte=False)
 
 
 def test_without_lte_requires_square_fdm():
