@@ -77,6 +77,16 @@ typedef enum { EDPC_FP32 = 0, EDPC_BF16 = 1 } edpc_precision;
                                    (Eq. 15 with x' = x, Eq. 16 with y = x'').
                                    latent must equal context * embed.  Runs the
                                    layer-by-layer step in both precisions. */
+#define EDPC_CFG_LOW_RANK 0x8u  /* the "low-rank factorization" ablation
+                                   (Table 4): no shared W1, b1, W2, b2; each
+                                   stream owns three factors, x' = x A_s
+                                   (A_s [F, latent]), Eq. 15 y = x' U_s, and
+                                   x'' = y B_s (B_s [latent, F]), without biases,
+                                   all three updated by Adam on the steps their
+                                   stream is active.  context * embed must be a
+                                   power of two <= 256; excludes
+                                   EDPC_CFG_NO_LTE.  Runs the layer-by-layer
+                                   step in both precisions. */
 
 typedef struct {
   uint32_t struct_size; /* sizeof(edpc_config) */
@@ -195,7 +205,9 @@ edpc_status edpc_model_step(edpc_model* m, const uint8_t* d_ctx,
                             float* d_loss, uint32_t flags, void* stream);
 
 /* Tensor access (synchronous).  Tensors are numbered 0..count-1 in storage
- * order; the last one is the FDM "U" with n_slots*latent*latent entries. */
+ * order: the shared parameters, then the FDM "U" with n_slots*latent*latent
+ * entries; under EDPC_CFG_LOW_RANK two more follow, "A" and "B", each with
+ * n_slots*F*latent entries (no kept gradient: EDPC_KIND_GRAD on them fails). */
 #define EDPC_KIND_PARAM 0u
 #define EDPC_KIND_GRAD 1u
 #define EDPC_KIND_ADAM_M 2u

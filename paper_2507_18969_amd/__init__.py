@@ -25,6 +25,7 @@ EDPC_FP32, EDPC_BF16 = 0, 1
 EDPC_CFG_ZERO_HEAD = 0x1
 EDPC_CFG_AUTOTUNE = 0x2
 EDPC_CFG_NO_LTE = 0x4
+EDPC_CFG_LOW_RANK = 0x8
 EDPC_STEP_BACKWARD, EDPC_STEP_UPDATE, EDPC_STEP_KEEP_FDM_GRAD = 0x1, 0x2, 0x4
 EDPC_KIND_PARAM, EDPC_KIND_GRAD, EDPC_KIND_ADAM_M, EDPC_KIND_ADAM_V = 0, 1, 2, 3
 KCLASS_COUNT = 24
@@ -147,9 +148,9 @@ def edpc_config_default(**overrides) -> edpc_config:
     for k, v in overrides.items():
         if k == "precision" and isinstance(v, str):
             v = {"fp32": EDPC_FP32, "bf16": EDPC_BF16}[v]
-        if k in ("zero_head", "autotune", "lte"):
+        if k in ("zero_head", "autotune", "lte", "low_rank"):
             bit = {"zero_head": EDPC_CFG_ZERO_HEAD, "autotune": EDPC_CFG_AUTOTUNE,
-                   "lte": EDPC_CFG_NO_LTE}[k]
+                   "lte": EDPC_CFG_NO_LTE, "low_rank": EDPC_CFG_LOW_RANK}[k]
             on = (not v) if k == "lte" else v
             c.flags = (c.flags | bit) if on else (c.flags & ~bit)
             continue

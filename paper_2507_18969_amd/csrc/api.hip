@@ -312,7 +312,7 @@ edpc_status edpc_model_step(edpc_model* mh, const uint8_t* d_ctx, const uint8_t*
 
 edpc_status edpc_model_tensor_count(const edpc_model* mh, size_t* n) {
   if (!mh || !n) return set_err(EDPC_E_INVALID_ARG, "NULL argument");
-  *n = mh->m->tens.size() + 1;
+  *n = mh->m->tens.size() + (mh->m->low_rank ? 3 : 1);
   return EDPC_OK;
 }
 
@@ -328,6 +328,9 @@ edpc_status edpc_model_tensor_info(const edpc_model* mh, size_t idx, char* name,
   } else if (idx == m.tens.size()) {
     nm = "U";
     ne = m.n_slots * (size_t)m.L * m.L;
+  } else if (m.low_rank && idx <= m.tens.size() + 2) {
+    nm = idx == m.tens.size() + 1 ? "A" : "B";
+    ne = m.n_slots * (size_t)m.F * m.L;
   } else {
     return set_err(EDPC_E_INVALID_ARG, "tensor index out of range");
   }
@@ -358,6 +361,15 @@ static float* tensor_ptr(Model& m, uint32_t kind, size_t idx, size_t* numel, boo
       if (for_write) fail(EDPC_E_INVALID_ARG, "the FDM gradient is read-only");
       return m.dUkeep;
     }
+    fail(EDPC_E_INVALID_ARG, "unknown tensor kind");
+  }
+  if (m.low_rank && idx <= m.tens.size() + 2) {
+    const bool a = idx == m.tens.size() + 1;
+    *numel = m.n_slots * (size_t)m.F * m.L;
+    if (kind == EDPC_KIND_PARAM) return a ? m.A : m.B;
+    if (kind == EDPC_KIND_ADAM_M) return a ? m.mA : m.mB;
+    if (kind == EDPC_KIND_ADAM_V) return a ? m.vA : m.vB;
+    if (kind == EDPC_KIND_GRAD) fail(EDPC_E_INVALID_ARG, "the low-rank factor gradients are not kept");
     fail(EDPC_E_INVALID_ARG, "unknown tensor kind");
   }
   fail(EDPC_E_INVALID_ARG, "tensor index out of range");

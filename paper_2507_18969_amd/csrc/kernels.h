@@ -51,11 +51,12 @@ void k_gather(const StepState* st, StreamIO io, int C, uint8_t* ctx, uint8_t* tg
               bool decoding, hipStream_t s);
 void k_embed(const StepState* st, const uint8_t* ctx, const float* emb, int C, int E, float* x32,
              bf16_t* x16, int max_rows, hipStream_t s);
-void k_fdm_fwd(const StepState* st, const float* x1, const float* U, const uint32_t* slot, int L,
-               float* y32, bf16_t* y16, int max_rows, hipStream_t s);
+// Per-stream [Lin, Lout] matrix: Lin <= 256, Lout a power of two in 4..256.
+void k_fdm_fwd(const StepState* st, const float* x1, const float* U, const uint32_t* slot, int Lin,
+               int Lout, float* y32, bf16_t* y16, int max_rows, hipStream_t s);
 void k_fdm_bwd(const StepState* st, const float* x1, const float* dy, float* U, float* mU,
-               float* vU, float* dU_keep, const uint32_t* slot, int L, AdamCfg ac, bool update,
-               float* dx1_32, bf16_t* dx1_16, int max_rows, hipStream_t s);
+               float* vU, float* dU_keep, const uint32_t* slot, int Lin, int Lout, AdamCfg ac,
+               bool update, float* dx1_32, bf16_t* dx1_16, int max_rows, hipStream_t s);
 void k_ln_fwd(const StepState* st, const float* h, const float* gamma, const float* beta, int F,
               float* z32, bf16_t* z16, float* mean, float* rstd, int max_rows, hipStream_t s);
 void k_ln_bwd(const StepState* st, const float* h, const float* mean, const float* rstd,

@@ -138,31 +138,33 @@ constexpr int kFdmBatch = 4;
 
 // ---------------------------------------------------------------------------
 // Feature Distribution Matrix (Eq. 15): y_s = x'_s U_s, one workgroup per row.
+// U_s is [Lin, Lout] (square for the FDM itself; the low-rank ablation's
+// per-stream factors A_s [F, F'] and B_s [F', F] use the same kernels).
 // Thread (g, t): t covers columns 4t..4t+3, group g rows l = g, g+G, ...
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) fdm_fwd_kernel(const StepState* __restrict__ st,
                                                       const float* __restrict__ x1,
                                                       const float* __restrict__ U,
-                                                      const uint32_t* __restrict__ slot, int L,
-                                                      float* __restrict__ y32,
+                                                      const uint32_t* __restrict__ slot, int Lin,
+                                                      int Lout, float* __restrict__ y32,
                                                       bf16_t* __restrict__ y16) {
   const int r = blockIdx.x;
   if (r >= st->rows) return;
   __shared__ float xs[256];
   __shared__ float part[1024];
-  const int tpr = L >> 2, G = 256 / tpr;
+  const int tpr = Lout >> 2, G = 256 / tpr;
   const int t = threadIdx.x % tpr, g = threadIdx.x / tpr;
-  for (int l = threadIdx.x; l < L; l += 256) xs[l] = x1[(size_t)r * L + l];
+  for (int l = threadIdx.x; l < Lin; l += 256) xs[l] = x1[(size_t)r * Lin + l];
   __syncthreads();
-  const float* Us = U + (size_t)slot[r] * L * L;
+  const float* Us = U + (size_t)slot[r] * Lin * Lout;
   float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
   if (g < G) {
     // rows l = g, g + G, ... in order; loads issued kFdmBatch rows at a time
     int l = g;
-    for (; l + (kFdmBatch - 1) * G < L; l += kFdmBatch * G) {
+    for (; l + (kFdmBatch - 1) * G < Lin; l += kFdmBatch * G) {
       float4 u[kFdmBatch];
 #pragma unroll
-      for (int q = 0; q < kFdmBatch; ++q) u[q] = *(const float4*)(Us + (size_t)(l + q * G) * L + 4 * t);
+      for (int q = 0; q < kFdmBatch; ++q) u[q] = *(const float4*)(Us + (size_t)(l + q * G) * Lout + 4 * t);
 #pragma unroll
       for (int q = 0; q < kFdmBatch; ++q) {
         const float xv = xs[l + q * G];
@@ -172,28 +174,29 @@ __global__ void __launch_bounds__(256) fdm_fwd_kernel(const StepState* __restric
         acc.w += xv * u[q].w;
       }
     }
-    for (; l < L; l += G) {
-      const float4 u = *(const float4*)(Us + (size_t)l * L + 4 * t);
+    for (; l < Lin; l += G) {
+      const float4 u = *(const float4*)(Us + (size_t)l * Lout + 4 * t);
       const float xv = xs[l];
       acc.x += xv * u.x;
       acc.y += xv * u.y;
       acc.z += xv * u.z;
       acc.w += xv * u.w;
     }
-    *(float4*)(part + g * L + 4 * t) = acc;
+    *(float4*)(part + g * Lout + 4 * t) = acc;
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < L; k += 256) {
+  for (int k = threadIdx.x; k < Lout; k += 256) {
     float y = 0.f;
-    for (int gg = 0; gg < G; ++gg) y += part[gg * L + k];
-    if (y32) y32[(size_t)r * L + k] = y;
-    if (y16) y16[(size_t)r * L + k] = f2bf(y);
+    for (int gg = 0; gg < G; ++gg) y += part[gg * Lout + k];
+    if (y32) y32[(size_t)r * Lout + k] = y;
+    if (y16) y16[(size_t)r * Lout + k] = f2bf(y);
   }
 }
 
-void k_fdm_fwd(const StepState* st, const float* x1, const float* U, const uint32_t* slot, int L,
-               float* y32, bf16_t* y16, int max_rows, hipStream_t s) {
-  hipLaunchKernelGGL(fdm_fwd_kernel, dim3(max_rows), dim3(256), 0, s, st, x1, U, slot, L, y32, y16);
+void k_fdm_fwd(const StepState* st, const float* x1, const float* U, const uint32_t* slot, int Lin,
+               int Lout, float* y32, bf16_t* y16, int max_rows, hipStream_t s) {
+  hipLaunchKernelGGL(fdm_fwd_kernel, dim3(max_rows), dim3(256), 0, s, st, x1, U, slot, Lin, Lout,
+                     y32, y16);
 }
 
 // Adjoint of Eq. 15 fused with the Adam step on U_s:
@@ -201,33 +204,32 @@ void k_fdm_fwd(const StepState* st, const float* x1, const float* U, const uint3
 __global__ void __launch_bounds__(256) fdm_bwd_kernel(
     const StepState* __restrict__ st, const float* __restrict__ x1, const float* __restrict__ dy,
     float* __restrict__ U, float* __restrict__ mU, float* __restrict__ vU,
-    float* __restrict__ dU_keep, const uint32_t* __restrict__ slot, int L, AdamCfg ac, bool update,
+    float* __restrict__ dU_keep, const uint32_t* __restrict__ slot, int Lin, int Lout, AdamCfg ac,
+    bool update,
     float* __restrict__ dx1_32, bf16_t* __restrict__ dx1_16) {
   const int r = blockIdx.x;
   if (r >= st->rows) return;
   __shared__ float xs[256];
   __shared__ float ds[256];
-  const int tpr = L >> 2, G = 256 / tpr;
+  const int tpr = Lout >> 2, G = 256 / tpr;
   const int t = threadIdx.x % tpr, g = threadIdx.x / tpr;
-  for (int l = threadIdx.x; l < L; l += 256) {
-    xs[l] = x1[(size_t)r * L + l];
-    ds[l] = dy[(size_t)r * L + l];
-  }
+  for (int l = threadIdx.x; l < Lin; l += 256) xs[l] = x1[(size_t)r * Lin + l];
+  for (int k = threadIdx.x; k < Lout; k += 256) ds[k] = dy[(size_t)r * Lout + k];
   __syncthreads();
   if (g >= G) return;
-  const size_t base_s = (size_t)slot[r] * L * L;
+  const size_t base_s = (size_t)slot[r] * Lin * Lout;
   const float4 d4 = *(const float4*)(ds + 4 * t);
   const float b1 = ac.beta1, b2 = ac.beta2;
   const float lr_bc = ac.lr / st->bc1;
   const float inv_bc2 = 1.0f / st->bc2;
   // one row l of U_s: dx'[l] (from U before the update), dU, Adam
   auto row = [&](int l, float4 u, float4 m, float4 v) {
-    const size_t idx = base_s + (size_t)l * L + 4 * t;
+    const size_t idx = base_s + (size_t)l * Lout + 4 * t;
     float part = u.x * d4.x + u.y * d4.y + u.z * d4.z + u.w * d4.w;
     for (int o = tpr >> 1; o >= 1; o >>= 1) part += __shfl_xor(part, o, 64);
     if (t == 0) {
-      if (dx1_32) dx1_32[(size_t)r * L + l] = part;
-      if (dx1_16) dx1_16[(size_t)r * L + l] = f2bf(part);
+      if (dx1_32) dx1_32[(size_t)r * Lin + l] = part;
+      if (dx1_16) dx1_16[(size_t)r * Lin + l] = f2bf(part);
     }
     const float xv = xs[l];
     const float gr[4] = {xv * d4.x, xv * d4.y, xv * d4.z, xv * d4.w};
@@ -247,18 +249,18 @@ __global__ void __launch_bounds__(256) fdm_bwd_kernel(
       nt_store4(vU + idx, v);
     }
   };
-  for (int l = g; l < L; l += G) {
-    const size_t idx = base_s + (size_t)l * L + 4 * t;
+  for (int l = g; l < Lin; l += G) {
+    const size_t idx = base_s + (size_t)l * Lout + 4 * t;
     row(l, *(const float4*)(U + idx), update ? nt_load4(mU + idx) : make_float4(0.f, 0.f, 0.f, 0.f),
         update ? nt_load4(vU + idx) : make_float4(0.f, 0.f, 0.f, 0.f));
   }
 }
 
 void k_fdm_bwd(const StepState* st, const float* x1, const float* dy, float* U, float* mU,
-               float* vU, float* dU_keep, const uint32_t* slot, int L, AdamCfg ac, bool update,
-               float* dx1_32, bf16_t* dx1_16, int max_rows, hipStream_t s) {
+               float* vU, float* dU_keep, const uint32_t* slot, int Lin, int Lout, AdamCfg ac,
+               bool update, float* dx1_32, bf16_t* dx1_16, int max_rows, hipStream_t s) {
   hipLaunchKernelGGL(fdm_bwd_kernel, dim3(max_rows), dim3(256), 0, s, st, x1, dy, U, mU, vU,
-                     dU_keep, slot, L, ac, update, dx1_32, dx1_16);
+                     dU_keep, slot, Lin, Lout, ac, update, dx1_32, dx1_16);
 }
 
 // ---------------------------------------------------------------------------

@@ -103,7 +103,8 @@ struct Model {
   edpc_config cfg;
   int C, E, F, L, N, H, K;
   bool bf16;
-  bool lte = true;  // false: the F x F FDM ablation (EDPC_CFG_NO_LTE)
+  bool lte = true;  // false: no shared W1, b1, W2, b2 (EDPC_CFG_NO_LTE or EDPC_CFG_LOW_RANK)
+  bool low_rank = false;  // per-stream factors A_s, U_s, B_s (EDPC_CFG_LOW_RANK)
   size_t n_slots, max_rows;
   KernelConfig kc;
   std::vector<TensorInfo> tens;
@@ -114,6 +115,8 @@ struct Model {
   float *param = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr;
   bf16_t* p16 = nullptr;
   float *U = nullptr, *mU = nullptr, *vU = nullptr, *dUkeep = nullptr;
+  // low-rank ablation: A [n_slots, F, L] and B [n_slots, L, F] with Adam moments
+  float *A = nullptr, *mA = nullptr, *vA = nullptr, *B = nullptr, *mB = nullptr, *vB = nullptr;
   StepState* st = nullptr;
 
   // workspace

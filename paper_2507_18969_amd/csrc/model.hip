@@ -103,8 +103,12 @@ void Model::validate(const edpc_config& c) {
   if (c.branches < 1 || c.branches > 3) fail(EDPC_E_INVALID_ARG, "branches must be 1..3");
   if (c.cdf_bits != 16) fail(EDPC_E_INVALID_ARG, "only 16-bit CDFs are supported");
   if (c.precision != EDPC_FP32 && c.precision != EDPC_BF16) fail(EDPC_E_INVALID_ARG, "unknown precision");
-  if (c.flags & ~(EDPC_CFG_ZERO_HEAD | EDPC_CFG_AUTOTUNE | EDPC_CFG_NO_LTE))
+  if (c.flags & ~(EDPC_CFG_ZERO_HEAD | EDPC_CFG_AUTOTUNE | EDPC_CFG_NO_LTE | EDPC_CFG_LOW_RANK))
     fail(EDPC_E_INVALID_ARG, "unknown config flags");
+  if ((c.flags & EDPC_CFG_NO_LTE) && (c.flags & EDPC_CFG_LOW_RANK))
+    fail(EDPC_E_INVALID_ARG, "EDPC_CFG_NO_LTE and EDPC_CFG_LOW_RANK exclude each other");
+  if ((c.flags & EDPC_CFG_LOW_RANK) && (!pow2((uint32_t)(c.context * c.embed)) || c.context * c.embed > 256))
+    fail(EDPC_E_INVALID_ARG, "the low-rank factors need context * embed a power of two <= 256");
   if ((c.flags & EDPC_CFG_NO_LTE) && c.latent != c.context * c.embed)
     fail(EDPC_E_INVALID_ARG, "without the LTE the FDM is F x F: latent must equal context * embed");
   if ((c.context * c.embed) % 8) fail(EDPC_E_INVALID_ARG, "context * embed must be a multiple of 8");
@@ -156,7 +160,7 @@ KernelConfig Model::default_config(const edpc_config& c, size_t rows) {
   // row-block kernels index activations with 32-bit offsets.
   const char* env = std::getenv("EDPC_FUSED");
   k.fused = !(env && env[0] == '0') && c.precision == EDPC_BF16 && rows <= (1u << 20) &&
-            !(c.flags & EDPC_CFG_NO_LTE) &&
+            !(c.flags & (EDPC_CFG_NO_LTE | EDPC_CFG_LOW_RANK)) &&
             fused_supported(F, L, H, (int)c.branches, (int)c.blocks);
   return k;
 }
@@ -186,7 +190,8 @@ Model::Model(const edpc_config& c, size_t nslots, size_t rows, const KernelConfi
   K = c.branches;
   bf16 = c.precision == EDPC_BF16;
   kc = kcfg ? *kcfg : default_config(c, rows);
-  lte = !(c.flags & EDPC_CFG_NO_LTE);
+  low_rank = (c.flags & EDPC_CFG_LOW_RANK) != 0;
+  lte = !(c.flags & EDPC_CFG_NO_LTE) && !low_rank;
   if (kc.fused && !(bf16 && lte && fused_supported(F, L, H, K, N) && rows <= (1u << 20)))
     fail(EDPC_E_UNSUPPORTED, "fused step requested for an unsupported shape");
 
@@ -238,6 +243,15 @@ Model::Model(const edpc_config& c, size_t nslots, size_t rows, const KernelConfi
   U = dalloc<float>(fdm);
   mU = dalloc<float>(fdm);
   vU = dalloc<float>(fdm);
+  if (low_rank) {
+    const size_t fac = n_slots * (size_t)F * L;
+    A = dalloc<float>(fac);
+    mA = dalloc<float>(fac);
+    vA = dalloc<float>(fac);
+    B = dalloc<float>(fac);
+    mB = dalloc<float>(fac);
+    vB = dalloc<float>(fac);
+  }
   st = dalloc<StepState>(1);
 
   const size_t R = max_rows;
@@ -248,10 +262,12 @@ Model::Model(const edpc_config& c, size_t nslots, size_t rows, const KernelConfi
   // first block's input (x'' = y) directly
   if (bf16 && lte) X16 = dalloc<bf16_t>(R * F);
   if (!bf16 || !lte) X32 = dalloc<float>(R * F);
-  X1 = lte ? dalloc<float>(R * L) : X32;
+  X1 = (lte || low_rank) ? dalloc<float>(R * L) : X32;
   for (int j = 0; j <= N; ++j) Hs.push_back(dalloc<float>(R * F));
   if (lte) {
     if (bf16) Y16 = dalloc<bf16_t>(R * L); else Y32 = dalloc<float>(R * L);
+  } else if (low_rank) {  // y = x' U_s in FP32, then x'' = y B_s writes the first block's input
+    Y32 = dalloc<float>(R * L);
   } else {
     Y32 = Hs[0];
   }
@@ -280,6 +296,9 @@ Model::Model(const edpc_config& c, size_t nslots, size_t rows, const KernelConfi
     dY = dalloc<float>(R * L);
     dX1_32 = dalloc<float>(R * L);
     if (bf16) dX1_16 = dalloc<bf16_t>(R * L);
+  } else if (low_rank) {
+    dY = dalloc<float>(R * L);
+    dX1_32 = dalloc<float>(R * L);
   } else {  // dy = dx'' and dx = dx'
     dY = dH32[0];
     dX1_32 = dX;
@@ -316,6 +335,12 @@ void Model::init_params(hipStream_t s) {
   hip_check(hipMemsetAsync(grad, 0, P * sizeof(float), s), "memset");
   hip_check(hipMemsetAsync(mU, 0, n_slots * (size_t)L * L * sizeof(float), s), "memset");
   hip_check(hipMemsetAsync(vU, 0, n_slots * (size_t)L * L * sizeof(float), s), "memset");
+  if (low_rank) {  // slot s draws the counter range starting at s * F * L, like U
+    const size_t fac = n_slots * (size_t)F * L;
+    k_init_uniform(A, fac, cfg.seed, 9, 0, (float)(1.0 / std::sqrt((double)F)), s);
+    k_init_uniform(B, fac, cfg.seed, 10, 0, (float)(1.0 / std::sqrt((double)L)), s);
+    for (float* z : {mA, vA, mB, vB}) hip_check(hipMemsetAsync(z, 0, fac * sizeof(float), s), "memset");
+  }
   if (bf16) k_to_bf16(param, p16, P, s);
   if (kc.fused) build_frags(s);
   hip_check(hipGetLastError(), "init");
@@ -722,7 +747,7 @@ void Model::step(StepMode mode, const StreamIO& io, const StepOutputs& out, int 
     fi.decoding = mode == MODE_DECODE ? 1 : 0;
     fi.io = io;
     TIMED(KC_EMBED, hip_check(launch_fused_in(F, L, fi, R, s), "fused in launch"));
-    TIMED(KC_FDM_FWD, k_fdm_fwd(st, X1, U, slot, L, Y32, Y16, R, s));  // Eq. 15
+    TIMED(KC_FDM_FWD, k_fdm_fwd(st, X1, U, slot, L, L, Y32, Y16, R, s));  // Eq. 15
     // LTE up .. head .. coder .. adjoint back to dY, one workgroup per 16 rows
     FusedArgs a = fa;
     a.head = ha;
@@ -734,7 +759,7 @@ void Model::step(StepMode mode, const StreamIO& io, const StepOutputs& out, int 
     }
     if (!backward) return;
     TIMED(KC_FDM_BWD, k_fdm_bwd(st, X1, dY, U, mU, vU, out.keep_fdm_grad ? dUkeep : nullptr, slot,
-                                L, ac, out.update, dX1_32, dX1_16, R, s));
+                                L, L, ac, out.update, dX1_32, dX1_16, R, s));
     TIMED(KC_EMB_GRAD, hip_check(launch_fused_out(F, L, fout, R, s), "fused out launch"));
     product(PS_WGRAD, 0, R, s);
     if (out.update) {
@@ -750,8 +775,10 @@ void Model::step(StepMode mode, const StreamIO& io, const StepOutputs& out, int 
   }
   TIMED(KC_EMBED, k_embed(st, ctx, P_("emb"), C, E, X32, X16, R, s));
   if (lte) product(PS_LTE_DOWN, 0, R, s);
-  TIMED(KC_FDM_FWD, k_fdm_fwd(st, X1, U, slot, L, Y32, Y16, R, s));  // Eq. 15
+  if (low_rank) TIMED(KC_FDM_FWD, k_fdm_fwd(st, X32, A, slot, F, L, X1, nullptr, R, s));  // x' = x A_s
+  TIMED(KC_FDM_FWD, k_fdm_fwd(st, X1, U, slot, L, L, Y32, Y16, R, s));  // Eq. 15
   if (lte) product(PS_LTE_UP, 0, R, s);
+  if (low_rank) TIMED(KC_FDM_FWD, k_fdm_fwd(st, Y32, B, slot, L, F, Hs[0], nullptr, R, s));  // x'' = y B_s
   for (int j = 0; j < N; ++j) {
     const std::string ln = "ln" + std::to_string(j);
     TIMED(KC_LN_FWD, k_ln_fwd(st, Hs[j], P_(ln + ".gamma"), P_(ln + ".beta"), F,
@@ -778,10 +805,18 @@ void Model::step(StepMode mode, const StreamIO& io, const StepOutputs& out, int 
                               dH32[j + 1], F, dH32[j], bf16 ? dH16[j] : nullptr, R, s));
   }
   if (lte) product(PS_LTE_UP_BWD, 0, R, s);
+  // low rank: dy = B_s dx'', dB_s = y (x) dx'' (B before its update), Adam on B_s
+  if (low_rank)
+    TIMED(KC_FDM_BWD, k_fdm_bwd(st, Y32, dH32[0], B, mB, vB, nullptr, slot, L, F, ac, out.update,
+                                dY, nullptr, R, s));
   // adjoint of Eq. 15, fused with Adam on U_s
   TIMED(KC_FDM_BWD, k_fdm_bwd(st, X1, dY, U, mU, vU, out.keep_fdm_grad ? dUkeep : nullptr, slot,
-                              L, ac, out.update, dX1_32, dX1_16, R, s));
+                              L, L, ac, out.update, dX1_32, dX1_16, R, s));
   if (lte) product(PS_LTE_DOWN_BWD, 0, R, s);
+  // low rank: dx = A_s dx', dA_s = x (x) dx', Adam on A_s
+  if (low_rank)
+    TIMED(KC_FDM_BWD, k_fdm_bwd(st, X32, dX1_32, A, mA, vA, nullptr, slot, F, L, ac, out.update,
+                                dX, nullptr, R, s));
   TIMED(KC_EMB_GRAD, k_emb_grad(st, ctx, dX, C, E, emb_partial, emb_chunk, emb_sub, R, G_("emb"), s));
   product(PS_WGRAD, 0, R, s);
   TIMED(KC_COLSUM, k_colsum(st, d_cs, n_cs, cs_blocks, cs_cols, cs_partial, R, s));

@@ -22,7 +22,8 @@ def lib_cfg(E, model: dict, precision: str = "fp32", **over):
     kw = {k: d[k] for k in ("context", "embed", "latent", "blocks", "hidden", "branches", "lr",
                             "beta1", "beta2", "eps", "seed") if k in d}
     return E.edpc_config_default(precision=precision, zero_head=d.get("zero_head", False),
-                                 autotune=d.get("autotune", False), lte=d.get("lte", True), **kw)
+                                 autotune=d.get("autotune", False), lte=d.get("lte", True),
+                                 low_rank=d.get("low_rank", False), **kw)
 
 
 def oracle_cfg(model: dict, **over) -> Config:
@@ -39,6 +40,11 @@ def load_oracle_state(m, om, slots=None):
     m.edpc_model_write("U", om.U.astype(np.float32))
     m.edpc_model_write("U", om.mU.astype(np.float32), kind=2)
     m.edpc_model_write("U", om.vU.astype(np.float32), kind=3)
+    if om.cfg.low_rank:
+        for n in ("A", "B"):
+            m.edpc_model_write(n, getattr(om, n).astype(np.float32))
+            m.edpc_model_write(n, getattr(om, "m" + n).astype(np.float32), kind=2)
+            m.edpc_model_write(n, getattr(om, "v" + n).astype(np.float32), kind=3)
     m.edpc_model_set_step(om.tau)
 
 

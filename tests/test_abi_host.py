@@ -59,6 +59,18 @@ def test_config_validation():
         E.edpc_config_validate(c)
 
 
+def test_low_rank_config_validation():
+    # the low-rank factors run through the per-stream kernels: F = context *
+    # embed a power of two <= 256, and the flag excludes the F x F ablation
+    E.edpc_config_validate(E.edpc_config_default(context=16, embed=16, latent=64, low_rank=True))
+    for bad in (dict(context=32, embed=16, latent=64, low_rank=True),
+                dict(context=12, embed=16, latent=64, low_rank=True),
+                dict(context=16, embed=16, latent=256, low_rank=True, lte=False)):
+        with pytest.raises(E.EdpcError) as ei:
+            E.edpc_config_validate(E.edpc_config_default(**bad))
+        assert ei.value.status == -1
+
+
 def test_encode_bound():
     c = E.edpc_config_default()
     assert E.edpc_encode_bound(c, [10, 0, 5]) == 96 + 20 * 3 + (22 + 2 + 12)

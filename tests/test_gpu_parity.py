@@ -15,7 +15,7 @@ import gen
 import oracle
 from oracle.codec import split_streams
 from oracle.model import Model as OModel
-from oracle.model import init_fdm, init_shared
+from oracle.model import init_fdm, init_low_rank, init_shared
 from oracle.quantize import cumulative, quantize
 from oracle.rangecoder import RangeEncoder
 from tests.gpu_util import banner, lib_cfg, load_oracle_state, oracle_cfg, parse_container
@@ -477,3 +477,47 @@ def test_without_lte_variant(E, precision):
 def test_without_lte_rejects_non_square_fdm(E):
     with pytest.raises(Exception):
         E.edpc_config_validate(lib_cfg(E, dict(SMALL, lte=False)))
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_low_rank_variant(E, precision):
+    # the "low-rank factorization" ablation of Table 4: per-stream factors
+    # x' = x A_s, y = x' U_s, x'' = y B_s, no shared W1 / W2 or biases
+    model = dict(SMALL, low_rank=True)
+    C = model["context"]
+    ocfg = oracle_cfg(model)
+    m0 = E.Model(lib_cfg(E, model, precision), 3, 3)
+    for k, v in init_shared(ocfg).items():
+        assert np.array_equal(m0.edpc_model_read(k), v.reshape(-1)), k
+    A0, B0 = init_low_rank(ocfg, range(3))
+    assert np.array_equal(m0.edpc_model_read("A"), A0.reshape(-1))
+    assert np.array_equal(m0.edpc_model_read("B"), B0.reshape(-1))
+    del m0
+    om, m, ctx, tgt = _step_case(E, model, precision, rows=8, pos=C + 8, om_steps=8, prefix=C + 9)
+    assert om.A.shape[1:] == (256, 64) and om.B.shape[1:] == (64, 256)
+    if precision == "fp32":
+        _, g_o, dU_o = _compare_step(E, om, m, ctx, tgt, p_tol=1e-5, g_rtol=1e-4)
+        _compare_update(E, om, m, ctx, tgt, g_o, dU_o, tol=1e-6)
+        # the factors moved like the oracle's wherever their gradient stands
+        # clear of rounding noise
+        for n in ("A", "B"):
+            new_g = m.edpc_model_read(n)
+            new_o = getattr(om, n).reshape(-1)
+            g = np.abs(g_o[n]).reshape(-1)
+            clear = g > 1e-3 * (g.max() + 1e-30)
+            assert clear.sum() > 0.5 * g.size, n
+            assert np.abs(new_g - new_o)[clear].max() <= 1e-6, n
+            mo = getattr(om, "m" + n).reshape(-1)
+            mg = m.edpc_model_read(n, kind=E.EDPC_KIND_ADAM_M)
+            assert np.abs(mg - mo).max() <= 1e-4 * (np.abs(mo).max() + 1e-30), n
+    else:
+        _compare_step(E, om, m, ctx, tgt, p_tol=2e-3, g_rtol=3e-2)
+    del m
+    data, lens = gen.make_streams("small", prefix=200, n_streams=4)
+    cont = _encode(E, lib_cfg(E, model, precision), data, lens)
+    out, _ = E.edpc_decode(cont)
+    assert out.cpu().numpy().tobytes() == data.tobytes()
+    _, pays = parse_container(cont.cpu().numpy().tobytes())
+    pay_o, _ = oracle.encode(split_streams(data, lens), ocfg)
+    for p, po in zip(pays, pay_o):
+        assert abs(len(p) - len(po)) <= 2
