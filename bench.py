@@ -168,6 +168,58 @@ def extra_workload(torch, E, name, warmup, steps):
     return res
 
 
+ABLATIONS = (
+    # name, model overrides (Table 4 rows; F = context x embed = 256 so every
+    # variant is accepted: w/o LTE needs latent = F, low-rank a power-of-two F)
+    ("base", {}),
+    ("wo_lte", {"latent": 256, "lte": False}),
+    ("low_rank", {"low_rank": True}),
+    ("k3", {"branches": 3}),
+    ("one_block", {"blocks": 1}),
+)
+
+
+def ablation_workload(torch, E, warmup, steps, precision="bf16"):
+    """Encoder steady-state rate and device memory of the Table 4 variants on one
+    model (context 16, embed 16, latent 64, 2 blocks x hidden 128, k = 2) over the
+    1024-stream order-2 Markov input (prefixes).  Memory is what the session holds
+    on the device (free-memory drop from begin to after the first steps)."""
+    import gen
+    w = gen.WORKLOADS["mid_bf16"]
+    base = dict(gen.WORKLOADS["small"].model)
+    C = base["context"]
+    prefix = C + warmup + steps + 8
+    log(f"ablations: generating input (prefix {prefix} bytes per stream)")
+    data, lens = gen.make_streams(w, prefix=prefix)
+    d_in = torch.as_tensor(data).to("cuda")
+    rows = int((lens > C + warmup).sum())
+    out = {"model": "context 16, embed 16, latent 64, 2 blocks x hidden 128, k = 2",
+           "streams": int(len(lens)), "precision": precision}
+    for name, over in ABLATIONS:
+        m = dict(base, **over)
+        keys = ("context", "embed", "latent", "blocks", "hidden", "branches", "lr", "beta1",
+                "beta2", "eps", "seed")
+        cfg = E.edpc_config_default(precision=precision, autotune=True,
+                                    lte=m.get("lte", True), low_rank=m.get("low_rank", False),
+                                    **{k: m[k] for k in keys})
+        torch.cuda.synchronize()
+        free0 = torch.cuda.mem_get_info()[0]
+        enc = E.edpc_encoder_begin(cfg, d_in, lens)
+        done, ms, _ = time_session(torch, enc, warmup, steps)
+        free1 = torch.cuda.mem_get_info()[0]
+        kern = enc.edpc_session_time_kernels(4)
+        enc.edpc_session_destroy()
+        torch.cuda.synchronize()
+        out[name] = {"encode_MBps": round(done * rows / (ms * 1e-3) / 1e6, 4),
+                     "ms_per_step": round(ms / done, 4), "steps": int(done),
+                     "session_MB": round((free0 - free1) / 1e6, 1),
+                     "row_block_step": kern["fused_rowblock_step"][1] > 0}
+        log(f"ablation {name}: {out[name]}")
+    del d_in
+    torch.cuda.empty_cache()
+    return out
+
+
 def source_digest():
     """Digest of the kernel sources the stored counter readings belong to."""
     import hashlib
@@ -282,7 +334,7 @@ def main():
                          "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE readings)")
     ap.add_argument("--extra", default="",
                     help="comma list of further workloads measured after the main one "
-                         "(ragged, large); reported under extra_workloads")
+                         "(ragged, large, ablations); reported under extra_workloads")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path (sharding the "
@@ -328,7 +380,10 @@ def main():
         line["bf16_over_fp32_encode"] = round(res["bf16"]["encode"] / res["fp32"]["encode"], 3)
     extra = {}
     for name in [x for x in a.extra.split(",") if x]:
-        extra[name] = extra_workload(torch, E, name, a.warmup, min(a.steps, 200))
+        if name == "ablations":
+            extra[name] = ablation_workload(torch, E, a.warmup, min(a.steps, 200))
+        else:
+            extra[name] = extra_workload(torch, E, name, a.warmup, min(a.steps, 200))
     if extra:
         line["extra_workloads"] = extra
     if a.full:
