@@ -179,6 +179,16 @@ ABLATIONS = (
 )
 
 
+def ablation_cfg(E, base, over, precision):
+    """Library configuration of one ablation: the base model with `over` applied."""
+    m = dict(base, **over)
+    keys = ("context", "embed", "latent", "blocks", "hidden", "branches", "lr", "beta1",
+            "beta2", "eps", "seed")
+    return E.edpc_config_default(precision=precision, autotune=True,
+                                 lte=m.get("lte", True), low_rank=m.get("low_rank", False),
+                                 **{k: m[k] for k in keys})
+
+
 def ablation_workload(torch, E, warmup, steps, precision="bf16"):
     """Encoder steady-state rate and device memory of the Table 4 variants on one
     model (context 16, embed 16, latent 64, 2 blocks x hidden 128, k = 2) over the
@@ -196,12 +206,7 @@ def ablation_workload(torch, E, warmup, steps, precision="bf16"):
     out = {"model": "context 16, embed 16, latent 64, 2 blocks x hidden 128, k = 2",
            "streams": int(len(lens)), "precision": precision}
     for name, over in ABLATIONS:
-        m = dict(base, **over)
-        keys = ("context", "embed", "latent", "blocks", "hidden", "branches", "lr", "beta1",
-                "beta2", "eps", "seed")
-        cfg = E.edpc_config_default(precision=precision, autotune=True,
-                                    lte=m.get("lte", True), low_rank=m.get("low_rank", False),
-                                    **{k: m[k] for k in keys})
+        cfg = ablation_cfg(E, base, over, precision)
         torch.cuda.synchronize()
         free0 = torch.cuda.mem_get_info()[0]
         enc = E.edpc_encoder_begin(cfg, d_in, lens)

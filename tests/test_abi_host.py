@@ -71,6 +71,20 @@ def test_low_rank_config_validation():
         assert ei.value.status == -1
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_bench_ablation_configs_validate(precision):
+    # every Table 4 variant the bench's ablation workload runs is accepted, and
+    # carries the flag bits of its variant
+    import bench
+    import gen
+    base = gen.WORKLOADS["small"].model
+    for name, over in bench.ABLATIONS:
+        cfg = bench.ablation_cfg(E, base, over, precision)
+        E.edpc_config_validate(cfg)
+        assert bool(cfg.flags & E.EDPC_CFG_NO_LTE) == (over.get("lte") is False), name
+        assert bool(cfg.flags & E.EDPC_CFG_LOW_RANK) == bool(over.get("low_rank")), name
+
+
 def test_encode_bound():
     c = E.edpc_config_default()
     assert E.edpc_encode_bound(c, [10, 0, 5]) == 96 + 20 * 3 + (22 + 2 + 12)
