@@ -12,7 +12,10 @@ Sources
   permutation of the 256 symbols (text-like data);
 * uniform random bytes (already-compressed / backup-like data);
 * run-length bytes, geometric run lengths (structured binary);
-* int16 little-endian samples of a noisy sinusoid (sound-like data).
+* int16 little-endian samples of a noisy sinusoid (sound-like data);
+* i.i.d. bytes over a four-letter alphabet with probabilities 1/2, 1/4,
+  1/8, 1/8 (entropy 1.75 bits): a source an online model learns within a
+  few hundred steps, so that coded probabilities become strongly peaked.
 
 Every function is deterministic in its seeds.  Nothing here models or codes
 the data; it only produces it.
@@ -127,6 +130,28 @@ def markov2_streams(n_streams: int, length: int, zipf_s: float = 1.2,
             out[:, i] = x
             prev2, prev1 = prev1, x
     return out
+
+
+#: Law of the skewed source: ranks 0..3 with these probabilities, written as
+#: the bytes "a".."d".
+SKEWED_PROBS = (0.5, 0.25, 0.125, 0.125)
+SKEWED_FIRST_BYTE = 0x61
+
+
+def skewed_streams(n_streams: int, length: int, table_seed: int = TABLE_SEED,
+                   first_stream: int = 0) -> np.ndarray:
+    """``[n_streams, length]`` uint8 of i.i.d. skewed bytes.
+
+    Byte i of stream s is the inverse-CDF rank of
+    ``uniform01(stream_seed(s, table_seed + 2) + i)`` under SKEWED_PROBS,
+    offset to SKEWED_FIRST_BYTE.  A shorter ``length`` yields an exact prefix.
+    """
+    cdf = np.cumsum(np.asarray(SKEWED_PROBS, dtype=np.float64))
+    seeds = stream_seed(np.arange(first_stream, first_stream + n_streams), table_seed + 2)
+    with np.errstate(over="ignore"):
+        idx = seeds[:, None] + np.arange(length, dtype=np.uint64)[None, :]
+    ranks = _rank_from_uniform(uniform01(idx), cdf)
+    return (SKEWED_FIRST_BYTE + ranks).astype(np.uint8)
 
 
 # --------------------------------------------------------------------------

@@ -20,7 +20,7 @@ from . import sources
 class Workload:
     name: str
     description: str
-    source: str  # "markov2" | "mixture"
+    source: str  # "markov2" | "mixture" | "skewed"
     n_streams: int
     stream_len: int | None  # equal-length streams; None for ragged
     total_bytes: int
@@ -60,6 +60,15 @@ WORKLOADS = {
     "large": Workload(
         "large", "1 GiB order-2 Markov Zipf(1.2), 16384 streams x 64 KiB; BF16 GEMMs",
         "markov2", 16384, 65536, 16384 * 65536, 1.2, _LARGE, "bf16"),
+    # a learnable stand-in (i.i.d. skewed bytes, 1.75 bits of entropy) on the
+    # two models above, for size parity where the coded probabilities are
+    # strongly peaked; not one of the benchmarked workloads
+    "skewed_small": Workload(
+        "skewed_small", "i.i.d. skewed 4-letter bytes, 8 streams x 2 KiB; small model, FP32",
+        "skewed", 8, 2048, 8 * 2048, 0.0, _SMALL, "fp32"),
+    "skewed_mid": Workload(
+        "skewed_mid", "i.i.d. skewed 4-letter bytes, 1024 streams x 512 B; 1024-stream model",
+        "skewed", 1024, 512, 1024 * 512, 0.0, _MID, "bf16"),
 }
 
 
@@ -75,9 +84,12 @@ def make_streams(w: Workload | str, prefix: int | None = None,
     if isinstance(w, str):
         w = WORKLOADS[w]
     nst = w.n_streams if n_streams is None else min(n_streams, w.n_streams)
-    if w.source == "markov2":
+    if w.source in ("markov2", "skewed"):
         length = w.stream_len if prefix is None else min(prefix, w.stream_len)
-        arr = sources.markov2_streams(nst, length, w.zipf_s)
+        if w.source == "markov2":
+            arr = sources.markov2_streams(nst, length, w.zipf_s)
+        else:
+            arr = sources.skewed_streams(nst, length)
         return arr.reshape(-1), np.full(nst, length, dtype=np.int64)
     lens = w.lens()[:nst]
     return sources.mixture_streams(lens, w.zipf_s, prefix=prefix)

@@ -12,6 +12,12 @@ Cases:
   mid_slice       4 streams x 512 bytes of the mid workload
   ragged_prefix   32 streams of the mixture source cut to seeded lengths in
                   [100, 1500] (ragged), mid model
+  ragged_wide     all 4096 streams of the mixture workload cut to their first
+                  96 bytes (64 model steps), mid model
+  skewed_small    the learnable skewed source, 8 streams x 2 KiB, small model
+  skewed_mid_64   the skewed source, 64 streams x 512 B, mid model
+  skewed_wide     the skewed source, 1024 streams x 256 B, mid model (the
+                  1024-row launch of the benchmarked configuration)
 """
 
 from __future__ import annotations
@@ -48,17 +54,28 @@ CASES = {
     "mid_prefix": ("mid_fp32", 160, None, {}),
     "mid_slice": ("mid_fp32", 512, 4, {}),
     "ragged_prefix": ("ragged", "ragged_prefix", None, {}),
+    "ragged_wide": ("ragged", 96, None, {}),
+    "skewed_small": ("skewed_small", None, None, {}),
+    "skewed_mid_64": ("skewed_mid", 512, 64, {}),
+    "skewed_wide": ("skewed_mid", 256, None, {}),
 }
 
 
-def run_case(name):
+def case_input(name):
+    """(flat data, lengths, model dict with the case's overrides) of a case."""
     wl, prefix, nst, over = CASES[name]
     w = gen.WORKLOADS[wl]
     if prefix == "ragged_prefix":
         data, lens = ragged_prefix_input()
     else:
         data, lens = gen.make_streams(w, prefix=prefix, n_streams=nst)
-    cfg = Config.from_dict(w.model).with_(**over)
+    return data, lens, dict(w.model, **over)
+
+
+def run_case(name):
+    wl, prefix, nst, over = CASES[name]
+    data, lens, model = case_input(name)
+    cfg = Config.from_dict(model)
     t = time.time()
     pay, info = oracle.encode(split_streams(data, lens), cfg)
     return {
@@ -73,7 +90,7 @@ def run_case(name):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--only", default=None)
+    ap.add_argument("--only", default=None, help="comma list of case names")
     a = ap.parse_args()
     path = os.path.join(HERE, "oracle_sizes.json")
     out = {}
@@ -81,7 +98,7 @@ def main():
         with open(path) as f:
             out = json.load(f)
     for name in CASES:
-        if a.only and name != a.only:
+        if a.only and name not in a.only.split(","):
             continue
         out[name] = run_case(name)
         print(name, sum(out[name]["payload_bytes"]), f"{out[name]['oracle_seconds']:.1f}s", flush=True)
