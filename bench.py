@@ -70,16 +70,17 @@ def time_session(torch, sess, warmup, steps):
     return done, a.elapsed_time(b), wall
 
 
-def run_precision(torch, E, w, d_in, lens, data, precision, warmup, steps):
+def run_precision(torch, E, w, d_in, lens, data, precision, warmup, steps,
+                  kernel_steps=KERNEL_TIMING_STEPS):
     cfg = lib_cfg(E, w.model, precision)
     rows = len(lens)
     log(f"{precision}: encoder session")
     enc = E.edpc_encoder_begin(cfg, d_in, lens)
-    # per-kernel HIP-event times over KERNEL_TIMING_STEPS steps right after the
+    # per-kernel HIP-event times over kernel_steps steps right after the
     # warm-up (direct launches with events on the session stream), then the
     # timed steps (captured windows, no per-kernel events)
     enc.edpc_session_run(warmup)
-    kern = enc.edpc_session_time_kernels(KERNEL_TIMING_STEPS)
+    kern = enc.edpc_session_time_kernels(kernel_steps)
     done, ms, wall = time_session(torch, enc, 0, steps)
     enc.edpc_session_destroy()
     enc_mbps = done * rows / (ms * 1e-3) / 1e6
@@ -101,8 +102,9 @@ def run_precision(torch, E, w, d_in, lens, data, precision, warmup, steps):
     assert torch.equal(out, d_sub), "decoder output differs from the input"
     dec_mbps = ddone * rows / (dms * 1e-3) / 1e6
     log(f"{precision}: decode {dec_mbps:.3f} MB/s ({dms / ddone:.3f} ms/step)")
-    return dict(encode=enc_mbps, decode=dec_mbps, ms_per_step=ms / done, wall_s=wall,
-                kernels=kern, steps=done)
+    return dict(encode=enc_mbps, decode=dec_mbps, ms_per_step=ms / done,
+                decode_ms_per_step=dms / ddone, wall_s=wall, kernels=kern, steps=done,
+                kernel_steps=kernel_steps)
 
 
 def full_job(torch, E, w, d_in, lens, precision):
@@ -166,6 +168,150 @@ def extra_workload(torch, E, name, warmup, steps):
     del d_in
     torch.cuda.empty_cache()
     return res
+
+
+GEMM_CLASSES = ("gemm_lte_down", "gemm_lte_up", "gemm_branches_gelu", "gemm_block_out",
+                "gemm_head", "gemm_head_bwd", "gemm_gelu_bwd", "gemm_branches_bwd",
+                "gemm_lte_up_bwd", "gemm_lte_down_bwd", "gemm_weight_grads")
+
+
+def gemm_flops_per_step(m, rows):
+    """Algorithmic flops (2 per multiply-add) of each matrix-product class of
+    the layer-by-layer step on `rows` active rows."""
+    F, L, H, N, K = (m["context"] * m["embed"], m["latent"], m["hidden"], m["blocks"],
+                     m["branches"])
+    weights = L * F + F * L + N * (K * H * F + F * H) + 256 * F
+    per = {"gemm_lte_down": L * F, "gemm_lte_up": F * L, "gemm_branches_gelu": N * K * H * F,
+           "gemm_block_out": N * F * H, "gemm_head": 256 * F, "gemm_head_bwd": F * 256,
+           "gemm_gelu_bwd": N * H * F, "gemm_branches_bwd": N * F * K * H,
+           "gemm_lte_up_bwd": L * F, "gemm_lte_down_bwd": F * L, "gemm_weight_grads": weights}
+    return {k: 2 * rows * v for k, v in per.items()}
+
+
+def gemm_roofline(w, kern, rows, precision, n_steps):
+    """MFMA roofline of the layer-by-layer step's matrix products: algorithmic
+    flops over their summed HIP-event time, in total and per product class."""
+    fl = gemm_flops_per_step(w.model, rows)
+    peak = MFMA_PEAK_TFLOPS[precision]
+    by, tot_f, tot_ms = {}, 0.0, 0.0
+    for c in GEMM_CLASSES:
+        ms, launches = kern.get(c, (0.0, 0))
+        if not launches:
+            continue
+        f = fl[c] * n_steps
+        tf = f / (ms * 1e-3) / 1e12
+        by[c] = {"ms_per_step": round(ms / n_steps, 4), "tflops": round(tf, 1),
+                 "frac": round(tf / peak, 4)}
+        tot_f += f
+        tot_ms += ms
+    if not tot_ms:
+        return None
+    tf = tot_f / (tot_ms * 1e-3) / 1e12
+    return {"kernels": "matrix products", "bound": "mfma", "achieved": round(tf, 1), "peak": peak,
+            "unit": "TFLOP/s", "frac": round(tf / peak, 4), "ms_per_step": round(tot_ms / n_steps, 4),
+            "by_class": by}
+
+
+def large_workload(torch, E, precisions, warmup=8, kernel_steps=8, steps=24):
+    """The 16384-stream large model: encoder and sequential-decoder steady
+    state in each precision (a prefix of the input long enough for the steps
+    timed; by causality those steps are the first steps of the whole job)."""
+    import gen
+    w = gen.WORKLOADS["large"]
+    C = w.model["context"]
+    prefix = C + warmup + kernel_steps + steps + 16
+    log(f"large: generating input (prefix {prefix} bytes per stream)")
+    data, lens = gen.make_streams(w, prefix=prefix)
+    d_in = torch.as_tensor(data).to("cuda")
+    rows = len(lens)
+    out = {"workload": w.description, "streams": rows}
+    for prec in precisions:
+        r = run_precision(torch, E, w, d_in, lens, data, prec, warmup, steps, kernel_steps)
+        kern = r["kernels"]
+        out[prec] = {"encode_MBps": round(r["encode"], 4), "decode_MBps": round(r["decode"], 4),
+                     "ms_per_step": round(r["ms_per_step"], 3),
+                     "decode_ms_per_step": round(r["decode_ms_per_step"], 3),
+                     "kernels_ms_per_step": {k: round(v[0] / kernel_steps, 4)
+                                             for k, v in kern.items() if v[1]},
+                     "roofline_fdm_bwd_adam": fdm_roofline(w, kern, rows, stored=False),
+                     "roofline_gemm": gemm_roofline(w, kern, rows, prec, kernel_steps)}
+        log(f"large {prec}: {out[prec]['encode_MBps']} / {out[prec]['decode_MBps']} MB/s")
+    if "bf16" in out and "fp32" in out:
+        out["bf16_over_fp32_encode"] = round(out["bf16"]["encode_MBps"] / out["fp32"]["encode_MBps"], 3)
+    del d_in
+    torch.cuda.empty_cache()
+    return out
+
+
+def ragged_full_job(torch, E):
+    """The whole 256 MiB ragged mixture job: one encode and one decode of all
+    4096 streams, including the tail of shrinking active sets."""
+    import gen
+    w = gen.WORKLOADS["ragged"]
+    log("ragged_full: generating the 256 MiB input")
+    data, lens = gen.make_streams(w)
+    d_in = torch.as_tensor(data).to("cuda")
+    cfg = lib_cfg(E, w.model, w.precision)
+    n = int(d_in.numel())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cont = E.edpc_encode(cfg, d_in, lens)
+    torch.cuda.synchronize()
+    te = time.perf_counter() - t0
+    log(f"ragged_full: encode {n / te / 1e6:.3f} MB/s")
+    t0 = time.perf_counter()
+    out, _ = E.edpc_decode(cont)
+    torch.cuda.synchronize()
+    td = time.perf_counter() - t0
+    ok = bool(torch.equal(out, d_in))
+    hdr = 96 + 20 * len(lens)
+    res = {"workload": w.description, "streams": int(len(lens)), "bytes": n,
+           "steps": int(lens.max()), "encode_MBps": round(n / te / 1e6, 4),
+           "decode_MBps": round(n / td / 1e6, 4), "encode_s": round(te, 2),
+           "decode_s": round(td, 2), "roundtrip": ok,
+           "bits_per_byte": round(8.0 * (cont.numel() - hdr) / n, 4)}
+    log(f"ragged_full: {res}")
+    del d_in, out, cont
+    torch.cuda.empty_cache()
+    return res
+
+
+GOLDEN_FILE = os.path.join(ROOT, "tests", "golden", "oracle_sizes.json")
+
+
+def size_parity(torch, E, precisions, cases=("mid_prefix", "skewed_wide")):
+    """Compressed size against the oracle's (the metric's qualifier): the
+    benchmarked configuration encodes the inputs of stored oracle cases (the
+    1024-stream workload's first 160 bytes per stream, and 1024 streams of a
+    learnable skewed source) and its payload is compared with the oracle's
+    payload, written by tests/golden/make_oracle_golden.py."""
+    import gen
+    with open(GOLDEN_FILE) as f:
+        gold = json.load(f)
+    out = {}
+    worst = 0.0
+    for case in cases:
+        g = gold[case]
+        data, lens = gen.make_streams(g["workload"], prefix=g["prefix"], n_streams=g["n_streams"])
+        assert [int(x) for x in lens] == g["lens"], case
+        w = gen.WORKLOADS[g["workload"]]
+        d_in = torch.as_tensor(data).to("cuda")
+        o_bytes = sum(g["payload_bytes"])
+        res = {"streams": int(len(lens)), "bytes": int(lens.sum()),
+               "oracle_bits_per_byte": round(8.0 * o_bytes / lens.sum(), 5)}
+        for prec in precisions:
+            cont = E.edpc_encode(lib_cfg(E, dict(w.model, **g["overrides"]), prec), d_in, lens)
+            torch.cuda.synchronize()
+            pay = cont.numel() - (96 + 20 * len(lens))
+            rel = (pay - o_bytes) / o_bytes
+            worst = max(worst, abs(rel))
+            res[prec] = {"bits_per_byte": round(8.0 * pay / lens.sum(), 5),
+                         "rel_diff": round(rel, 6)}
+        out[case] = res
+        log(f"size parity {case}: {res}")
+    out["max_abs_rel_diff"] = round(worst, 6)
+    out["within_0.5pct"] = bool(worst <= 0.005)
+    return out
 
 
 ABLATIONS = (
@@ -339,7 +485,10 @@ def main():
                          "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE readings)")
     ap.add_argument("--extra", default="",
                     help="comma list of further workloads measured after the main one "
-                         "(ragged, large, ablations); reported under extra_workloads")
+                         "(ragged, ragged_full, large, ablations); reported under "
+                         "extra_workloads")
+    ap.add_argument("--no-size-parity", action="store_true",
+                    help="skip the compressed-size comparison with the oracle's stored sizes")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path (sharding the "
@@ -387,8 +536,14 @@ def main():
     for name in [x for x in a.extra.split(",") if x]:
         if name == "ablations":
             extra[name] = ablation_workload(torch, E, a.warmup, min(a.steps, 200))
+        elif name == "large":
+            extra[name] = large_workload(torch, E, a.precisions.split(","))
+        elif name == "ragged_full":
+            extra[name] = ragged_full_job(torch, E)
         else:
             extra[name] = extra_workload(torch, E, name, a.warmup, min(a.steps, 200))
+    if not a.no_size_parity:
+        line["size_parity_vs_oracle"] = size_parity(torch, E, list(res))
     if extra:
         line["extra_workloads"] = extra
     if a.full:

@@ -42,7 +42,13 @@
 extern "C" {
 #endif
 
-#define EDPC_ABI_VERSION 1
+#define EDPC_ABI_VERSION 2
+
+/* Limits of the codec.  The step counter of a run is a signed 32-bit value
+ * on the device, so a stream holds fewer than 2^31 bytes; the stream count
+ * bounds the container header. */
+#define EDPC_MAX_STREAM_LEN 0x7FFFFFFFull
+#define EDPC_MAX_STREAMS (1u << 24)
 
 typedef enum {
   EDPC_OK = 0,
@@ -87,6 +93,15 @@ typedef enum { EDPC_FP32 = 0, EDPC_BF16 = 1 } edpc_precision;
                                    power of two <= 256; excludes
                                    EDPC_CFG_NO_LTE.  Runs the layer-by-layer
                                    step in both precisions. */
+#define EDPC_CFG_LAYERWISE 0x10u /* BF16 models whose shape has the row-block
+                                   fused step run the layer-by-layer launch
+                                   sequence instead.  The two sequences sum in
+                                   different orders; the choice is recorded in
+                                   the container and the decoder follows the
+                                   container, not this flag. */
+#define EDPC_CFG_NO_GRAPHS 0x20u /* sessions launch every step directly instead
+                                   of replaying captured windows of 32 steps
+                                   (same results; for timing and debugging) */
 
 typedef struct {
   uint32_t struct_size; /* sizeof(edpc_config) */
@@ -114,8 +129,13 @@ edpc_status edpc_config_default(edpc_config* cfg);
 edpc_status edpc_config_validate(const edpc_config* cfg);
 
 /* ------------------------------------------------------------------------
- * Whole-input codec.  Input: n_streams byte streams concatenated in d_in,
- * lengths in h_lens.  Output: one container (header + per-stream payloads)
+ * Whole-input codec: Algorithm 1 run over b streams in lockstep.  Bytes
+ * 0 .. t-1 of every stream are coded with equal probability; every later
+ * byte x_i is coded with the model's Pr(i) (Eq. 1) and followed by one Adam
+ * step on the mean cross entropy over the active streams (Eq. 2); decoding
+ * replays the same loop.  Input: n_streams byte streams concatenated in
+ * d_in, lengths in h_lens (each <= EDPC_MAX_STREAM_LEN, n_streams <=
+ * EDPC_MAX_STREAMS).  Output: one container (header + per-stream payloads)
  * in d_out.  These calls synchronise `stream` before returning.
  * ---------------------------------------------------------------------- */
 
@@ -131,6 +151,8 @@ edpc_status edpc_encode(const edpc_config* cfg, const uint8_t* d_in,
                         void* stream);
 
 /* Parse a container header held in host memory (at least the header bytes;
+ * lengths above the codec limits, or sums of them that would overflow, are
+ * EDPC_E_CORRUPT;
  * *header_len receives its size, or the size needed if in_len is short, in
  * which case EDPC_E_CORRUPT is returned).  cfg/n_streams/h_lens may be NULL;
  * h_lens needs lens_cap >= n_streams entries. */
@@ -178,7 +200,10 @@ edpc_status edpc_session_time_kernels(edpc_session* s, uint64_t n_steps, float* 
 const char* edpc_kclass_name(int c);
 
 /* ------------------------------------------------------------------------
- * Model-level access: one step of the network on explicit contexts.
+ * Model-level access: one step of the network on explicit contexts, i.e.
+ * the "Model(x_{i-t} .. x_{i-1})" call of Algorithm 1 with Pr(i) (Eq. 1),
+ * optionally the cross entropy (Eq. 2), its gradient, and the update step
+ * (Adam, Sec. 4.1).  The network is Eqs. 9-16 (see the top of this file).
  * ---------------------------------------------------------------------- */
 typedef struct edpc_model edpc_model;
 
@@ -195,9 +220,11 @@ void edpc_model_destroy(edpc_model* m);
 
 /* One step on `rows` rows.  d_ctx: [rows, context] bytes, oldest first.
  * d_target: [rows] bytes (required with BACKWARD/UPDATE, else may be NULL).
- * h_slot: [rows] distinct FDM slot indices < n_slots (host memory).
+ * h_slot: [rows] distinct FDM slot indices < n_slots (host memory: the
+ * library checks range and distinctness before any kernel reads a slot).
  * Optional outputs: d_probs [rows, 256] FP32 softmax, d_cum [rows, 257]
- * integer CDF (the coder's table), d_loss [1] FP32 mean cross entropy.
+ * integer CDF (the coder's table), d_loss [1] FP32 mean cross entropy
+ * (device memory, so that the call stays asynchronous).
  * Asynchronous on `stream`. */
 edpc_status edpc_model_step(edpc_model* m, const uint8_t* d_ctx,
                             const uint8_t* d_target, const uint32_t* h_slot,
@@ -212,6 +239,14 @@ edpc_status edpc_model_step(edpc_model* m, const uint8_t* d_ctx,
 #define EDPC_KIND_GRAD 1u
 #define EDPC_KIND_ADAM_M 2u
 #define EDPC_KIND_ADAM_V 3u
+/* BF16 models, edpc_model_read only: the BF16 operand copy of a shared
+ * tensor that the products read, widened to FP32, in the tensor's own
+ * layout.  The row-block fused step keeps two copies of each weight matrix,
+ * one per product orientation (X W^T: OPERAND_NT, X W: OPERAND_NN); the
+ * layer-by-layer step keeps one copy of every tensor (both kinds return it).
+ * Tensors without an operand copy, and FP32 models, are EDPC_E_INVALID_ARG. */
+#define EDPC_KIND_OPERAND_NT 4u
+#define EDPC_KIND_OPERAND_NN 5u
 edpc_status edpc_model_tensor_count(const edpc_model* m, size_t* n);
 edpc_status edpc_model_tensor_info(const edpc_model* m, size_t idx, char* name,
                                    size_t name_cap, size_t* numel);
@@ -229,8 +264,24 @@ edpc_status edpc_model_write_device(edpc_model* m, uint32_t kind, size_t idx,
 edpc_status edpc_model_get_step(const edpc_model* m, uint64_t* tau);
 edpc_status edpc_model_set_step(edpc_model* m, uint64_t tau);
 
+/* Whole training state of a model (what Algorithm 1 adapts online: every
+ * parameter with its Adam moments, and the Adam step counter), as one host
+ * blob.  Layout (little-endian): "EDPS", u32 version (1), u32 tensor count,
+ * u32 0, u64 tau, u32 x 9 configuration fields (context, embed, latent,
+ * blocks, hidden, branches, cdf_bits, precision, flags), u64 n_slots; then
+ * per tensor in edpc_model_tensor_info order: u32 name length, the name
+ * padded with zeros to a multiple of 4 bytes, u64 numel, numel FP32
+ * parameters, numel FP32 first moments, numel FP32 second moments.
+ * get_state: if cap is too small (or h_buf is NULL) returns
+ * EDPC_E_CAPACITY with the size in *len.  set_state: the blob must come
+ * from a model of the same configuration and slot count
+ * (EDPC_E_INVALID_ARG otherwise).  Both synchronise the device. */
+edpc_status edpc_model_get_state(const edpc_model* m, void* h_buf, size_t cap, size_t* len);
+edpc_status edpc_model_set_state(edpc_model* m, const void* h_buf, size_t len);
+
 /* ------------------------------------------------------------------------
- * Range coder alone (the "Arithmetic Coding" step of Sec. 2.1): codes
+ * Range coder alone (the arithmetic-coding step of Sec. 2.1 and of
+ * Algorithm 1's encode / decode lines; G. N. N. Martin's range coder): codes
  * symbols with caller-supplied 16-bit CDF tables, one coder per stream.
  * d_cum: [n_steps, n_streams, 257] u32, cum[0] = 0, cum[256] = 65536,
  * strictly increasing.  d_sym: [n_steps, n_streams] bytes.  Stream s writes

@@ -14,7 +14,7 @@ decide the integers in the same precision.
 
 Pinned by: sum/positivity invariants, the uniform and one-hot special cases,
 and |q_v - p_v (T-256)| <= 1 away from the argmax bin
-(tests/test_oracle_quantize.py).
+(tests/test_oracle_coder.py).
 """
 
 from __future__ import annotations

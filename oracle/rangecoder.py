@@ -24,7 +24,7 @@ the following reading:
 Pinned by: exhaustive decode(encode(x)) == x on tiny alphabets and lengths,
 random round trips, the code-length bound (ideal + 2 bytes + truncation
 slack), and the uniform case, where 16-bit frequencies of 256 shift the
-stream's bytes through verbatim (tests/test_oracle_rangecoder.py).
+stream's bytes through verbatim (tests/test_oracle_coder.py).
 """
 
 from __future__ import annotations

@@ -26,8 +26,13 @@ EDPC_CFG_ZERO_HEAD = 0x1
 EDPC_CFG_AUTOTUNE = 0x2
 EDPC_CFG_NO_LTE = 0x4
 EDPC_CFG_LOW_RANK = 0x8
+EDPC_CFG_LAYERWISE = 0x10
+EDPC_CFG_NO_GRAPHS = 0x20
+EDPC_MAX_STREAM_LEN = 0x7FFFFFFF
+EDPC_MAX_STREAMS = 1 << 24
 EDPC_STEP_BACKWARD, EDPC_STEP_UPDATE, EDPC_STEP_KEEP_FDM_GRAD = 0x1, 0x2, 0x4
 EDPC_KIND_PARAM, EDPC_KIND_GRAD, EDPC_KIND_ADAM_M, EDPC_KIND_ADAM_V = 0, 1, 2, 3
+EDPC_KIND_OPERAND_NT, EDPC_KIND_OPERAND_NN = 4, 5
 KCLASS_COUNT = 24
 
 #: every symbol include/edpc.h declares
@@ -39,7 +44,8 @@ EXPORTS = [
     "edpc_session_destroy", "edpc_session_time_kernels", "edpc_kclass_name", "edpc_model_create", "edpc_model_destroy", "edpc_model_step",
     "edpc_model_tensor_count", "edpc_model_tensor_info", "edpc_model_read", "edpc_model_write",
     "edpc_model_read_device", "edpc_model_write_device",
-    "edpc_model_get_step", "edpc_model_set_step", "edpc_rc_encode", "edpc_rc_decode",
+    "edpc_model_get_step", "edpc_model_set_step", "edpc_model_get_state",
+    "edpc_model_set_state", "edpc_rc_encode", "edpc_rc_decode",
     "edpc_rc_encode_host", "edpc_rc_decode_host",
 ]
 
@@ -110,6 +116,8 @@ def lib() -> ctypes.CDLL:
         "edpc_model_write_device": (ctypes.c_int, [_P, ctypes.c_uint32, _SZ, _P, _SZ, _P]),
         "edpc_model_get_step": (ctypes.c_int, [_P, _U64P]),
         "edpc_model_set_step": (ctypes.c_int, [_P, ctypes.c_uint64]),
+        "edpc_model_get_state": (ctypes.c_int, [_P, _P, _SZ, _SZP]),
+        "edpc_model_set_state": (ctypes.c_int, [_P, _P, _SZ]),
         "edpc_rc_encode": (ctypes.c_int, [_P, _P, _SZ, _SZ, _P, _SZ, _U32P, _P]),
         "edpc_rc_decode": (ctypes.c_int, [_P, _P, _U32P, _SZ, _SZ, _SZ, _P, _P]),
         "edpc_rc_encode_host": (ctypes.c_int, [_P, _P, _SZ, _P, _SZ, _SZP]),
@@ -148,10 +156,12 @@ def edpc_config_default(**overrides) -> edpc_config:
     for k, v in overrides.items():
         if k == "precision" and isinstance(v, str):
             v = {"fp32": EDPC_FP32, "bf16": EDPC_BF16}[v]
-        if k in ("zero_head", "autotune", "lte", "low_rank"):
+        if k in ("zero_head", "autotune", "lte", "low_rank", "layerwise", "graphs"):
             bit = {"zero_head": EDPC_CFG_ZERO_HEAD, "autotune": EDPC_CFG_AUTOTUNE,
-                   "lte": EDPC_CFG_NO_LTE, "low_rank": EDPC_CFG_LOW_RANK}[k]
-            on = (not v) if k == "lte" else v
+                   "lte": EDPC_CFG_NO_LTE, "low_rank": EDPC_CFG_LOW_RANK,
+                   "layerwise": EDPC_CFG_LAYERWISE, "graphs": EDPC_CFG_NO_GRAPHS}[k]
+            # "lte" and "graphs" name the feature; their bits switch it off
+            on = (not v) if k in ("lte", "graphs") else v
             c.flags = (c.flags | bit) if on else (c.flags & ~bit)
             continue
         setattr(c, k, v)
@@ -356,6 +366,20 @@ class Model:
 
     def edpc_model_set_step(self, tau: int):
         _check(lib().edpc_model_set_step(self.h, tau))
+
+    def edpc_model_get_state(self) -> bytes:
+        """The whole training state as one blob (layout in include/edpc.h)."""
+        n = ctypes.c_size_t()
+        st = lib().edpc_model_get_state(self.h, None, 0, ctypes.byref(n))
+        if st != -3:
+            _check(st)
+        buf = np.empty(n.value, dtype=np.uint8)
+        _check(lib().edpc_model_get_state(self.h, _np_ptr(buf), buf.size, ctypes.byref(n)))
+        return buf.tobytes()
+
+    def edpc_model_set_state(self, blob: bytes):
+        buf = np.frombuffer(bytes(blob), dtype=np.uint8)
+        _check(lib().edpc_model_set_state(self.h, _np_ptr(buf), buf.size))
 
 
 def edpc_model_create(cfg: edpc_config, n_slots: int, max_rows: int) -> Model:

@@ -375,10 +375,68 @@ static float* tensor_ptr(Model& m, uint32_t kind, size_t idx, size_t* numel, boo
   fail(EDPC_E_INVALID_ARG, "tensor index out of range");
 }
 
+}  // extern "C"
+
+namespace {
+float bf16_widen(uint16_t h) {
+  const uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+// The BF16 operand copy of shared tensor idx, widened, in its own layout.
+void read_operand(Model& m, uint32_t kind, size_t idx, float* h_dst, size_t numel) {
+  if (!m.bf16) fail(EDPC_E_INVALID_ARG, "FP32 models keep no operand copies");
+  if (idx >= m.tens.size()) fail(EDPC_E_INVALID_ARG, "only shared tensors have operand copies");
+  const TensorInfo& t = m.tens[idx];
+  if (numel != t.numel) fail(EDPC_E_INVALID_ARG, "numel mismatch");
+  hip_check(hipDeviceSynchronize(), "sync");
+  if (!m.kc.fused) {
+    std::vector<uint16_t> h(t.numel);
+    hip_check(hipMemcpy(h.data(), m.p16 + t.off, t.numel * 2, hipMemcpyDeviceToHost), "copy");
+    for (size_t i = 0; i < t.numel; ++i) h_dst[i] = bf16_widen(h[i]);
+    return;
+  }
+  for (const Model::FragMat& fm : m.frag_mats) {
+    const size_t size = (size_t)fm.rows * fm.cols;
+    if (t.off < fm.off || t.off >= fm.off + size) continue;
+    // the tensor is rows [r0, r0 + numel / cols) of the matrix
+    const size_t r0 = (t.off - fm.off) / fm.cols, nrow = t.numel / fm.cols;
+    std::vector<uint16_t> f(size);
+    const uint4* src = kind == EDPC_KIND_OPERAND_NT ? fm.nt : fm.nn;
+    hip_check(hipMemcpy(f.data(), src, size * 2, hipMemcpyDeviceToHost), "copy");
+    // fragment (nb, kb) of KB k-blocks, lane l, element v (layouts in fused.h)
+    for (size_t q = 0; q < size; ++q) {
+      const size_t frag = q / 512, l = (q / 8) % 64, v = q % 8;
+      size_t r, c;
+      if (kind == EDPC_KIND_OPERAND_NT) {
+        const size_t KB = fm.cols / 32, nb = frag / KB, kb = frag % KB;
+        r = nb * 16 + l % 16;
+        c = kb * 32 + 8 * (l / 16) + v;
+      } else {
+        const size_t KB = fm.rows / 32, nb = frag / KB, kb = frag % KB;
+        r = kb * 32 + 8 * (l / 16) + v;
+        c = nb * 16 + l % 16;
+      }
+      if (r >= r0 && r < r0 + nrow) h_dst[(r - r0) * fm.cols + c] = bf16_widen(f[q]);
+    }
+    return;
+  }
+  fail(EDPC_E_INVALID_ARG, "tensor " + t.name + " has no operand copy in the fused step");
+}
+}  // namespace
+
+extern "C" {
+
 edpc_status edpc_model_read(const edpc_model* mh, uint32_t kind, size_t idx, float* h_dst,
                             size_t numel) {
   return guarded([&] {
     if (!mh || !h_dst) fail(EDPC_E_INVALID_ARG, "NULL argument");
+    if (kind == EDPC_KIND_OPERAND_NT || kind == EDPC_KIND_OPERAND_NN) {
+      read_operand(*mh->m, kind, idx, h_dst, numel);
+      return EDPC_OK;
+    }
     size_t ne = 0;
     float* p = tensor_ptr(*mh->m, kind, idx, &ne, false);
     if (numel != ne) fail(EDPC_E_INVALID_ARG, "numel mismatch");
@@ -448,6 +506,150 @@ edpc_status edpc_model_set_step(edpc_model* mh, uint64_t tau) {
   if (!mh) return set_err(EDPC_E_INVALID_ARG, "NULL model");
   mh->m->tau = tau;
   return EDPC_OK;
+}
+
+// ---------------------------------------------------------------- whole state
+
+}  // extern "C"
+
+namespace {
+struct BlobWriter {
+  uint8_t* p;
+  size_t cap, n = 0;
+  void put(const void* src, size_t k) {
+    if (p && n + k <= cap) std::memcpy(p + n, src, k);
+    n += k;
+  }
+  void u32(uint32_t v) { put(&v, 4); }
+  void u64(uint64_t v) { put(&v, 8); }
+};
+struct BlobReader {
+  const uint8_t* p;
+  size_t len, n = 0;
+  const uint8_t* take(size_t k) {
+    if (k > len - n) fail(EDPC_E_INVALID_ARG, "state blob truncated");
+    const uint8_t* q = p + n;
+    n += k;
+    return q;
+  }
+  uint32_t u32() { uint32_t v; std::memcpy(&v, take(4), 4); return v; }
+  uint64_t u64() { uint64_t v; std::memcpy(&v, take(8), 8); return v; }
+};
+constexpr uint32_t kStateVersion = 1;
+
+void cfg_words(const edpc_config& c, uint32_t w[9]) {
+  const uint32_t v[9] = {c.context, c.embed, c.latent, c.blocks, c.hidden, c.branches,
+                         c.cdf_bits, c.precision, c.flags};
+  std::memcpy(w, v, sizeof(v));
+}
+
+size_t n_tensors(const Model& m) { return m.tens.size() + (m.low_rank ? 3 : 1); }
+std::string tensor_name(const Model& m, size_t i) {
+  if (i < m.tens.size()) return m.tens[i].name;
+  if (i == m.tens.size()) return "U";
+  return i == m.tens.size() + 1 ? "A" : "B";
+}
+}  // namespace
+
+extern "C" {
+
+edpc_status edpc_model_get_state(const edpc_model* mh, void* h_buf, size_t cap, size_t* len) {
+  return guarded([&] {
+    if (!mh || !mh->m || !len) fail(EDPC_E_INVALID_ARG, "NULL argument");
+    Model& m = *mh->m;
+    // size first: the blob is written only when it fits
+    BlobWriter sz{nullptr, 0};
+    const size_t nt = n_tensors(m);
+    sz.n = 4 + 4 + 4 + 4 + 8 + 9 * 4 + 8;
+    for (size_t i = 0; i < nt; ++i) {
+      size_t ne = 0;
+      (void)tensor_ptr(m, EDPC_KIND_PARAM, i, &ne, false);
+      sz.n += 4 + ((tensor_name(m, i).size() + 3) & ~(size_t)3) + 8 + 3 * ne * sizeof(float);
+    }
+    *len = sz.n;
+    if (!h_buf || cap < sz.n) fail(EDPC_E_CAPACITY, "state buffer too small");
+    hip_check(hipDeviceSynchronize(), "sync");
+    BlobWriter w{(uint8_t*)h_buf, cap};
+    w.put("EDPS", 4);
+    w.u32(kStateVersion);
+    w.u32((uint32_t)nt);
+    w.u32(0);
+    w.u64(m.tau);
+    uint32_t cw[9];
+    cfg_words(m.cfg, cw);
+    for (uint32_t v : cw) w.u32(v);
+    w.u64(m.n_slots);
+    for (size_t i = 0; i < nt; ++i) {
+      const std::string nm = tensor_name(m, i);
+      w.u32((uint32_t)nm.size());
+      const size_t padded = (nm.size() + 3) & ~(size_t)3;
+      std::string pad = nm;
+      pad.resize(padded, '\0');
+      w.put(pad.data(), padded);
+      size_t ne = 0;
+      (void)tensor_ptr(m, EDPC_KIND_PARAM, i, &ne, false);
+      w.u64(ne);
+      for (uint32_t kind : {EDPC_KIND_PARAM, EDPC_KIND_ADAM_M, EDPC_KIND_ADAM_V}) {
+        const float* src = tensor_ptr(m, kind, i, &ne, false);
+        hip_check(hipMemcpy((uint8_t*)h_buf + w.n, src, ne * sizeof(float), hipMemcpyDeviceToHost),
+                  "copy");
+        w.n += ne * sizeof(float);
+      }
+    }
+    return EDPC_OK;
+  });
+}
+
+edpc_status edpc_model_set_state(edpc_model* mh, const void* h_buf, size_t len) {
+  return guarded([&] {
+    if (!mh || !mh->m || !h_buf) fail(EDPC_E_INVALID_ARG, "NULL argument");
+    Model& m = *mh->m;
+    BlobReader r{(const uint8_t*)h_buf, len};
+    if (std::memcmp(r.take(4), "EDPS", 4) != 0) fail(EDPC_E_INVALID_ARG, "not a state blob");
+    if (r.u32() != kStateVersion) fail(EDPC_E_INVALID_ARG, "state blob version");
+    const uint32_t nt = r.u32();
+    (void)r.u32();
+    const uint64_t tau = r.u64();
+    uint32_t cw[9];
+    cfg_words(m.cfg, cw);
+    for (uint32_t v : cw)
+      if (r.u32() != v) fail(EDPC_E_INVALID_ARG, "state blob of another model configuration");
+    if (r.u64() != m.n_slots) fail(EDPC_E_INVALID_ARG, "state blob of another slot count");
+    if (nt != n_tensors(m)) fail(EDPC_E_INVALID_ARG, "state blob tensor count");
+    // validate the whole blob before writing anything
+    struct Part { size_t idx; const uint8_t* data; size_t ne; };
+    std::vector<Part> parts;
+    for (size_t i = 0; i < nt; ++i) {
+      const uint32_t nl = r.u32();
+      const uint8_t* nm = r.take((nl + 3) & ~(uint32_t)3);
+      if (std::string((const char*)nm, nl) != tensor_name(m, i))
+        fail(EDPC_E_INVALID_ARG, "state blob tensor name");
+      size_t ne = 0;
+      (void)tensor_ptr(m, EDPC_KIND_PARAM, i, &ne, false);
+      if (r.u64() != ne) fail(EDPC_E_INVALID_ARG, "state blob tensor size");
+      if (ne > (len - r.n) / (3 * sizeof(float))) fail(EDPC_E_INVALID_ARG, "state blob truncated");
+      parts.push_back(Part{i, r.take(3 * ne * sizeof(float)), ne});
+    }
+    if (r.n != len) fail(EDPC_E_INVALID_ARG, "state blob has trailing bytes");
+    hip_check(hipDeviceSynchronize(), "sync");
+    for (const Part& pt : parts) {
+      int q = 0;
+      for (uint32_t kind : {EDPC_KIND_PARAM, EDPC_KIND_ADAM_M, EDPC_KIND_ADAM_V}) {
+        size_t ne = 0;
+        float* dst = tensor_ptr(m, kind, pt.idx, &ne, true);
+        hip_check(hipMemcpy(dst, pt.data + (size_t)q * ne * sizeof(float), ne * sizeof(float),
+                            hipMemcpyHostToDevice), "copy");
+        ++q;
+      }
+    }
+    if (m.bf16) {  // operand copies of the products follow the FP32 master
+      k_to_bf16(m.param, m.p16, m.P, nullptr);
+      if (m.kc.fused) m.build_frags(nullptr);
+    }
+    hip_check(hipDeviceSynchronize(), "sync");
+    m.tau = tau;
+    return EDPC_OK;
+  });
 }
 
 // ---------------------------------------------------------------- coder only

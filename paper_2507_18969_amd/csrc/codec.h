@@ -30,6 +30,7 @@ constexpr uint16_t kFormatVersion = 1;
 constexpr uint32_t kArch = 950;
 constexpr size_t kHeaderFixed = 92;
 constexpr size_t kPerStream = 20;
+constexpr int kGraphSteps = 32;  // steps per captured window of a session
 
 struct Header {
   edpc_config cfg;
@@ -37,6 +38,7 @@ struct Header {
   uint32_t arch;
   std::vector<uint64_t> lens, pay_lens;
   std::vector<uint32_t> crcs;
+  uint64_t total_len = 0, total_pay = 0;  // sums of lens / pay_lens (checked)
   size_t header_len;
 };
 

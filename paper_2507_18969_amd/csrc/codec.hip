@@ -72,7 +72,8 @@ edpc_status parse_header(const uint8_t* p, size_t len, Header* h, size_t* need, 
   if (std::memcmp(p, "EDPC", 4) != 0) { *err = "bad magic"; return EDPC_E_CORRUPT; }
   if (rd16(p + 4) != kFormatVersion) { *err = "unsupported format version"; return EDPC_E_UNSUPPORTED; }
   const uint32_t hl = rd32(p + 8), n = rd32(p + 12);
-  if ((uint64_t)hl != kHeaderFixed + (uint64_t)kPerStream * n + 4 || n == 0) {
+  if (n == 0 || n > EDPC_MAX_STREAMS) { *err = "stream count out of range"; return EDPC_E_CORRUPT; }
+  if ((uint64_t)hl != kHeaderFixed + (uint64_t)kPerStream * n + 4) {
     *err = "inconsistent header length";
     return EDPC_E_CORRUPT;
   }
@@ -95,24 +96,43 @@ edpc_status parse_header(const uint8_t* p, size_t len, Header* h, size_t* need, 
   h->lens.resize(n);
   h->pay_lens.resize(n);
   h->crcs.resize(n);
+  // Each length is bounded before any arithmetic on it (2 len + 2 cannot
+  // wrap), and the totals are summed with overflow checks, so that no later
+  // offset computed from the header can leave the caller's buffers.
+  uint64_t total = 0, pay_total = 0;
   for (uint32_t s = 0; s < n; ++s) {
     const uint8_t* q = p + kHeaderFixed + kPerStream * s;
     h->lens[s] = rd64(q);
     h->pay_lens[s] = rd64(q + 8);
     h->crcs[s] = rd32(q + 16);
+    if (h->lens[s] > EDPC_MAX_STREAM_LEN) {
+      *err = "stream length out of range";
+      return EDPC_E_CORRUPT;
+    }
     if (h->pay_lens[s] > 2 * h->lens[s] + 2 || (h->lens[s] == 0) != (h->pay_lens[s] == 0)) {
       *err = "payload length out of range";
       return EDPC_E_CORRUPT;
     }
+    if (__builtin_add_overflow(total, h->lens[s], &total) ||
+        __builtin_add_overflow(pay_total, h->pay_lens[s], &pay_total)) {
+      *err = "stream lengths overflow";
+      return EDPC_E_CORRUPT;
+    }
   }
+  h->total_len = total;
+  h->total_pay = pay_total;
   h->header_len = hl;
   return EDPC_OK;
 }
 
 size_t encode_bound(const edpc_config& cfg, const uint64_t* lens, size_t n) {
   (void)cfg;
+  if (n > EDPC_MAX_STREAMS) fail(EDPC_E_INVALID_ARG, "too many streams");
   size_t b = kHeaderFixed + kPerStream * n + 4;
-  for (size_t s = 0; s < n; ++s) b += 2 * lens[s] + 2;
+  for (size_t s = 0; s < n; ++s) {
+    if (lens[s] > EDPC_MAX_STREAM_LEN) fail(EDPC_E_INVALID_ARG, "stream longer than EDPC_MAX_STREAM_LEN");
+    b += 2 * lens[s] + 2;
+  }
   return b;
 }
 
@@ -246,8 +266,7 @@ static void common_setup(Session& ss, const KernelConfig* kc) {
   ss.io.off = ss.d_off;
   ss.io.lens = ss.d_lens;
   ss.next = std::min<uint64_t>(ss.cfg.context, ss.maxlen);
-  const char* env = std::getenv("EDPC_GRAPH_STEPS");
-  ss.graph_steps = env ? std::max(0, std::atoi(env)) : 32;
+  ss.graph_steps = (ss.cfg.flags & EDPC_CFG_NO_GRAPHS) ? 0 : kGraphSteps;
 }
 
 std::unique_ptr<Session> encoder_begin(const edpc_config& cfg, const uint8_t* d_in,
@@ -255,9 +274,9 @@ std::unique_ptr<Session> encoder_begin(const edpc_config& cfg, const uint8_t* d_
                                        const KernelConfig* kc) {
   Model::validate(cfg);
   if (n == 0) fail(EDPC_E_INVALID_ARG, "n_streams must be >= 1");
-  if (n > (1u << 24)) fail(EDPC_E_INVALID_ARG, "too many streams");
+  if (n > EDPC_MAX_STREAMS) fail(EDPC_E_INVALID_ARG, "too many streams");
   for (size_t i = 0; i < n; ++i)
-    if (lens[i] > (1ull << 40)) fail(EDPC_E_INVALID_ARG, "stream too long");
+    if (lens[i] > EDPC_MAX_STREAM_LEN) fail(EDPC_E_INVALID_ARG, "stream longer than EDPC_MAX_STREAM_LEN");
   std::unique_ptr<Session> ss(new Session());
   ss->s = s;
   ss->cfg = cfg;
@@ -344,10 +363,10 @@ std::unique_ptr<Session> decoder_begin(const uint8_t* d_in, size_t in_len, uint8
   if (!KernelConfig::decode(h.kernel_id, &kc)) fail(EDPC_E_UNSUPPORTED, "unknown kernel configuration");
   Model::validate(h.cfg);
   const size_t n = h.lens.size();
-  uint64_t total = 0, pay_total = 0;
-  for (size_t i = 0; i < n; ++i) { total += h.lens[i]; pay_total += h.pay_lens[i]; }
-  if (h.header_len + pay_total > in_len) fail(EDPC_E_CORRUPT, "container truncated");
-  if (total > out_cap) fail(EDPC_E_CAPACITY, "output buffer too small");
+  // (parse_header bounded every length and checked both sums)
+  if (h.total_pay > in_len || h.header_len > in_len - h.total_pay)
+    fail(EDPC_E_CORRUPT, "container truncated");
+  if (h.total_len > out_cap) fail(EDPC_E_CAPACITY, "output buffer too small");
   std::unique_ptr<Session> ss(new Session());
   ss->decoding = true;
   ss->s = s;

@@ -34,6 +34,17 @@ struct AdamCfg {
   float lr, beta1, beta2, eps;
 };
 
+// Adam's bias correction 1 - beta^tau, formed as -expm1(tau log1p(beta - 1))
+// so that it keeps full FP32 relative accuracy at small tau (1 - powf loses
+// log2(1 / (1 - beta^tau)) bits to cancellation, about 8 bits at beta 0.999
+// and tau 3).  beta - 1 is exact in FP32 for beta in [0.5, 1]; beta = 0
+// gives 1.  tau = 0 (no update yet) gives 0.
+__device__ __forceinline__ float adam_bias_correction(float beta, uint32_t tau) {
+  if (tau == 0) return 0.0f;
+  if (beta <= 0.0f) return 1.0f;
+  return -expm1f((float)tau * log1pf(beta - 1.0f));
+}
+
 __device__ __forceinline__ float gelu_f(float x) {
   return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f));
 }

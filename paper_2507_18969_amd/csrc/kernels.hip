@@ -37,8 +37,8 @@ __global__ void __launch_bounds__(kScheduleThreads) step_schedule_kernel(StepSta
   st->model = step >= sc.context ? 1 : 0;
   const uint32_t tau = step >= sc.context ? (uint32_t)(step - sc.context + 1) : 0u;
   st->tau = tau;
-  st->bc1 = 1.0f - powf(sc.beta1, (float)tau);
-  st->bc2 = 1.0f - powf(sc.beta2, (float)tau);
+  st->bc1 = adam_bias_correction(sc.beta1, tau);
+  st->bc2 = adam_bias_correction(sc.beta2, tau);
 }
 
 void k_step_schedule(StepState* st, Schedule sc, int step, hipStream_t s) {
@@ -61,8 +61,8 @@ __global__ void step_explicit_kernel(StepState* st, int rows, uint32_t tau, floa
   st->inv_rows = rows > 0 ? 1.0f / (float)rows : 0.0f;
   st->model = 1;
   st->tau = tau;
-  st->bc1 = 1.0f - powf(beta1, (float)tau);
-  st->bc2 = 1.0f - powf(beta2, (float)tau);
+  st->bc1 = adam_bias_correction(beta1, tau);
+  st->bc2 = adam_bias_correction(beta2, tau);
 }
 
 void k_step_explicit(StepState* st, int rows, uint32_t tau, float beta1, float beta2,

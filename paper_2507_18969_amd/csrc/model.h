@@ -37,7 +37,7 @@ enum ProductSlot : int {
 
 // Kernel configuration: one tile id per product slot, plus the numerics
 // revision of the kernels.  Encoded into 64 bits for the container.
-constexpr uint32_t kNumericsRevision = 2;
+constexpr uint32_t kNumericsRevision = 3;
 struct KernelConfig {
   int tile[PS_COUNT];
   bool fused = false;  // BF16 row-block fused step (bit 47 of the id)
@@ -163,6 +163,15 @@ struct Model {
   int b1_blocks = 0;
   float* b1_partial = nullptr;
   void build_frags(hipStream_t s) { k_build_frags(d_frag_jobs, n_frag_jobs, total_frags, s); }
+  // matrices with fragment copies: element offset in the flat buffers, shape
+  // and the two copies (for read-back)
+  struct FragMat {
+    size_t off;
+    int rows, cols;
+    const uint4* nt;
+    const uint4* nn;
+  };
+  std::vector<FragMat> frag_mats;
   std::vector<void*> allocs;
 
   Model(const edpc_config& c, size_t n_slots, size_t max_rows, const KernelConfig* kc);

@@ -103,7 +103,8 @@ void Model::validate(const edpc_config& c) {
   if (c.branches < 1 || c.branches > 3) fail(EDPC_E_INVALID_ARG, "branches must be 1..3");
   if (c.cdf_bits != 16) fail(EDPC_E_INVALID_ARG, "only 16-bit CDFs are supported");
   if (c.precision != EDPC_FP32 && c.precision != EDPC_BF16) fail(EDPC_E_INVALID_ARG, "unknown precision");
-  if (c.flags & ~(EDPC_CFG_ZERO_HEAD | EDPC_CFG_AUTOTUNE | EDPC_CFG_NO_LTE | EDPC_CFG_LOW_RANK))
+  if (c.flags & ~(EDPC_CFG_ZERO_HEAD | EDPC_CFG_AUTOTUNE | EDPC_CFG_NO_LTE | EDPC_CFG_LOW_RANK |
+                  EDPC_CFG_LAYERWISE | EDPC_CFG_NO_GRAPHS))
     fail(EDPC_E_INVALID_ARG, "unknown config flags");
   if ((c.flags & EDPC_CFG_NO_LTE) && (c.flags & EDPC_CFG_LOW_RANK))
     fail(EDPC_E_INVALID_ARG, "EDPC_CFG_NO_LTE and EDPC_CFG_LOW_RANK exclude each other");
@@ -155,11 +156,10 @@ KernelConfig Model::default_config(const edpc_config& c, size_t rows) {
   }
   k.tile[PS_WGRAD] = pick_tile(rows, wg, 512);
   // BF16 shapes with a row-block kernel take the fused step (one workgroup per
-  // 16 rows runs LTE up .. head .. coder .. adjoint); EDPC_FUSED=0 in the
-  // encoder's environment selects the layer-by-layer products instead.  The
-  // row-block kernels index activations with 32-bit offsets.
-  const char* env = std::getenv("EDPC_FUSED");
-  k.fused = !(env && env[0] == '0') && c.precision == EDPC_BF16 && rows <= (1u << 20) &&
+  // 16 rows runs LTE up .. head .. coder .. adjoint) unless EDPC_CFG_LAYERWISE
+  // asks for the layer-by-layer products.  The row-block kernels index
+  // activations with 32-bit offsets.
+  k.fused = !(c.flags & EDPC_CFG_LAYERWISE) && c.precision == EDPC_BF16 && rows <= (1u << 20) &&
             !(c.flags & (EDPC_CFG_NO_LTE | EDPC_CFG_LOW_RANK)) &&
             fused_supported(F, L, H, (int)c.branches, (int)c.blocks);
   return k;
@@ -473,6 +473,7 @@ void Model::setup_fused(hipStream_t s) {
   for (auto& j : jobs) {
     j.nt = frags + (size_t)j.nt;
     j.nn = frags + (size_t)j.nn;
+    frag_mats.push_back(FragMat{(size_t)(j.src - param), j.rows, j.cols, j.nt, j.nn});
   }
   n_frag_jobs = (int)jobs.size();
   total_frags = fr;

@@ -23,7 +23,9 @@ def lib_cfg(E, model: dict, precision: str = "fp32", **over):
                             "beta1", "beta2", "eps", "seed") if k in d}
     return E.edpc_config_default(precision=precision, zero_head=d.get("zero_head", False),
                                  autotune=d.get("autotune", False), lte=d.get("lte", True),
-                                 low_rank=d.get("low_rank", False), **kw)
+                                 low_rank=d.get("low_rank", False),
+                                 layerwise=d.get("layerwise", False),
+                                 graphs=d.get("graphs", True), **kw)
 
 
 def oracle_cfg(model: dict, **over) -> Config:

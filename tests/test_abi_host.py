@@ -25,7 +25,7 @@ def test_exports_every_declared_symbol():
     assert declared == set(E.EXPORTS)
     for name in declared:
         assert hasattr(L, name), name
-    assert L.edpc_abi_version() == 1
+    assert L.edpc_abi_version() == 2
 
 
 def test_host_coder_matches_oracle_coder():
@@ -92,7 +92,7 @@ def test_encode_bound():
         E.edpc_encode_bound(c, [])
 
 
-def _header(lens, pay_lens, crcs, cfg=None, version=1, kernel=2 << 48, arch=950):
+def _header(lens, pay_lens, crcs, cfg=None, version=1, kernel=3 << 48, arch=950):
     """Container header written from the documented layout (independent of
     the library's writer)."""
     c = cfg or E.edpc_config_default()
@@ -137,3 +137,50 @@ def test_decode_info_rejects_version_and_bad_lengths():
     with pytest.raises(E.EdpcError) as ei:  # non-empty payload for an empty stream
         E.edpc_decode_info(_header([0], [2], [0]))
     assert ei.value.status == -4
+
+
+def test_decode_info_rejects_lengths_beyond_the_codec_limits():
+    # crafted headers with valid CRCs: lengths whose arithmetic would wrap
+    # (2 * len + 2, the sums of lengths) must be reported as corrupt before
+    # any offset is formed from them
+    big = E.EDPC_MAX_STREAM_LEN
+    cfg, lens, _, total = E.edpc_decode_info(_header([big, 3], [12, 4], [0, 0]))
+    assert list(lens) == [big, 3] and total == big + 3
+    for lens_, pays in (([big + 1], [8]), ([1 << 63], [8]), ([(1 << 64) - 1], [2]),
+                        ([5, 1 << 62], [4, 4])):
+        with pytest.raises(E.EdpcError) as ei:
+            E.edpc_decode_info(_header(lens_, pays, [0] * len(lens_)))
+        assert ei.value.status == -4, (lens_, pays)
+    # payload length that wraps 2 * len + 2
+    with pytest.raises(E.EdpcError) as ei:
+        E.edpc_decode_info(_header([1 << 63], [(1 << 64) - 1], [0]))
+    assert ei.value.status == -4
+
+
+def test_decode_info_rejects_stream_count_beyond_limit():
+    # only the fixed part is given: the count is refused before the header
+    # length (which would be 20 bytes per stream) is consulted
+    h = bytearray(_header([4], [3], [0]))
+    struct.pack_into("<II", h, 8, 96 + 20 * (E.EDPC_MAX_STREAMS + 1), E.EDPC_MAX_STREAMS + 1)
+    with pytest.raises(E.EdpcError) as ei:
+        E.edpc_decode_info(bytes(h[:96]))
+    assert ei.value.status == -4
+
+
+def test_encode_bound_rejects_overlong_streams():
+    c = E.edpc_config_default()
+    assert E.edpc_encode_bound(c, [E.EDPC_MAX_STREAM_LEN]) == 96 + 20 + 2 * E.EDPC_MAX_STREAM_LEN + 2
+    with pytest.raises(E.EdpcError) as ei:
+        E.edpc_encode_bound(c, [E.EDPC_MAX_STREAM_LEN + 1])
+    assert ei.value.status == -1
+
+
+def test_config_flags_for_launch_choices():
+    # the launch sequence and graph replay are configuration bits, not
+    # environment settings
+    c = E.edpc_config_default(precision="bf16", layerwise=True, graphs=False)
+    assert c.flags & E.EDPC_CFG_LAYERWISE and c.flags & E.EDPC_CFG_NO_GRAPHS
+    E.edpc_config_validate(c)
+    c.flags |= 0x40
+    with pytest.raises(E.EdpcError):
+        E.edpc_config_validate(c)

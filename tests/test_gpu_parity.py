@@ -86,7 +86,8 @@ def test_initial_parameters_bit_identical(E):
     assert np.array_equal(m.edpc_model_read("U"), init_fdm(oracle_cfg(SMALL), range(8)).reshape(-1))
 
 
-def _step_case(E, model, precision, rows, pos, om_steps=0, n_slots=None, prefix=None, wl="small"):
+def _step_case(E, model, precision, rows, pos, om_steps=0, n_slots=None, prefix=None, wl="small",
+               **over):
     data, lens = gen.make_streams(wl, prefix=prefix or (pos + 1), n_streams=rows)
     st = np.frombuffer(data.tobytes(), dtype=np.uint8).reshape(rows, -1)
     C = model["context"]
@@ -96,7 +97,7 @@ def _step_case(E, model, precision, rows, pos, om_steps=0, n_slots=None, prefix=
     for i in range(C, C + om_steps):
         om.step(st[:, i - C:i].astype(np.int64), st[:, i].astype(np.int64), np.arange(rows))
     om.round_to_f32()
-    cfg = lib_cfg(E, model, precision)
+    cfg = lib_cfg(E, model, precision, **over)
     m = E.Model(cfg, n_slots or rows, rows)
     if om_steps:
         load_oracle_state(m, om)
@@ -203,22 +204,20 @@ def test_one_step_fp32_ragged_rows_and_slots(E):
 
 @pytest.mark.parametrize("fused", ["1", "0"])
 @pytest.mark.parametrize("om_steps", [0, 1008])
-def test_one_step_bf16_small(E, monkeypatch, fused, om_steps):
+def test_one_step_bf16_small(E, fused, om_steps):
     # BF16 row-block fused step (default) and layer-by-layer products, from the
     # initial state and from the oracle's state at position 1024
-    monkeypatch.setenv("EDPC_FUSED", fused)
     om, m, ctx, tgt = _step_case(E, SMALL, "bf16", rows=8, pos=16 + om_steps, om_steps=om_steps,
-                                 prefix=16 + om_steps + 1)
+                                 prefix=16 + om_steps + 1, layerwise=fused == "0")
     _compare_step(E, om, m, ctx, tgt, p_tol=2e-3, g_rtol=3e-2)
 
 
 @pytest.mark.parametrize("precision,fused", [("bf16", "1"), ("bf16", "0"), ("fp32", "0")])
-def test_one_step_mid_ragged_row_blocks(E, monkeypatch, precision, fused):
+def test_one_step_mid_ragged_row_blocks(E, precision, fused):
     # mid model (F = 512, L = 128, H = 256): 40 rows = two full 16-row blocks
     # and a ragged one, after 8 oracle steps
-    monkeypatch.setenv("EDPC_FUSED", fused)
     om, m, ctx, tgt = _step_case(E, MID, precision, rows=40, pos=40, prefix=41, om_steps=8,
-                                  wl="mid_bf16")
+                                  wl="mid_bf16", layerwise=fused == "0")
     if precision == "fp32":
         _compare_step(E, om, m, ctx, tgt, p_tol=1e-5, g_rtol=1e-4)
     else:
@@ -343,7 +342,7 @@ def test_autotuned_encode_roundtrip(E):
     cfg = lib_cfg(E, SMALL, autotune=True)
     cont = _encode(E, cfg, data, lens)
     kid = int.from_bytes(cont[76:84].cpu().numpy().tobytes(), "little")
-    assert kid >> 48 == 2  # numerics revision
+    assert kid >> 48 == 3  # numerics revision
     out, _ = E.edpc_decode(cont)
     assert out.cpu().numpy().tobytes() == data.tobytes()
 
@@ -357,40 +356,46 @@ def test_bf16_roundtrip_and_size_vs_fp32(E):
     assert abs(c16.numel() - c32.numel()) / c32.numel() <= 0.005
 
 
-def test_graph_replay_matches_direct_launches(E, monkeypatch):
+def _without_graph_flag(cont):
+    """The container with the EDPC_CFG_NO_GRAPHS bit of its configuration
+    cleared (header CRC recomputed), so that payloads can be compared."""
+    import struct
+    import zlib
+    b = bytearray(cont.cpu().numpy().tobytes())
+    hl = struct.unpack_from("<I", b, 8)[0]
+    flags = struct.unpack_from("<I", b, 48)[0]
+    struct.pack_into("<I", b, 48, flags & ~0x20)
+    struct.pack_into("<I", b, hl - 4, zlib.crc32(bytes(b[:hl - 4])))
+    return bytes(b)
+
+
+def test_graph_replay_matches_direct_launches(E):
     # same input through captured step windows and through direct launches:
-    # identical containers, and each decodes in the other mode
+    # identical payloads, and each container decodes
     data, lens = gen.make_streams("small", prefix=400, n_streams=8)
     lens = np.array([400, 400, 399, 250, 130, 129, 64, 17])
     st = split_streams(data, [400] * 8)
     flat = np.frombuffer(b"".join(s[:l] for s, l in zip(st, lens)), dtype=np.uint8)
-    cfg = lib_cfg(E, SMALL)
-    monkeypatch.setenv("EDPC_GRAPH_STEPS", "0")
-    direct = _encode(E, cfg, flat, lens)
-    monkeypatch.setenv("EDPC_GRAPH_STEPS", "16")
-    graph = _encode(E, cfg, flat, lens)
-    graph2 = _encode(E, cfg, flat, lens)
-    assert torch.equal(direct, graph) and torch.equal(graph, graph2)
-    out, _ = E.edpc_decode(direct)
-    assert out.cpu().numpy().tobytes() == flat.tobytes()
-    monkeypatch.setenv("EDPC_GRAPH_STEPS", "0")
-    out, _ = E.edpc_decode(graph)
-    assert out.cpu().numpy().tobytes() == flat.tobytes()
+    direct = _encode(E, lib_cfg(E, SMALL, graphs=False), flat, lens)
+    graph = _encode(E, lib_cfg(E, SMALL), flat, lens)
+    graph2 = _encode(E, lib_cfg(E, SMALL), flat, lens)
+    assert torch.equal(graph, graph2)
+    assert _without_graph_flag(direct) == graph.cpu().numpy().tobytes()
+    for cont in (direct, graph):
+        out, _ = E.edpc_decode(cont)
+        assert out.cpu().numpy().tobytes() == flat.tobytes()
 
 
-def test_fused_and_layerwise_containers_decode_either_way(E, monkeypatch):
-    # the container records which BF16 step encoded it; the decoder follows
-    # the container whatever its own environment says
+def test_fused_and_layerwise_containers_decode(E):
+    # the container records which BF16 step encoded it (bit 47 of the kernel
+    # configuration id); the decoder follows the container
     data, lens = gen.make_streams("small", prefix=300, n_streams=8)
-    cfg = lib_cfg(E, SMALL, "bf16")
     conts = {}
     for fused in ("1", "0"):
-        monkeypatch.setenv("EDPC_FUSED", fused)
-        conts[fused] = _encode(E, cfg, data, lens)
+        conts[fused] = _encode(E, lib_cfg(E, SMALL, "bf16", layerwise=fused == "0"), data, lens)
         kid = int.from_bytes(conts[fused][76:84].cpu().numpy().tobytes(), "little")
         assert (kid >> 47) & 1 == int(fused)
     for fused, cont in conts.items():
-        monkeypatch.setenv("EDPC_FUSED", "0" if fused == "1" else "1")
         out, _ = E.edpc_decode(cont)
         assert out.cpu().numpy().tobytes() == data.tobytes()
     assert abs(conts["1"].numel() - conts["0"].numel()) / conts["0"].numel() <= 0.005

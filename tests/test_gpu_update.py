@@ -1,0 +1,244 @@
+"""GPU parity of the BF16 update step: one Adam step (Sec. 4.1) on the mean
+cross entropy (Eq. 2), taken by the launch sequence the encoder runs, from
+an oracle state, checked element by element against the oracle's own step.
+
+What is compared, per shared tensor and for the FDM slices U_s of the rows:
+
+* the gradient the update consumed (read back after the update: the weight
+  gradients of the products summed over all rows, and the bias, LayerNorm
+  and embedding gradients the fused Adam kernel forms from per-row-block
+  partials) against the oracle's FP64 adjoint, within 3e-2 of the tensor's
+  largest entry (BF16 operands; the bound of the one-step gradient tests);
+* the FP32 master, first and second moments against the oracle's Adam step
+  (constants as the configuration carries them, in FP32).  The bound is
+  derived, not chosen: with the oracle's gradient g and the
+  GPU's g + d, |d| <= e (e = 3e-2 max|g|, the gradient bound), the moments
+  move by at most (1 - b1) e and (1 - b2)(2|g| e + e^2), and the update
+  lr/bc1 * m / (sqrt(v / bc2) + eps) is increasing in m and decreasing in v,
+  so the GPU's parameter lies between the updates at the corners of that
+  box (plus FP32 rounding);
+* the BF16 operand copies the next step's products read (the two
+  fragment-ordered copies of the row-block step, or the layer-by-layer
+  shadow) against the round-to-nearest-even BF16 value of the new master:
+  bit-exact;
+* as an invariant of the update itself, the new master and moments against
+  Adam applied to the gradient the GPU reports (FP32 rounding only).
+"""
+
+import numpy as np
+import pytest
+
+import gen
+from oracle.model import Model as OModel
+from tests.gpu_util import banner, lib_cfg, load_oracle_state, oracle_cfg
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+SMALL = gen.WORKLOADS["small"].model
+MID = gen.WORKLOADS["mid_fp32"].model
+G_RTOL = 3e-2
+F32 = 2.0 ** -23
+
+
+@pytest.fixture(scope="module")
+def E():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2507_18969_amd as E
+    E.lib()
+    return E
+
+
+@pytest.fixture(autouse=True)
+def _name(request):
+    banner(request.node.nodeid)
+
+
+def _dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=torch.uint8)
+
+
+def bf16_rne(x):
+    """Round FP32 values to BF16 (nearest, ties to even), widened back."""
+    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32)
+
+
+def _consts(cfg, tau):
+    """Adam constants as the configuration carries them (FP32 values), with
+    the bias corrections 1 - beta^tau."""
+    b1, b2, lr, eps = (float(np.float32(x)) for x in (cfg.beta1, cfg.beta2, cfg.lr, cfg.eps))
+    return b1, b2, lr, eps, 1.0 - b1 ** tau, 1.0 - b2 ** tau
+
+
+def _u_slack(u_terms):
+    """FP32 rounding of the update lr/bc1 * m / (sqrt(v / bc2) + eps): the
+    bias corrections are each within a few ulps (formed as -expm1(tau
+    log1p(beta - 1)), no cancellation), and the quotients, product and square
+    root add half an ulp each; m = b1 m0 + (1 - b1) g itself carries an
+    absolute rounding error of an ulp of its terms, which can cancel.  So the
+    bound is 16 ulps of the update formed from |b1 m0| + |(1 - b1) g|."""
+    return np.abs(u_terms) * (F32 * 16)
+
+
+def _u_terms(lr, bc1, bc2, eps, b1, m0, g, v):
+    return lr / bc1 * (np.abs(b1 * m0) + (1.0 - b1) * np.abs(g)) / (np.sqrt(v / bc2) + eps)
+
+
+def _adam_box(cfg, tau, theta0, m0, v0, g, e):
+    """Interval of the Adam step's results when the gradient is g +- e."""
+    b1, b2, lr, eps, bc1, bc2 = _consts(cfg, tau)
+    m = b1 * m0 + (1.0 - b1) * g
+    v = b2 * v0 + (1.0 - b2) * g * g
+    dm = (1.0 - b1) * e
+    dv = (1.0 - b2) * (2.0 * np.abs(g) * e + e * e)
+    us = []
+    for mc in (m - dm, m + dm):
+        for vc in (np.maximum(v - dv, 0.0), v + dv):
+            us.append(lr / bc1 * mc / (np.sqrt(vc / bc2) + eps))
+    us = np.stack(us)
+    ut = _u_terms(lr, bc1, bc2, eps, b1, m0, np.abs(g) + e, np.maximum(v - dv, 0.0))
+    return m, dm, v, dv, theta0 - us.max(0), theta0 - us.min(0), _u_slack(ut)
+
+
+def _check_box(name, got_p, got_m, got_v, theta0, box):
+    m, dm, v, dv, lo, hi, us = box
+    rm = F32 * 4 * (np.abs(m) + dm) + 1e-30
+    rv = F32 * 4 * (np.abs(v) + dv) + 1e-30
+    assert np.all(np.abs(got_m - m) <= dm + rm), (name, "m", np.abs(got_m - m).max())
+    assert np.all(np.abs(got_v - v) <= dv + rv), (name, "v", np.abs(got_v - v).max())
+    slack = F32 * 2 * np.abs(theta0) + us + 1e-12
+    assert np.all(got_p >= lo - slack) and np.all(got_p <= hi + slack), (
+        name, "param", float(np.max(np.maximum(lo - slack - got_p, got_p - hi - slack))))
+
+
+def _check_own_adam(name, cfg, tau, theta0, m0, v0, g, got_p, got_m, got_v):
+    """The update is Adam of the gradient the GPU reports (FP32 rounding)."""
+    b1, b2, lr, eps, bc1, bc2 = _consts(cfg, tau)
+    g = g.astype(np.float64)
+    m = b1 * m0 + (1.0 - b1) * g
+    v = b2 * v0 + (1.0 - b2) * g * g
+    u = lr / bc1 * m / (np.sqrt(v / bc2) + eps)
+    assert np.all(np.abs(got_m - m) <= F32 * 4 * (np.abs(b1 * m0) + np.abs(g)) + 1e-30), (name, "m")
+    assert np.all(np.abs(got_v - v) <= F32 * 4 * (b2 * v0 + g * g) + 1e-30), (name, "v")
+    ut = _u_terms(lr, bc1, bc2, eps, b1, m0, g, v)
+    assert np.all(np.abs(got_p - (theta0 - u)) <= F32 * 2 * np.abs(theta0) + _u_slack(ut)
+                  + 1e-12), (name, "param", np.abs(got_p - (theta0 - u)).max())
+
+
+def _update_case(E, model, rows, om_steps, wl, layerwise=False, sample_rows=None):
+    C = model["context"]
+    pos = C + om_steps
+    data, _ = gen.make_streams(wl, prefix=pos + 1, n_streams=rows)
+    st = np.frombuffer(data.tobytes(), dtype=np.uint8).reshape(rows, -1)
+    ocfg = oracle_cfg(model)
+    om = OModel(ocfg, rows)
+    for i in range(C, pos):
+        om.step(st[:, i - C:i].astype(np.int64), st[:, i].astype(np.int64), np.arange(rows))
+    om.round_to_f32()
+    m = E.Model(lib_cfg(E, model, "bf16", layerwise=layerwise), rows, rows)
+    load_oracle_state(m, om)
+    ctx, tgt = st[:, pos - C:pos], st[:, pos]
+    slots = np.arange(rows)
+    c = om.forward(ctx.astype(np.int64), slots)
+    g_o, dU_o = om.backward(c, tgt.astype(np.int64))
+    theta0 = {k: om.p[k].copy() for k in om.p}
+    m0 = {k: om.m[k].copy() for k in om.p}
+    v0 = {k: om.v[k].copy() for k in om.p}
+    U0, mU0, vU0 = om.U.copy(), om.mU.copy(), om.vU.copy()
+    tau = om.tau + 1
+    m.edpc_model_step(_dev(ctx), _dev(tgt), slots, flags=E.EDPC_STEP_UPDATE)
+    torch.cuda.synchronize()
+    assert m.edpc_model_get_step() == tau
+    operand_checked = 0
+    for k in om.p:
+        g = g_o[k].reshape(-1)
+        e = G_RTOL * (np.abs(g).max() + 1e-30)
+        gg = m.edpc_model_read(k, kind=E.EDPC_KIND_GRAD)
+        assert np.abs(gg - g).max() <= e, (k, "grad", np.abs(gg - g).max() / e * G_RTOL)
+        p = m.edpc_model_read(k).astype(np.float64)
+        mm = m.edpc_model_read(k, kind=E.EDPC_KIND_ADAM_M).astype(np.float64)
+        vv = m.edpc_model_read(k, kind=E.EDPC_KIND_ADAM_V).astype(np.float64)
+        t0, mo, vo = theta0[k].reshape(-1), m0[k].reshape(-1), v0[k].reshape(-1)
+        _check_box(k, p, mm, vv, t0, _adam_box(ocfg, tau, t0, mo, vo, g, e))
+        _check_own_adam(k, ocfg, tau, t0, mo, vo, gg, p, mm, vv)
+        p32 = p.astype(np.float32)
+        for kind in (E.EDPC_KIND_OPERAND_NT, E.EDPC_KIND_OPERAND_NN):
+            try:
+                op = m.edpc_model_read(k, kind=kind)
+            except E.EdpcError:
+                assert not layerwise, k  # the layer-by-layer shadow covers every tensor
+                continue
+            assert np.array_equal(op.view(np.uint32), bf16_rne(p32).view(np.uint32)), (k, kind)
+            operand_checked += 1
+    assert operand_checked >= 2 * (3 + 2 * model["blocks"]) or layerwise
+    # FDM slices of (sampled) rows: Adam on U_s with the per-row gradient bound
+    U = m.edpc_model_read("U").reshape(om.U.shape).astype(np.float64)
+    mU = m.edpc_model_read("U", kind=E.EDPC_KIND_ADAM_M).reshape(om.U.shape).astype(np.float64)
+    vU = m.edpc_model_read("U", kind=E.EDPC_KIND_ADAM_V).reshape(om.U.shape).astype(np.float64)
+    rs = range(rows) if sample_rows is None else sample_rows
+    for r in rs:
+        e = G_RTOL * (np.abs(dU_o[r]).max() + 1e-30)
+        box = _adam_box(ocfg, tau, U0[r], mU0[r], vU0[r], dU_o[r], e)
+        _check_box(f"U[{r}]", U[r], mU[r], vU[r], U0[r], box)
+    return om, m
+
+
+def test_bf16_fused_update_small_one_row_block(E):
+    # small model (F = 256, L = 64, H = 128): 8 rows in one 16-row block,
+    # from the oracle's state after 24 steps
+    _update_case(E, SMALL, rows=8, om_steps=24, wl="small")
+
+
+@pytest.mark.parametrize("layerwise", [False, True])
+def test_bf16_update_mid_three_row_blocks(E, layerwise):
+    # 1024-stream model: 40 rows = two full 16-row blocks and a ragged one
+    _update_case(E, MID, rows=40, om_steps=8, wl="mid_bf16", layerwise=layerwise)
+
+
+def test_bf16_fused_update_mid_full_batch(E):
+    # the benchmarked launch: 1024 rows (64 row blocks, the gradient sums over
+    # all of them), from the oracle's state after 2 steps; U checked on
+    # sampled rows
+    sample = np.random.default_rng(17).choice(1024, size=16, replace=False)
+    _update_case(E, MID, rows=1024, om_steps=2, wl="mid_bf16", sample_rows=sample)
+
+
+def test_bf16_fused_one_block_model(E):
+    # the fused step with a single refinement block (Table 4 "one block" row)
+    model = dict(SMALL, blocks=1)
+    _update_case(E, model, rows=24, om_steps=8, wl="mid_bf16")
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp32"])
+def test_state_blob_moves_a_model(E, precision):
+    # the whole training state (parameters, Adam moments, step counter) as one
+    # blob: a fresh model given it continues exactly like the original
+    rows = 8
+    data, _ = gen.make_streams("small", prefix=64, n_streams=rows)
+    st = np.frombuffer(data.tobytes(), dtype=np.uint8).reshape(rows, -1)
+    cfg = lib_cfg(E, SMALL, precision)
+    a = E.Model(cfg, rows, rows)
+    slots = np.arange(rows)
+    for i in range(16, 20):
+        a.edpc_model_step(_dev(st[:, i - 16:i]), _dev(st[:, i]), slots, flags=E.EDPC_STEP_UPDATE)
+    blob = a.edpc_model_get_state()
+    b = E.Model(cfg, rows, rows)
+    b.edpc_model_set_state(blob)
+    assert b.edpc_model_get_step() == 4 and b.edpc_model_get_state() == blob
+    probs = []
+    for m in (a, b):
+        p = torch.empty((rows, 256), dtype=torch.float32, device="cuda")
+        m.edpc_model_step(_dev(st[:, 20:36]), _dev(st[:, 36]), slots, p, flags=E.EDPC_STEP_UPDATE)
+        torch.cuda.synchronize()
+        probs.append(p.cpu().numpy())
+    assert np.array_equal(probs[0], probs[1])
+    assert a.edpc_model_get_state() == b.edpc_model_get_state()
+    other = E.Model(lib_cfg(E, dict(SMALL, hidden=64), precision), rows, rows)
+    with pytest.raises(E.EdpcError) as ei:
+        other.edpc_model_set_state(blob)
+    assert ei.value.status == -1
+    with pytest.raises(E.EdpcError):
+        b.edpc_model_set_state(blob[:-4])
