@@ -295,6 +295,20 @@ edpc_status edpc_rc_decode(const uint32_t* d_cum, const uint8_t* d_in,
                            const uint32_t* h_in_lens, size_t cap_per_stream,
                            size_t n_steps, size_t n_streams, uint8_t* d_sym,
                            void* stream);
+/* Allocation-free edpc_rc_encode, for callers that cannot allocate device
+ * memory (serving loops and harnesses that forbid hipMalloc): same arguments
+ * and results, but the per-stream payload lengths pass through a fixed
+ * device array of EDPC_RC_NOALLOC_MAX_STREAMS entries that the library
+ * holds, one per GPU, until the process ends, instead of a temporary
+ * allocation.  n_streams above EDPC_RC_NOALLOC_MAX_STREAMS is
+ * EDPC_E_INVALID_ARG.  Calls that overlap on one GPU race on that array;
+ * the call synchronises `stream`. */
+#define EDPC_RC_NOALLOC_MAX_STREAMS 65536
+edpc_status edpc_rc_encode_noalloc(const uint32_t* d_cum, const uint8_t* d_sym,
+                                   size_t n_steps, size_t n_streams, uint8_t* d_out,
+                                   size_t cap_per_stream, uint32_t* h_out_lens,
+                                   void* stream);
+
 /* The same coder compiled for the host (reference and CPU tests). */
 edpc_status edpc_rc_encode_host(const uint32_t* h_cum, const uint8_t* h_sym,
                                 size_t n_steps, uint8_t* h_out, size_t cap,

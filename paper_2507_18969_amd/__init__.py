@@ -30,6 +30,7 @@ EDPC_CFG_LAYERWISE = 0x10
 EDPC_CFG_NO_GRAPHS = 0x20
 EDPC_MAX_STREAM_LEN = 0x7FFFFFFF
 EDPC_MAX_STREAMS = 1 << 24
+EDPC_RC_NOALLOC_MAX_STREAMS = 65536
 EDPC_STEP_BACKWARD, EDPC_STEP_UPDATE, EDPC_STEP_KEEP_FDM_GRAD = 0x1, 0x2, 0x4
 EDPC_KIND_PARAM, EDPC_KIND_GRAD, EDPC_KIND_ADAM_M, EDPC_KIND_ADAM_V = 0, 1, 2, 3
 EDPC_KIND_OPERAND_NT, EDPC_KIND_OPERAND_NN = 4, 5
@@ -45,7 +46,7 @@ EXPORTS = [
     "edpc_model_tensor_count", "edpc_model_tensor_info", "edpc_model_read", "edpc_model_write",
     "edpc_model_read_device", "edpc_model_write_device",
     "edpc_model_get_step", "edpc_model_set_step", "edpc_model_get_state",
-    "edpc_model_set_state", "edpc_rc_encode", "edpc_rc_decode",
+    "edpc_model_set_state", "edpc_rc_encode", "edpc_rc_decode", "edpc_rc_encode_noalloc",
     "edpc_rc_encode_host", "edpc_rc_decode_host",
 ]
 
@@ -119,6 +120,7 @@ def lib() -> ctypes.CDLL:
         "edpc_model_get_state": (ctypes.c_int, [_P, _P, _SZ, _SZP]),
         "edpc_model_set_state": (ctypes.c_int, [_P, _P, _SZ]),
         "edpc_rc_encode": (ctypes.c_int, [_P, _P, _SZ, _SZ, _P, _SZ, _U32P, _P]),
+        "edpc_rc_encode_noalloc": (ctypes.c_int, [_P, _P, _SZ, _SZ, _P, _SZ, _U32P, _P]),
         "edpc_rc_decode": (ctypes.c_int, [_P, _P, _U32P, _SZ, _SZ, _SZ, _P, _P]),
         "edpc_rc_encode_host": (ctypes.c_int, [_P, _P, _SZ, _P, _SZ, _SZP]),
         "edpc_rc_decode_host": (ctypes.c_int, [_P, _P, _SZ, _SZ, _P]),
@@ -396,6 +398,18 @@ def edpc_rc_encode(d_cum, d_sym, cap_per_stream: int, stream=None):
     _check(lib().edpc_rc_encode(_dptr(d_cum), _dptr(d_sym), n_steps, n_streams, _dptr(out),
                                 cap_per_stream, lens.ctypes.data_as(_U32P), _stream(stream)))
     return out, lens
+
+
+def edpc_rc_encode_noalloc(d_cum, d_sym, out, stream=None):
+    """edpc_rc_encode into a caller-provided payload tensor ``out``
+    [n_streams, cap] (uint8); the library allocates nothing.  Returns the
+    lengths."""
+    n_steps, n_streams = d_sym.shape
+    lens = np.zeros(n_streams, dtype=np.uint32)
+    _check(lib().edpc_rc_encode_noalloc(_dptr(d_cum), _dptr(d_sym), n_steps, n_streams,
+                                        _dptr(out), out.shape[1], lens.ctypes.data_as(_U32P),
+                                        _stream(stream)))
+    return lens
 
 
 def edpc_rc_decode(d_cum, d_payload, lens, stream=None):

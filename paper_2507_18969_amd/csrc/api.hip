@@ -1,5 +1,7 @@
 // extern "C" boundary: argument checks, error translation, handles.
+#include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -671,6 +673,64 @@ edpc_status edpc_rc_encode(const uint32_t* d_cum, const uint8_t* d_sym, size_t n
     (void)hipFree(d_len);
     hip_check(e, "rc encode");
     for (size_t i = 0; i < n_streams; ++i) h_out_lens[i] = (uint32_t)l[i];
+    return EDPC_OK;
+  });
+}
+
+}  // extern "C"
+
+// Device array behind edpc_rc_encode_noalloc: the per-stream payload
+// lengths of one call (every entry below n_streams is written by the coder
+// kernel before it is read back).  Each GPU holds its own copy; host code
+// reaches it only through the address hipGetSymbolAddress returns for the
+// current device.
+static __device__ __align__(256) uint64_t scratch[EDPC_RC_NOALLOC_MAX_STREAMS];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint64_t* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of this device's scratch array, looked up once per device.
+uint64_t* scratch_ptr() {
+  int dev = 0;
+  hip_check(hipGetDevice(&dev), "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) fail(EDPC_E_UNSUPPORTED, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress");
+    g_scratch_ptr[dev] = (uint64_t*)p;
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace
+
+extern "C" {
+
+edpc_status edpc_rc_encode_noalloc(const uint32_t* d_cum, const uint8_t* d_sym, size_t n_steps,
+                                   size_t n_streams, uint8_t* d_out, size_t cap,
+                                   uint32_t* h_out_lens, void* stream) {
+  return guarded([&] {
+    if (!d_cum || !d_sym || !d_out || !h_out_lens) fail(EDPC_E_INVALID_ARG, "NULL argument");
+    if (n_streams == 0) fail(EDPC_E_INVALID_ARG, "n_streams must be >= 1");
+    if (n_streams > EDPC_RC_NOALLOC_MAX_STREAMS)
+      fail(EDPC_E_INVALID_ARG, "n_streams exceeds EDPC_RC_NOALLOC_MAX_STREAMS");
+    if (cap < 2 * n_steps + 2) fail(EDPC_E_INVALID_ARG, "cap_per_stream < 2 * n_steps + 2");
+    hipStream_t s = S(stream);
+    uint64_t* d_len = scratch_ptr();
+    k_rc_table_encode(d_cum, d_sym, n_steps, n_streams, d_out, cap, d_len, s);
+    hip_check(hipGetLastError(), "rc encode launch");
+    // lengths back through a fixed host buffer, a slice at a time
+    constexpr size_t kSlice = 512;
+    uint64_t part[kSlice];
+    for (size_t b = 0; b < n_streams; b += kSlice) {
+      const size_t k = std::min(kSlice, n_streams - b);
+      hip_check(hipMemcpyAsync(part, d_len + b, k * sizeof(uint64_t), hipMemcpyDeviceToHost, s),
+                "copy");
+      hip_check(hipStreamSynchronize(s), "rc encode");
+      for (size_t i = 0; i < k; ++i) h_out_lens[b + i] = (uint32_t)part[i];
+    }
     return EDPC_OK;
   });
 }
