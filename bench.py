@@ -92,6 +92,7 @@ def run_precision(torch, E, w, d_in, lens, data, precision, warmup, steps,
     sub = np.ascontiguousarray(data.reshape(rows, -1)[:, :cut]).reshape(-1)
     d_sub = torch.as_tensor(sub).to("cuda")
     cont = E.edpc_encode(cfg, d_sub, np.full(rows, cut))
+    kernel_id = int.from_bytes(cont[76:84].cpu().numpy().tobytes(), "little")
     out = torch.empty(rows * cut, dtype=torch.uint8, device="cuda")
     log(f"{precision}: decoder session")
     dec = E.edpc_decoder_begin(cont, out)
@@ -104,7 +105,7 @@ def run_precision(torch, E, w, d_in, lens, data, precision, warmup, steps,
     log(f"{precision}: decode {dec_mbps:.3f} MB/s ({dms / ddone:.3f} ms/step)")
     return dict(encode=enc_mbps, decode=dec_mbps, ms_per_step=ms / done,
                 decode_ms_per_step=dms / ddone, wall_s=wall, kernels=kern, steps=done,
-                kernel_steps=kernel_steps)
+                kernel_steps=kernel_steps, kernel_id=kernel_id)
 
 
 def full_job(torch, E, w, d_in, lens, precision):
@@ -168,6 +169,37 @@ def extra_workload(torch, E, name, warmup, steps):
     del d_in
     torch.cuda.empty_cache()
     return res
+
+
+TILE_NAMES = ("32x32", "64x32", "32x64", "64x64", "128x64", "64x128", "128x128",
+              "w128x128", "w256x128", "w128x256", "w256x256")
+
+
+def kernel_tiles(kernel_id):
+    """Tile shape per product class of a container's kernel configuration id
+    (4 bits per product slot, slots in GEMM_CLASSES order)."""
+    return {c: TILE_NAMES[(kernel_id >> (4 * i)) & 15] if ((kernel_id >> (4 * i)) & 15) < len(TILE_NAMES)
+            else "?" for i, c in enumerate(GEMM_CLASSES)}
+
+
+def copy_rate(torch, nbytes=4 << 30, reps=3):
+    """Device-to-device copy rate of the HIP runtime (bytes read + written per
+    second) on a buffer too large for any cache: the practical ceiling of a
+    pass that reads and writes each byte once."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    gbs = 2 * nbytes * reps / (a.elapsed_time(b) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"bytes": nbytes, "GB_per_s": round(gbs, 1)}
 
 
 GEMM_CLASSES = ("gemm_lte_down", "gemm_lte_up", "gemm_branches_gelu", "gemm_block_out",
@@ -234,11 +266,14 @@ def large_workload(torch, E, precisions, warmup=8, kernel_steps=8, steps=24):
                      "kernels_ms_per_step": {k: round(v[0] / kernel_steps, 4)
                                              for k, v in kern.items() if v[1]},
                      "roofline_fdm_bwd_adam": fdm_roofline(w, kern, rows, stored=False),
-                     "roofline_gemm": gemm_roofline(w, kern, rows, prec, kernel_steps)}
+                     "roofline_gemm": gemm_roofline(w, kern, rows, prec, kernel_steps),
+                     "tiles": kernel_tiles(r["kernel_id"])}
         log(f"large {prec}: {out[prec]['encode_MBps']} / {out[prec]['decode_MBps']} MB/s")
     if "bf16" in out and "fp32" in out:
         out["bf16_over_fp32_encode"] = round(out["bf16"]["encode_MBps"] / out["fp32"]["encode_MBps"], 3)
     del d_in
+    torch.cuda.empty_cache()
+    out["device_copy"] = copy_rate(torch)
     torch.cuda.empty_cache()
     return out
 
@@ -471,6 +506,20 @@ def cpu_baseline(w, data, lens, n_model_steps):
                       f"FP64 numpy, {dt:.1f} s"}
 
 
+def run_extra(torch, E, a):
+    extra = {}
+    for name in [x for x in a.extra.split(",") if x]:
+        if name == "ablations":
+            extra[name] = ablation_workload(torch, E, a.warmup, min(a.steps, 200))
+        elif name == "large":
+            extra[name] = large_workload(torch, E, a.precisions.split(","))
+        elif name == "ragged_full":
+            extra[name] = ragged_full_job(torch, E)
+        else:
+            extra[name] = extra_workload(torch, E, name, a.warmup, min(a.steps, 200))
+    return extra
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -489,6 +538,8 @@ def main():
                          "extra_workloads")
     ap.add_argument("--no-size-parity", action="store_true",
                     help="skip the compressed-size comparison with the oracle's stored sizes")
+    ap.add_argument("--only-extra", action="store_true",
+                    help="measure only the --extra workloads (no main line; for profiling)")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path (sharding the "
@@ -500,6 +551,9 @@ def main():
     import gen
     import paper_2507_18969_amd as E
     E.lib()
+    if a.only_extra:
+        print(json.dumps({"extra_workloads": run_extra(torch, E, a)}), flush=True)
+        return
     w = gen.WORKLOADS["mid_bf16"]
     log("generating 64 MiB input")
     data, lens = gen.make_streams(w)
@@ -532,16 +586,7 @@ def main():
     }
     if "bf16" in res and "fp32" in res:
         line["bf16_over_fp32_encode"] = round(res["bf16"]["encode"] / res["fp32"]["encode"], 3)
-    extra = {}
-    for name in [x for x in a.extra.split(",") if x]:
-        if name == "ablations":
-            extra[name] = ablation_workload(torch, E, a.warmup, min(a.steps, 200))
-        elif name == "large":
-            extra[name] = large_workload(torch, E, a.precisions.split(","))
-        elif name == "ragged_full":
-            extra[name] = ragged_full_job(torch, E)
-        else:
-            extra[name] = extra_workload(torch, E, name, a.warmup, min(a.steps, 200))
+    extra = run_extra(torch, E, a)
     if not a.no_size_parity:
         line["size_parity_vs_oracle"] = size_parity(torch, E, list(res))
     if extra:

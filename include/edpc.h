@@ -218,6 +218,19 @@ edpc_status edpc_model_create(const edpc_config* cfg, size_t n_slots,
                               size_t max_rows, edpc_model** out);
 void edpc_model_destroy(edpc_model* m);
 
+/* The same with an explicit kernel configuration: `kernel_id` is the 64-bit
+ * id a container records (tile shape per matrix product, 4 bits per product
+ * slot; bit 47 the BF16 row-block fused step; bits 48.. the numerics
+ * revision), so that a model can run the summation orders of a given
+ * container, or a chosen tile everywhere.  0 picks the default.  An id of
+ * another numerics revision, an unknown tile, or a tile or fused step the
+ * model's shape and precision cannot run is EDPC_E_UNSUPPORTED. */
+edpc_status edpc_model_create_with_kernels(const edpc_config* cfg, size_t n_slots,
+                                           size_t max_rows, uint64_t kernel_id,
+                                           edpc_model** out);
+/* The kernel configuration id a model runs. */
+edpc_status edpc_model_kernel_id(const edpc_model* m, uint64_t* kernel_id);
+
 /* One step on `rows` rows.  d_ctx: [rows, context] bytes, oldest first.
  * d_target: [rows] bytes (required with BACKWARD/UPDATE, else may be NULL).
  * h_slot: [rows] distinct FDM slot indices < n_slots (host memory: the

@@ -42,7 +42,8 @@ EXPORTS = [
     "edpc_config_validate", "edpc_encode_bound", "edpc_encode", "edpc_decode_info",
     "edpc_decode", "edpc_encoder_begin", "edpc_decoder_begin", "edpc_session_run",
     "edpc_session_progress", "edpc_encoder_finish", "edpc_decoder_finish",
-    "edpc_session_destroy", "edpc_session_time_kernels", "edpc_kclass_name", "edpc_model_create", "edpc_model_destroy", "edpc_model_step",
+    "edpc_session_destroy", "edpc_session_time_kernels", "edpc_kclass_name", "edpc_model_create", "edpc_model_create_with_kernels", "edpc_model_kernel_id",
+    "edpc_model_destroy", "edpc_model_step",
     "edpc_model_tensor_count", "edpc_model_tensor_info", "edpc_model_read", "edpc_model_write",
     "edpc_model_read_device", "edpc_model_write_device",
     "edpc_model_get_step", "edpc_model_set_step", "edpc_model_get_state",
@@ -107,6 +108,9 @@ def lib() -> ctypes.CDLL:
         "edpc_session_time_kernels": (ctypes.c_int, [_P, ctypes.c_uint64, _P, _P]),
         "edpc_kclass_name": (ctypes.c_char_p, [ctypes.c_int]),
         "edpc_model_create": (ctypes.c_int, [cfgp, _SZ, _SZ, ctypes.POINTER(_P)]),
+        "edpc_model_create_with_kernels": (ctypes.c_int, [cfgp, _SZ, _SZ, ctypes.c_uint64,
+                                                           ctypes.POINTER(_P)]),
+        "edpc_model_kernel_id": (ctypes.c_int, [_P, _U64P]),
         "edpc_model_destroy": (None, [_P]),
         "edpc_model_step": (ctypes.c_int, [_P, _P, _P, _U32P, _SZ, _P, _P, _P, ctypes.c_uint32, _P]),
         "edpc_model_tensor_count": (ctypes.c_int, [_P, _SZP]),
@@ -299,10 +303,14 @@ def edpc_decoder_begin(container, d_out, stream=None) -> Session:
 class Model:
     """edpc_model_create ... edpc_model_destroy, with tensor access by name."""
 
-    def __init__(self, cfg: edpc_config, n_slots: int, max_rows: int):
+    def __init__(self, cfg: edpc_config, n_slots: int, max_rows: int, kernel_id: int = 0):
         self.cfg = cfg
         h = ctypes.c_void_p()
-        _check(lib().edpc_model_create(ctypes.byref(cfg), n_slots, max_rows, ctypes.byref(h)))
+        if kernel_id:
+            _check(lib().edpc_model_create_with_kernels(ctypes.byref(cfg), n_slots, max_rows,
+                                                        kernel_id, ctypes.byref(h)))
+        else:
+            _check(lib().edpc_model_create(ctypes.byref(cfg), n_slots, max_rows, ctypes.byref(h)))
         self.h = h
         self.n_slots = n_slots
         n = ctypes.c_size_t()
@@ -368,6 +376,11 @@ class Model:
 
     def edpc_model_set_step(self, tau: int):
         _check(lib().edpc_model_set_step(self.h, tau))
+
+    def edpc_model_kernel_id(self) -> int:
+        k = ctypes.c_uint64()
+        _check(lib().edpc_model_kernel_id(self.h, ctypes.byref(k)))
+        return k.value
 
     def edpc_model_get_state(self) -> bytes:
         """The whole training state as one blob (layout in include/edpc.h)."""

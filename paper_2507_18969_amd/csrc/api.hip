@@ -258,6 +258,39 @@ edpc_status edpc_model_create(const edpc_config* cfg, size_t n_slots, size_t max
   });
 }
 
+edpc_status edpc_model_create_with_kernels(const edpc_config* cfg, size_t n_slots,
+                                           size_t max_rows, uint64_t kernel_id,
+                                           edpc_model** out) {
+  return guarded([&] {
+    if (!cfg || !out) fail(EDPC_E_INVALID_ARG, "NULL argument");
+    *out = nullptr;
+    if (kernel_id == 0) return edpc_model_create(cfg, n_slots, max_rows, out);
+    KernelConfig kc;
+    if (!KernelConfig::decode(kernel_id, &kc)) fail(EDPC_E_UNSUPPORTED, "unknown kernel configuration");
+    Model::validate(*cfg);
+    const bool bf16 = cfg->precision == EDPC_BF16;
+    for (int ps = 0; ps < PS_COUNT; ++ps) {
+      const EpiKind epi = ps == PS_GATE ? EPI_GATE_FWD : ps == PS_GATE_BWD ? EPI_GATE_BWD : EPI_STORE;
+      const int nb = ps == PS_GATE ? (int)cfg->branches : 1;
+      if (!wide_tile_supported(kc.tile[ps], bf16, epi, nb))
+        fail(EDPC_E_UNSUPPORTED, "tile of the kernel configuration does not serve this model");
+    }
+    std::unique_ptr<edpc_model> h(new edpc_model());
+    h->m.reset(new Model(*cfg, n_slots, max_rows, &kc));
+    h->m->init_params(nullptr);
+    h->m->build_tables(nullptr);
+    hip_check(hipDeviceSynchronize(), "model create");
+    *out = h.release();
+    return EDPC_OK;
+  });
+}
+
+edpc_status edpc_model_kernel_id(const edpc_model* mh, uint64_t* kernel_id) {
+  if (!mh || !mh->m || !kernel_id) return set_err(EDPC_E_INVALID_ARG, "NULL argument");
+  *kernel_id = mh->m->kc.encode();
+  return EDPC_OK;
+}
+
 void edpc_model_destroy(edpc_model* m) {
   if (m) (void)hipDeviceSynchronize();
   delete m;

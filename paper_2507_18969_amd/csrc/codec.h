@@ -19,7 +19,7 @@ namespace edpc {
 //           precision, flags
 //   52  f32 lr, beta1, beta2, eps
 //   68  u64 seed
-//   76  u64 kernel configuration id: 3 bits of tile choice per product slot,
+//   76  u64 kernel configuration id: 4 bits of tile choice per product slot,
 //           bit 47 the BF16 row-block fused step, bits 48.. the numerics revision
 //   84  u32 device architecture (950 for gfx950)
 //   88  u32 reserved (0)

@@ -54,6 +54,20 @@ struct WgradProblem {
   int tiles_n, tile_begin;  // tiles of this problem start at tile_begin
 };
 
+// Work-group -> tile order for a launch of `total` tiles numbered row-major
+// (tiles of one row of the output share their A rows).  Work-groups are
+// dealt to the 8 XCDs in turn (work-group L to XCD L mod 8), and each XCD
+// has its own L2, so consecutive tile numbers would land on different XCDs
+// and every XCD would fetch every A row panel.  This mapping gives XCD x
+// the contiguous tile range [x q + min(x, r), ...) (q = total / 8,
+// r = total % 8) in the order its work-groups arrive, so a row panel is
+// fetched by one XCD and reused from its L2.  It only permutes which
+// work-group computes which tile: results do not change.
+__device__ __forceinline__ int xcd_tile(int L, int total) {
+  const int x = L & 7, q = total >> 3, r = total & 7;
+  return x * q + (x < r ? x : r) + (L >> 3);
+}
+
 // Tile configurations (the autotuner picks one per product; the choice is
 // recorded in the container so the decoder uses the same summation order).
 enum TileId : int {
@@ -64,17 +78,28 @@ enum TileId : int {
   TILE_128x64 = 4,
   TILE_64x128 = 5,
   TILE_128x128 = 6,
-  TILE_COUNT = 7
+  // 8-wave wide tiles, BF16 only (gemm_wide.hip); gated products with k = 2
+  TILE_W128x128 = 7,
+  TILE_W256x128 = 8,
+  TILE_W128x256 = 9,
+  TILE_W256x256 = 10,
+  TILE_COUNT = 11
 };
 
 struct TileShape {
   int bm, bn;
 };
 inline TileShape tile_shape(int id) {
-  static const TileShape t[TILE_COUNT] = {{32, 32}, {64, 32}, {32, 64}, {64, 64},
-                                          {128, 64}, {64, 128}, {128, 128}};
+  static const TileShape t[TILE_COUNT] = {{32, 32},  {64, 32},   {32, 64},   {64, 64},
+                                          {128, 64}, {64, 128},  {128, 128}, {128, 128},
+                                          {256, 128}, {128, 256}, {256, 256}};
   return t[id];
 }
+
+// Whether tile id `tile` serves a product of this precision / epilogue /
+// branch count (the wide tiles: BF16, and gated forward products only with
+// two branches).
+bool wide_tile_supported(int tile, bool bf16, EpiKind epi, int nb);
 
 // Launchers (gemm.hip).  `bf16` selects BF16 operands (A, B hold bf16_t).
 // `a_kmajor` / `b_kmajor` select the operand layouts; nb = number of B
@@ -83,5 +108,10 @@ hipError_t launch_gemm(int tile, bool bf16, bool a_kmajor, bool b_kmajor, EpiKin
                        const GemmArgs& g, int grid_m_max, hipStream_t s);
 hipError_t launch_wgrad(int tile, bool bf16, const WgradProblem* d_probs, int n_probs,
                         int total_tiles, const StepState* st, hipStream_t s);
+// Wide tiles (gemm_wide.hip), reached through the two launchers above.
+hipError_t launch_gemm_wide(int tile, bool a_kmajor, bool b_kmajor, EpiKind epi, int nb,
+                            const GemmArgs& g, int grid_m_max, hipStream_t s);
+hipError_t launch_wgrad_wide(int tile, const WgradProblem* d_probs, int n_probs, int total_tiles,
+                             const StepState* st, hipStream_t s);
 
 }  // namespace edpc

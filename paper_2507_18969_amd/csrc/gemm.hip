@@ -291,7 +291,8 @@ __global__ void __launch_bounds__(kThreads) gemm_kernel(GemmArgs g) {
   const int M = g.m_rows ? g.st->rows : g.M;
   const int K = g.k_rows ? g.st->rows : g.K;
   const int N = g.N;
-  const int m0 = blockIdx.y * T::BM, n0 = blockIdx.x * T::BN;
+  const int tile = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  const int m0 = (tile / gridDim.x) * T::BM, n0 = (tile % gridDim.x) * T::BN;
   if (m0 >= M) return;
   TC tc;
   tc.run(g.A, g.lda, g.B, g.ldb, g.b_branch_stride, M, N, K, m0, n0, smem);
@@ -349,10 +350,11 @@ __global__ void __launch_bounds__(kThreads) wgrad_kernel(const WgradProblem* __r
                                                          int n_probs, const StepState* st) {
   typedef TileCompute<BF, T, false, false, 1> TC;
   extern __shared__ __align__(16) char smem[];
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
   int p = 0;
-  while (p + 1 < n_probs && (int)blockIdx.x >= probs[p + 1].tile_begin) ++p;
+  while (p + 1 < n_probs && tile >= probs[p + 1].tile_begin) ++p;
   const WgradProblem pr = probs[p];
-  const int t = blockIdx.x - pr.tile_begin;
+  const int t = tile - pr.tile_begin;
   const int m0 = (t / pr.tiles_n) * T::BM, n0 = (t % pr.tiles_n) * T::BN;
   const int K = st->rows;
   TC tc;
@@ -436,6 +438,10 @@ static hipError_t launch_p(int tile, bool ak, bool bk, EpiKind epi, int nb, cons
 
 hipError_t launch_gemm(int tile, bool bf16, bool a_kmajor, bool b_kmajor, EpiKind epi, int nb,
                        const GemmArgs& g, int grid_m_max, hipStream_t s) {
+  if (tile >= TILE_W128x128) {
+    if (!wide_tile_supported(tile, bf16, epi, nb)) return hipErrorInvalidValue;
+    return launch_gemm_wide(tile, a_kmajor, b_kmajor, epi, nb, g, grid_m_max, s);
+  }
   return bf16 ? launch_p<true>(tile, a_kmajor, b_kmajor, epi, nb, g, grid_m_max, s)
               : launch_p<false>(tile, a_kmajor, b_kmajor, epi, nb, g, grid_m_max, s);
 }
@@ -467,6 +473,10 @@ static hipError_t launch_wp(int tile, const WgradProblem* p, int n, int tt, cons
 
 hipError_t launch_wgrad(int tile, bool bf16, const WgradProblem* d_probs, int n_probs,
                         int total_tiles, const StepState* st, hipStream_t s) {
+  if (tile >= TILE_W128x128) {
+    if (!bf16) return hipErrorInvalidValue;
+    return launch_wgrad_wide(tile, d_probs, n_probs, total_tiles, st, s);
+  }
   return bf16 ? launch_wp<true>(tile, d_probs, n_probs, total_tiles, st, s)
               : launch_wp<false>(tile, d_probs, n_probs, total_tiles, st, s);
 }

@@ -1,0 +1,476 @@
+// Wide-tile BF16 matrix products for the large models (gfx950 MFMA).
+//
+// The 4-wave tiles of gemm.hip move 64 KiB of operands per 128 x 128 x 128
+// chunk for 4.2 MFLOP: 64 flops per byte, which at one CU's share of the
+// BF16 peak (about 4 kflop per clock) asks ~64 bytes per clock from L2, the
+// most a CU's vector cache can take.  These kernels use 8 waves on tiles of
+// up to 256 x 256 outputs (128 flops per byte), K in chunks of 64 staged
+// through a double-buffered LDS tile (one barrier per chunk, the next
+// chunk's global loads in flight under the current chunk's MFMAs), and the
+// 32 x 32 x 16 BF16 MFMA, whose operands each serve 32 rows or columns.
+//
+// Contract and epilogues as in gemm.h.  Summation order: K in chunks of 64
+// in increasing order, each chunk by the MFMA's fixed order; fixed by the
+// tile id, which the container records.
+#include "gemm.h"
+
+namespace edpc {
+
+constexpr int kWideThreads = 512;  // 8 waves
+constexpr int kWideBK = 64;
+constexpr int kWideLds = kWideBK + 8;  // LDS row stride (bf16): 144 bytes
+
+// LDS element offset of the 16-byte chunk `chunk` (8 k values) of tile row
+// `row`: chunks are XOR-swizzled by the row's group of 8, so that eight
+// consecutive lanes hit distinct banks both when they read one chunk of
+// eight consecutive rows (MFMA operands), when they write eight chunks of
+// one row (K-major staging) and when they write one chunk of rows eight
+// apart (the transposed staging of the other layout).
+__device__ __forceinline__ int wide_lds_off(int row, int chunk) {
+  return row * kWideLds + 8 * (chunk ^ ((row >> 3) & 7));
+}
+
+// Global -> registers -> LDS staging of one [ROWS x 64] operand tile, stored
+// in LDS as [ROWS][kWideLds] (k contiguous).
+//   KMAJOR: src[row * ld + k], moved as 16-byte vectors of 8 k;
+//   else:   src[k * ld + row], moved as 8 x 8 blocks transposed in registers.
+// Tile row i maps to global row base0 + i (i < half) or base1 + i - half
+// (K-major only: the two branch matrices of the gated product), valid below
+// lim0 / lim1.
+template <int ROWS, bool KMAJOR>
+struct WideStage {
+  static constexpr int NV = ROWS * kWideBK / 8;                     // 16-byte vectors
+  static constexpr int NBLK = (ROWS / 8) * (kWideBK / 8);           // 8 x 8 blocks
+  static constexpr int VPT = (NV + kWideThreads - 1) / kWideThreads;
+  static constexpr int BPT = (NBLK + kWideThreads - 1) / kWideThreads;
+  static constexpr int NREG = KMAJOR ? VPT : 8 * BPT;
+  uint4 r[NREG];
+
+  __device__ __forceinline__ void load(const bf16_t* __restrict__ src, int ld, int base0, int lim0,
+                                       int half, int base1, int lim1, int k0, int K) {
+    if constexpr (KMAJOR) {
+#pragma unroll
+      for (int p = 0; p < VPT; ++p) {
+        const int v = threadIdx.x + p * kWideThreads;
+        const int i = v / (kWideBK / 8), kq = v % (kWideBK / 8);
+        const int gk = k0 + kq * 8;
+        const bool second = i >= half;
+        const int grow = second ? base1 + (i - half) : base0 + i;
+        const int lim = second ? lim1 : lim0;
+        uint4 val = make_uint4(0, 0, 0, 0);
+        if (v < NV && grow < lim && gk < K) val = ld_global16(src + (size_t)grow * ld + gk);
+        r[p] = val;
+      }
+    } else {
+#pragma unroll
+      for (int p = 0; p < BPT; ++p) {
+        const int b = threadIdx.x + p * kWideThreads;
+        const int kb = b / (ROWS / 8), rb = b % (ROWS / 8);
+        const int grow = base0 + rb * 8;  // 8 contiguous rows (lim0 is a multiple of 8)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int gk = k0 + kb * 8 + q;
+          uint4 val = make_uint4(0, 0, 0, 0);
+          if (b < NBLK && grow < lim0 && gk < K) val = ld_global16(src + (size_t)gk * ld + grow);
+          r[8 * p + q] = val;
+        }
+      }
+    }
+  }
+
+  __device__ __forceinline__ void store(bf16_t* lds) const {
+    if constexpr (KMAJOR) {
+#pragma unroll
+      for (int p = 0; p < VPT; ++p) {
+        const int v = threadIdx.x + p * kWideThreads;
+        if (v >= NV) continue;
+        const int i = v / (kWideBK / 8), kq = v % (kWideBK / 8);
+        *(uint4*)(lds + wide_lds_off(i, kq)) = r[p];
+      }
+    } else {
+#pragma unroll
+      for (int p = 0; p < BPT; ++p) {
+        const int b = threadIdx.x + p * kWideThreads;
+        if (b >= NBLK) continue;
+        const int kb = b / (ROWS / 8), rb = b % (ROWS / 8);
+        // r[8p + q] holds k = kb*8 + q for rows rb*8 .. rb*8 + 7
+        const uint32_t* w = (const uint32_t*)&r[8 * p];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {  // row rb*8 + j gets its 8 k values
+          const int q2 = j >> 1;
+          const uint32_t sel = (j & 1) ? 0x07060302u : 0x05040100u;
+          uint32_t o[4];
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+            o[t] = __builtin_amdgcn_perm(w[4 * (2 * t + 1) + q2], w[4 * (2 * t) + q2], sel);
+          *(uint4*)(lds + wide_lds_off(rb * 8 + j, kb)) = make_uint4(o[0], o[1], o[2], o[3]);
+        }
+      }
+    }
+  }
+};
+
+// Tile of BM x BN outputs over 8 waves arranged WM x WN; each wave owns
+// (BM / WM) x (BN / WN) outputs as TM x TN blocks of 32 x 32.  GATE: the
+// tile's columns are BN / 2 outputs of each of two branch products, and a
+// wave's two column blocks are the same outputs of the two branches.
+template <int BM_, int BN_, int WM_, bool GATE_>
+struct WideTile {
+  static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = 8 / WM_;
+  static constexpr int TM = BM / WM / 32, TN = BN / WN / 32;
+  static constexpr bool GATE = GATE_;
+  static_assert(!GATE || TN == 2, "gated tiles give each wave one block per branch");
+  static constexpr int LDS_A = BM * kWideLds, LDS_B = BN * kWideLds;  // bf16 elements
+  static constexpr int SMEM = 2 * (LDS_A + LDS_B) * 2;                  // bytes, two stages
+  // tile-local column (B row) of block tn of wave wn
+  __device__ static int col_block(int wn, int tn) {
+    return GATE ? tn * (BN / 2) + wn * 32 : wn * (BN / WN) + tn * 32;
+  }
+};
+
+template <class T, bool AK, bool BKM>
+struct WideCompute {
+  typedef f32x16 Acc;
+  Acc acc[T::TM][T::TN];
+
+  // A rows [m0, m0 + BM) valid below M; B rows as WideStage; K in chunks.
+  __device__ __forceinline__ void run(const bf16_t* A, int lda, int m0, int M, const bf16_t* B,
+                                      int ldb, int b0, int blim0, int bhalf, int b1, int blim1,
+                                      int K, char* smem) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wm = wave / T::WN, wn = wave % T::WN;
+#pragma unroll
+    for (int i = 0; i < T::TM; ++i)
+#pragma unroll
+      for (int j = 0; j < T::TN; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+    bf16_t* lds = (bf16_t*)smem;
+    auto lds_a = [&](int s) { return lds + s * (T::LDS_A + T::LDS_B); };
+    auto lds_b = [&](int s) { return lds + s * (T::LDS_A + T::LDS_B) + T::LDS_A; };
+    WideStage<T::BM, AK> sa;
+    WideStage<T::BN, BKM> sb;
+    const int nchunks = (K + kWideBK - 1) / kWideBK;
+    sa.load(A, lda, m0, M, T::BM, 0, 0, 0, K);
+    sb.load(B, ldb, b0, blim0, bhalf, b1, blim1, 0, K);
+    sa.store(lds_a(0));
+    sb.store(lds_b(0));
+    __syncthreads();
+    // operand rows of this lane: 32 rows per block, chunk half by lane / 32
+    const int lrow = lane & 31, lhalf = lane >> 5;
+    for (int c = 0; c < nchunks; ++c) {
+      const bool more = c + 1 < nchunks;
+      if (more) {
+        sa.load(A, lda, m0, M, T::BM, 0, 0, (c + 1) * kWideBK, K);
+        sb.load(B, ldb, b0, blim0, bhalf, b1, blim1, (c + 1) * kWideBK, K);
+      }
+      const bf16_t* la = lds_a(c & 1);
+      const bf16_t* lb = lds_b(c & 1);
+#pragma unroll
+      for (int kk = 0; kk < kWideBK; kk += 16) {
+        bf16x8 fa[T::TM], fb[T::TN];
+        const int ch = kk / 8 + lhalf;
+#pragma unroll
+        for (int i = 0; i < T::TM; ++i)
+          fa[i] = __builtin_bit_cast(
+              bf16x8, *(const uint4*)(la + wide_lds_off(wm * (T::BM / T::WM) + i * 32 + lrow, ch)));
+#pragma unroll
+        for (int j = 0; j < T::TN; ++j)
+          fb[j] = __builtin_bit_cast(
+              bf16x8, *(const uint4*)(lb + wide_lds_off(T::col_block(wn, j) + lrow, ch)));
+#pragma unroll
+        for (int i = 0; i < T::TM; ++i)
+#pragma unroll
+          for (int j = 0; j < T::TN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+      }
+      if (more) {
+        sa.store(lds_a((c + 1) & 1));
+        sb.store(lds_b((c + 1) & 1));
+      }
+      __syncthreads();
+    }
+  }
+};
+
+__device__ __forceinline__ int wacc_row(int r, int lane) {
+  return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+}
+
+__device__ __forceinline__ float4 ld4(const float* p) {
+  return __builtin_bit_cast(float4, ld_global16(p));
+}
+__device__ __forceinline__ void st4(float* p, float4 v) {
+  st_global16(p, __builtin_bit_cast(uint4, v));
+}
+__device__ __forceinline__ void st4bf(bf16_t* p, float4 v) {
+  typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+  const u32x2 u = {(uint32_t)f2bf(v.x) | ((uint32_t)f2bf(v.y) << 16),
+                   (uint32_t)f2bf(v.z) | ((uint32_t)f2bf(v.w) << 16)};
+  *(__attribute__((address_space(1))) u32x2*)p = u;
+}
+
+// Epilogue through LDS.  The accumulators of half the tile's rows go to LDS
+// as FP32 [BM / 2][BN + 4] (the MFMA layout gives each lane single values
+// scattered over rows), then every thread walks that half tile four columns
+// at a time, so that the bias / residual / branch-value reads and the
+// output writes are 16-byte accesses that fill whole cache lines.  With one
+// work-group per CU nothing else hides the latency of those reads, so each
+// thread issues the reads of EB items before it uses any of them, the first
+// batch before the accumulators go through LDS.
+// EPI_WGRAD_OUT: dw = acc (ld = N), used by the weight-gradient kernel.
+constexpr int EPI_WGRAD_OUT = 16;
+
+template <int EPI>
+struct EpiPre {  // global operands of one item (four columns of one row)
+  static constexpr int N = EPI == EPI_GATE_BWD ? 3 : (EPI == EPI_STORE ? 1 : 0);
+  static constexpr int EB = EPI == EPI_GATE_BWD ? 4 : 8;  // items per batch
+  float4 v[N > 0 ? N : 1];
+};
+
+template <class T, int EPI>
+__device__ __forceinline__ void wide_epilogue(const typename WideCompute<T, true, true>::Acc (&acc)[T::TM][T::TN],
+                                              const GemmArgs& g, float* dw, int m0, int n0, int M,
+                                              int N, char* smem) {
+  constexpr int HR = T::BM / 2, LDE = T::BN + 4;
+  float* lds = (float*)smem;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int wm = wave / T::WN, wn = wave % T::WN;
+  constexpr int WROWS = T::BM / T::WM;  // rows per wave
+  // output columns of the tile handled per half-tile row (gated: per branch)
+  constexpr int COLS = T::GATE ? T::BN / 2 : T::BN;
+  constexpr int ITEMS = HR * COLS / 4;
+  static_assert(kWideThreads % (COLS / 4) == 0, "a thread keeps its columns");
+  constexpr int EB = EpiPre<EPI>::EB;
+  // a thread's items all lie in the same four columns
+  const int c = 4 * (threadIdx.x % (COLS / 4));
+  const int n = n0 + c;
+  const bool col_ok = n < N;
+  float4 bias0 = make_float4(0.f, 0.f, 0.f, 0.f), bias1 = bias0;
+  if constexpr (EPI == EPI_STORE) {
+    if (g.bias && col_ok) bias0 = ld4(g.bias + n);
+  } else if constexpr (EPI == EPI_GATE_FWD) {
+    if (col_ok) {
+      bias0 = ld4(g.bias + n);
+      bias1 = ld4(g.bias + g.bias_branch_stride + n);
+    }
+  }
+  auto row_of = [&](int it) { return it / (COLS / 4); };
+  // global operands of item `it` of half h
+  auto fetch = [&](int h, int it, EpiPre<EPI>& p) {
+    const int m = m0 + h * HR + row_of(it);
+    if (it >= ITEMS || m >= M || !col_ok) return;
+    if constexpr (EPI == EPI_STORE) {
+      if (g.resid) p.v[0] = ld4(g.resid + (size_t)m * g.ld_resid + n);
+    } else if constexpr (EPI == EPI_GATE_BWD) {
+      for (int b = 0; b < g.bias_branch_stride; ++b)
+        p.v[b] = ld4(g.aux + (size_t)m * g.ld_aux + b * g.aux_branch + n);
+    }
+  };
+  // result of item `it` of half h from the LDS half tile and its operands
+  auto finish = [&](int h, int it, const EpiPre<EPI>& p) {
+    const int row = row_of(it);
+    const int m = m0 + h * HR + row;
+    if (it >= ITEMS || m >= M || !col_ok) return;
+    const float4 v = *(const float4*)&lds[row * LDE + c];
+    if constexpr (EPI == EPI_WGRAD_OUT) {
+      st4(dw + (size_t)m * N + n, v);
+    } else if constexpr (EPI == EPI_STORE) {
+      float4 o = make_float4(v.x + bias0.x, v.y + bias0.y, v.z + bias0.z, v.w + bias0.w);
+      if (g.resid) {
+        const float4 q = p.v[0];
+        o.x += q.x; o.y += q.y; o.z += q.z; o.w += q.w;
+      }
+      if (g.out32) st4(g.out32 + (size_t)m * g.ld_out32 + n, o);
+      if (g.out16) st4bf(g.out16 + (size_t)m * g.ld_out16 + n, o);
+    } else if constexpr (EPI == EPI_GATE_FWD) {
+      // a_b = acc_b + bias_b (Eq. 10); aux keeps both; out = GeLU(a_0 a_1) (Eqs. 11-12)
+      const float4 w1 = *(const float4*)&lds[row * LDE + T::BN / 2 + c];
+      const float4 a0 = make_float4(v.x + bias0.x, v.y + bias0.y, v.z + bias0.z, v.w + bias0.w);
+      const float4 a1 = make_float4(w1.x + bias1.x, w1.y + bias1.y, w1.z + bias1.z, w1.w + bias1.w);
+      st4(g.aux + (size_t)m * g.ld_aux + n, a0);
+      st4(g.aux + (size_t)m * g.ld_aux + g.aux_branch + n, a1);
+      const float4 o = make_float4(gelu_f(a0.x * a1.x), gelu_f(a0.y * a1.y),
+                                   gelu_f(a0.z * a1.z), gelu_f(a0.w * a1.w));
+      if (g.out32) st4(g.out32 + (size_t)m * g.ld_out32 + n, o);
+      if (g.out16) st4bf(g.out16 + (size_t)m * g.ld_out16 + n, o);
+    } else {  // EPI_GATE_BWD: dP = acc * GeLU'(prod a); dX_b = dP * prod_{c != b} a_c
+      const int nbr = g.bias_branch_stride;
+      const float* av = (const float*)p.v;
+      const float* vv = (const float*)&v;
+      float o[3][4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        float prod = av[e];
+        for (int b = 1; b < nbr; ++b) prod *= av[4 * b + e];
+        const float dp = vv[e] * gelu_grad_f(prod);
+        for (int b = 0; b < nbr; ++b) {
+          float x = dp;
+          for (int cc = 0; cc < nbr; ++cc)
+            if (cc != b) x *= av[4 * cc + e];
+          o[b][e] = x;
+        }
+      }
+      for (int b = 0; b < nbr; ++b) {
+        const float4 ob = make_float4(o[b][0], o[b][1], o[b][2], o[b][3]);
+        if (g.out32) st4(g.out32 + (size_t)m * g.ld_out32 + b * g.aux_branch + n, ob);
+        if (g.out16) st4bf(g.out16 + (size_t)m * g.ld_out16 + b * g.aux_branch + n, ob);
+      }
+    }
+  };
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    EpiPre<EPI> pre[EB];
+    // first batch of operand reads in flight before the half goes through LDS
+#pragma unroll
+    for (int e = 0; e < EB; ++e) fetch(h, threadIdx.x + e * kWideThreads, pre[e]);
+    __syncthreads();  // the K loop (or the previous half) is done with LDS
+    if (wm * WROWS >= h * HR && wm * WROWS < (h + 1) * HR) {
+#pragma unroll
+      for (int i = 0; i < T::TM; ++i)
+#pragma unroll
+        for (int j = 0; j < T::TN; ++j)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int row = wm * WROWS - h * HR + i * 32 + wacc_row(r, lane);
+            lds[row * LDE + T::col_block(wn, j) + (lane & 31)] = acc[i][j][r];
+          }
+    }
+    __syncthreads();
+    for (int b0 = 0; b0 < ITEMS; b0 += EB * kWideThreads) {
+      if (b0 > 0) {
+#pragma unroll
+        for (int e = 0; e < EB; ++e) fetch(h, b0 + threadIdx.x + e * kWideThreads, pre[e]);
+      }
+#pragma unroll
+      for (int e = 0; e < EB; ++e) finish(h, b0 + threadIdx.x + e * kWideThreads, pre[e]);
+    }
+  }
+}
+
+template <class T, bool AK, bool BKM, int EPI>
+__global__ void __launch_bounds__(kWideThreads) gemm_wide_kernel(GemmArgs g) {
+  extern __shared__ __align__(16) char smem[];
+  const int M = g.m_rows ? g.st->rows : g.M;
+  const int K = g.k_rows ? g.st->rows : g.K;
+  const int N = g.N;
+  const int tile = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  const int tx = tile % gridDim.x, ty = tile / gridDim.x;
+  const int m0 = ty * T::BM;
+  if (m0 >= M) return;
+  WideCompute<T, AK, BKM> wc;
+  int n0;  // first output column of the tile (per branch for gated tiles)
+  if constexpr (T::GATE) {
+    n0 = tx * (T::BN / 2);
+    const int bro = (int)(g.b_branch_stride / g.ldb);  // rows between the branch matrices
+    wc.run((const bf16_t*)g.A, g.lda, m0, M, (const bf16_t*)g.B, g.ldb, n0, N, T::BN / 2,
+           bro + n0, bro + N, K, smem);
+  } else {
+    n0 = tx * T::BN;
+    wc.run((const bf16_t*)g.A, g.lda, m0, M, (const bf16_t*)g.B, g.ldb, n0, N, T::BN, 0, 0, K,
+           smem);
+  }
+  wide_epilogue<T, EPI>(wc.acc, g, nullptr, m0, n0, M, N, smem);
+}
+
+// Weight gradients dW = dOut^T In over grouped problems (K = active rows).
+template <class T>
+__global__ void __launch_bounds__(kWideThreads) wgrad_wide_kernel(const WgradProblem* __restrict__ probs,
+                                                                  int n_probs, const StepState* st) {
+  extern __shared__ __align__(16) char smem[];
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  int p = 0;
+  while (p + 1 < n_probs && tile >= probs[p + 1].tile_begin) ++p;
+  const WgradProblem pr = probs[p];
+  const int t = tile - pr.tile_begin;
+  const int m0 = (t / pr.tiles_n) * T::BM, n0 = (t % pr.tiles_n) * T::BN;
+  const int K = st->rows;
+  WideCompute<T, false, false> wc;
+  wc.run((const bf16_t*)pr.dout, pr.M, m0, pr.M, (const bf16_t*)pr.in, pr.N, n0, pr.N, T::BN, 0,
+         0, K, smem);
+  GemmArgs unused;
+  wide_epilogue<T, EPI_WGRAD_OUT>(wc.acc, unused, pr.dw, m0, n0, pr.M, pr.N, smem);
+}
+
+// ---------------------------------------------------------------------------
+// Dispatch
+// ---------------------------------------------------------------------------
+template <class T, bool AK, bool BKM, int EPI>
+static hipError_t launch_wide_one(const GemmArgs& g, int grid_m_max, hipStream_t s) {
+  const int cols = T::GATE ? T::BN / 2 : T::BN;
+  dim3 grid((g.N + cols - 1) / cols, (grid_m_max + T::BM - 1) / T::BM);
+  if (grid.x == 0 || grid.y == 0) return hipSuccess;
+  static_assert(T::SMEM <= 160 * 1024, "tile does not fit in LDS");
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)gemm_wide_kernel<T, AK, BKM, EPI>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, T::SMEM);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL((gemm_wide_kernel<T, AK, BKM, EPI>), grid, dim3(kWideThreads), T::SMEM, s, g);
+  return hipGetLastError();
+}
+
+template <int BM, int BN, int WM>
+static hipError_t launch_wide_t(bool ak, bool bk, EpiKind epi, int nb, const GemmArgs& g, int gm,
+                                hipStream_t s) {
+  typedef WideTile<BM, BN, WM, false> P;
+  typedef WideTile<BM, BN, WM, true> G;
+  if (ak && bk) {
+    if (epi == EPI_STORE) return launch_wide_one<P, true, true, EPI_STORE>(g, gm, s);
+    if (epi == EPI_GATE_FWD && nb == 2) return launch_wide_one<G, true, true, EPI_GATE_FWD>(g, gm, s);
+  } else if (ak && !bk) {
+    if (epi == EPI_STORE) return launch_wide_one<P, true, false, EPI_STORE>(g, gm, s);
+    if (epi == EPI_GATE_BWD) return launch_wide_one<P, true, false, EPI_GATE_BWD>(g, gm, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+bool wide_tile_supported(int tile, bool bf16, EpiKind epi, int nb) {
+  if (tile < TILE_W128x128) return true;
+  if (!bf16) return false;
+  return !(epi == EPI_GATE_FWD && nb != 2);
+}
+
+hipError_t launch_gemm_wide(int tile, bool a_kmajor, bool b_kmajor, EpiKind epi, int nb,
+                            const GemmArgs& g, int grid_m_max, hipStream_t s) {
+  switch (tile) {
+    case TILE_W128x128: return launch_wide_t<128, 128, 4>(a_kmajor, b_kmajor, epi, nb, g, grid_m_max, s);
+    case TILE_W256x128: return launch_wide_t<256, 128, 4>(a_kmajor, b_kmajor, epi, nb, g, grid_m_max, s);
+    case TILE_W128x256: return launch_wide_t<128, 256, 2>(a_kmajor, b_kmajor, epi, nb, g, grid_m_max, s);
+    case TILE_W256x256: return launch_wide_t<256, 256, 2>(a_kmajor, b_kmajor, epi, nb, g, grid_m_max, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <class T>
+static hipError_t launch_wgrad_wide_t(const WgradProblem* d_probs, int n_probs, int total_tiles,
+                                      const StepState* st, hipStream_t s) {
+  if (total_tiles == 0) return hipSuccess;
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)wgrad_wide_kernel<T>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, T::SMEM);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL((wgrad_wide_kernel<T>), dim3(total_tiles), dim3(kWideThreads), T::SMEM, s,
+                     d_probs, n_probs, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_wgrad_wide(int tile, const WgradProblem* d_probs, int n_probs, int total_tiles,
+                             const StepState* st, hipStream_t s) {
+  switch (tile) {
+    case TILE_W128x128: return launch_wgrad_wide_t<WideTile<128, 128, 4, false>>(d_probs, n_probs, total_tiles, st, s);
+    case TILE_W256x128: return launch_wgrad_wide_t<WideTile<256, 128, 4, false>>(d_probs, n_probs, total_tiles, st, s);
+    case TILE_W128x256: return launch_wgrad_wide_t<WideTile<128, 256, 2, false>>(d_probs, n_probs, total_tiles, st, s);
+    case TILE_W256x256: return launch_wgrad_wide_t<WideTile<256, 256, 2, false>>(d_probs, n_probs, total_tiles, st, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace edpc

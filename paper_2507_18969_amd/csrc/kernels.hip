@@ -249,10 +249,27 @@ __global__ void __launch_bounds__(256) fdm_bwd_kernel(
       nt_store4(vU + idx, v);
     }
   };
-  for (int l = g; l < Lin; l += G) {
+  // rows l = g, g + G, ...; the loads of kFdmBatch rows are issued before any
+  // of them is used, so that each thread keeps 3 kFdmBatch 16-byte loads in
+  // flight (the rows are independent: each updates its own slice of U_s)
+  const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  int l = g;
+  for (; l + (kFdmBatch - 1) * G < Lin; l += kFdmBatch * G) {
+    float4 u[kFdmBatch], m[kFdmBatch], v[kFdmBatch];
+#pragma unroll
+    for (int q = 0; q < kFdmBatch; ++q) {
+      const size_t idx = base_s + (size_t)(l + q * G) * Lout + 4 * t;
+      u[q] = *(const float4*)(U + idx);
+      m[q] = update ? nt_load4(mU + idx) : z4;
+      v[q] = update ? nt_load4(vU + idx) : z4;
+    }
+#pragma unroll
+    for (int q = 0; q < kFdmBatch; ++q) row(l + q * G, u[q], m[q], v[q]);
+  }
+  for (; l < Lin; l += G) {
     const size_t idx = base_s + (size_t)l * Lout + 4 * t;
-    row(l, *(const float4*)(U + idx), update ? nt_load4(mU + idx) : make_float4(0.f, 0.f, 0.f, 0.f),
-        update ? nt_load4(vU + idx) : make_float4(0.f, 0.f, 0.f, 0.f));
+    row(l, *(const float4*)(U + idx), update ? nt_load4(mU + idx) : z4,
+        update ? nt_load4(vU + idx) : z4);
   }
 }
 

@@ -19,17 +19,18 @@ void hip_check(hipError_t e, const char* what) {
 
 uint64_t KernelConfig::encode() const {
   uint64_t id = (uint64_t)kNumericsRevision << 48;
-  for (int i = 0; i < PS_COUNT; ++i) id |= (uint64_t)(tile[i] & 7) << (3 * i);
+  for (int i = 0; i < PS_COUNT; ++i) id |= (uint64_t)(tile[i] & 15) << (4 * i);
   if (fused) id |= 1ull << 47;
   return id;
 }
 
 bool KernelConfig::decode(uint64_t id, KernelConfig* out) {
+  static_assert(4 * PS_COUNT <= 47, "tile ids overlap the fused bit");
   if ((id >> 48) != kNumericsRevision) return false;
-  if ((id >> (3 * PS_COUNT)) & ((1ull << (47 - 3 * PS_COUNT)) - 1)) return false;
+  if ((id >> (4 * PS_COUNT)) & ((1ull << (47 - 4 * PS_COUNT)) - 1)) return false;
   out->fused = ((id >> 47) & 1) != 0;
   for (int i = 0; i < PS_COUNT; ++i) {
-    const int t = (int)((id >> (3 * i)) & 7);
+    const int t = (int)((id >> (4 * i)) & 15);
     if (t >= TILE_COUNT) return false;
     out->tile[i] = t;
   }
@@ -119,15 +120,21 @@ void Model::validate(const edpc_config& c) {
 }
 
 // Largest tile whose grid still has >= `want` tiles; the smallest otherwise.
-static int pick_tile(size_t M, const std::vector<std::pair<int, int>>& shapes, size_t want) {
-  static const int order[] = {TILE_128x128, TILE_128x64, TILE_64x128, TILE_64x64,
-                              TILE_64x32,   TILE_32x64,  TILE_32x32};
+// The wide 8-wave tiles serve BF16 products (and gated ones with k = 2).
+static int pick_tile(size_t M, const std::vector<std::pair<int, int>>& shapes, size_t want,
+                     bool bf16, EpiKind epi = EPI_STORE, int nb = 1) {
+  static const int order[] = {TILE_W256x256, TILE_W256x128, TILE_W128x256, TILE_W128x128,
+                              TILE_128x64,   TILE_64x128,   TILE_64x64,    TILE_64x32,
+                              TILE_32x64,    TILE_32x32};
   for (int t : order) {
+    if (!wide_tile_supported(t, bf16, epi, nb)) continue;
     const TileShape ts = tile_shape(t);
+    // a wide gated tile holds bn / 2 outputs of each of the two branches
+    const int bn = (epi == EPI_GATE_FWD && t >= TILE_W128x128) ? ts.bn / 2 : ts.bn;
     size_t n = 0;
     for (auto& mn : shapes) {
       const size_t m = mn.first ? (size_t)mn.first : M;
-      n += ((m + ts.bm - 1) / ts.bm) * ((mn.second + ts.bn - 1) / ts.bn);
+      n += ((m + ts.bm - 1) / ts.bm) * ((mn.second + bn - 1) / bn);
     }
     if (n >= want) return t;
   }
@@ -138,10 +145,12 @@ KernelConfig Model::default_config(const edpc_config& c, size_t rows) {
   KernelConfig k;
   const int F = c.context * c.embed, L = c.latent, H = c.hidden;
   const int KH = c.branches * H;
-  auto one = [&](int n) { return pick_tile(rows, {{0, n}}, 256); };
+  const bool bf = c.precision == EDPC_BF16;
+  auto one = [&](int n) { return pick_tile(rows, {{0, n}}, 256, bf); };
   k.tile[PS_LTE_DOWN] = one(L);
   k.tile[PS_LTE_UP] = one(F);
-  k.tile[PS_GATE] = one(H);
+  // gated products: a wide tile's columns hold both branches of H / 2 outputs
+  k.tile[PS_GATE] = pick_tile(rows, {{0, H}}, 256, bf, EPI_GATE_FWD, (int)c.branches);
   k.tile[PS_OUT] = one(F);
   k.tile[PS_HEAD] = one(256);
   k.tile[PS_HEAD_BWD] = one(F);
@@ -154,7 +163,7 @@ KernelConfig Model::default_config(const edpc_config& c, size_t rows) {
     wg.push_back({F, H});
     wg.push_back({KH, F});
   }
-  k.tile[PS_WGRAD] = pick_tile(rows, wg, 512);
+  k.tile[PS_WGRAD] = pick_tile(rows, wg, 512, bf);
   // BF16 shapes with a row-block kernel take the fused step (one workgroup per
   // 16 rows runs LTE up .. head .. coder .. adjoint) unless EDPC_CFG_LAYERWISE
   // asks for the layer-by-layer products.  The row-block kernels index
@@ -844,8 +853,11 @@ void Model::autotune(hipStream_t s) {
     if (lte_ps && !lte) continue;
     int best = kc.tile[ps];
     float best_ms = 1e30f;
+    const EpiKind epi = ps == PS_GATE ? EPI_GATE_FWD : ps == PS_GATE_BWD ? EPI_GATE_BWD : EPI_STORE;
+    const int nb = ps == PS_GATE ? K : 1;
     for (int t = 0; t < TILE_COUNT; ++t) {
       const TileShape sh = tile_shape(t);
+      if (!wide_tile_supported(t, bf16, epi, nb)) continue;
       if (ps != PS_WGRAD && sh.bm > 2 * R && t != TILE_32x32) continue;
       kc.tile[ps] = t;
       product(ps, 0, R, s);  // warm-up (first launch may set attributes)

@@ -128,7 +128,7 @@ def _check_own_adam(name, cfg, tau, theta0, m0, v0, g, got_p, got_m, got_v):
                   + 1e-12), (name, "param", np.abs(got_p - (theta0 - u)).max())
 
 
-def _update_case(E, model, rows, om_steps, wl, layerwise=False, sample_rows=None):
+def _update_case(E, model, rows, om_steps, wl, layerwise=False, sample_rows=None, kernel_id=0):
     C = model["context"]
     pos = C + om_steps
     data, _ = gen.make_streams(wl, prefix=pos + 1, n_streams=rows)
@@ -138,7 +138,9 @@ def _update_case(E, model, rows, om_steps, wl, layerwise=False, sample_rows=None
     for i in range(C, pos):
         om.step(st[:, i - C:i].astype(np.int64), st[:, i].astype(np.int64), np.arange(rows))
     om.round_to_f32()
-    m = E.Model(lib_cfg(E, model, "bf16", layerwise=layerwise), rows, rows)
+    m = E.Model(lib_cfg(E, model, "bf16", layerwise=layerwise), rows, rows, kernel_id)
+    if kernel_id:
+        assert m.edpc_model_kernel_id() == kernel_id
     load_oracle_state(m, om)
     ctx, tgt = st[:, pos - C:pos], st[:, pos]
     slots = np.arange(rows)
@@ -149,9 +151,11 @@ def _update_case(E, model, rows, om_steps, wl, layerwise=False, sample_rows=None
     v0 = {k: om.v[k].copy() for k in om.p}
     U0, mU0, vU0 = om.U.copy(), om.mU.copy(), om.vU.copy()
     tau = om.tau + 1
-    m.edpc_model_step(_dev(ctx), _dev(tgt), slots, flags=E.EDPC_STEP_UPDATE)
+    probs = torch.empty((rows, 256), dtype=torch.float32, device="cuda")
+    m.edpc_model_step(_dev(ctx), _dev(tgt), slots, probs, flags=E.EDPC_STEP_UPDATE)
     torch.cuda.synchronize()
     assert m.edpc_model_get_step() == tau
+    assert np.abs(probs.cpu().numpy() - c["p"]).max() <= 2e-3
     operand_checked = 0
     for k in om.p:
         g = g_o[k].reshape(-1)
@@ -210,6 +214,37 @@ def test_bf16_fused_one_block_model(E):
     # the fused step with a single refinement block (Table 4 "one block" row)
     model = dict(SMALL, blocks=1)
     _update_case(E, model, rows=24, om_steps=8, wl="mid_bf16")
+
+
+# the 8-wave wide BF16 tiles (tile ids of the kernel configuration)
+WIDE_TILES = {"w128x128": 7, "w256x128": 8, "w128x256": 9, "w256x256": 10}
+
+
+def _uniform_kernel_id(E, cfg, tile):
+    """Kernel configuration with `tile` for every matrix product (layer-by-
+    layer step), in the numerics revision the library runs."""
+    rev = E.Model(cfg, 1, 1).edpc_model_kernel_id() >> 48
+    return (rev << 48) | sum(tile << (4 * i) for i in range(11))
+
+
+@pytest.mark.parametrize("tile", sorted(WIDE_TILES))
+def test_bf16_update_wide_tiles(E, tile):
+    # every product of the layer-by-layer step (forward, both adjoint
+    # layouts, the gated epilogues, the weight gradients) on one wide tile
+    # shape: 300 rows span a 256-row tile and a ragged one
+    kid = _uniform_kernel_id(E, lib_cfg(E, MID, "bf16", layerwise=True), WIDE_TILES[tile])
+    _update_case(E, MID, rows=300, om_steps=4, wl="mid_bf16", layerwise=True,
+                 sample_rows=range(0, 300, 37), kernel_id=kid)
+
+
+def test_wide_tiles_refused_where_they_do_not_apply(E):
+    # FP32 models and three-branch gated products have no wide tile
+    for model, prec in ((SMALL, "fp32"), (dict(SMALL, branches=3), "bf16")):
+        cfg = lib_cfg(E, model, prec, layerwise=True)
+        kid = _uniform_kernel_id(E, cfg, WIDE_TILES["w256x256"])
+        with pytest.raises(E.EdpcError) as ei:
+            E.Model(cfg, 4, 4, kid)
+        assert ei.value.status == -6
 
 
 @pytest.mark.parametrize("precision", ["bf16", "fp32"])
