@@ -311,6 +311,36 @@ def ragged_full_job(torch, E):
     return res
 
 
+def stream_job(torch, E, chunk=4096, precision="bf16"):
+    """End-to-end host-to-host rate of the 1024-stream workload: the whole
+    64 MiB encoded from pinned host memory into host memory and decoded back
+    (edpc_encode_host / edpc_decode_host: input and output move through a
+    device window of a few chunks per stream, overlapped with the steps)."""
+    import gen
+    w = gen.WORKLOADS["mid_bf16"]
+    data, lens = gen.make_streams(w)
+    h_in = torch.from_numpy(data).pin_memory()
+    cfg = lib_cfg(E, w.model, precision)
+    cap = E.edpc_encode_bound(cfg, lens)
+    h_cont = torch.empty(cap, dtype=torch.uint8).pin_memory()
+    n = int(data.size)
+    t0 = time.perf_counter()
+    clen = E.edpc_encode_host(cfg, h_in, lens, chunk, out=h_cont)
+    te = time.perf_counter() - t0
+    log(f"stream: encode {n / te / 1e6:.3f} MB/s")
+    h_out = torch.empty(n, dtype=torch.uint8).pin_memory()
+    t0 = time.perf_counter()
+    got = E.edpc_decode_host(h_cont[:clen], chunk, out=h_out)
+    td = time.perf_counter() - t0
+    ok = got == n and bool(torch.equal(h_out, h_in))
+    res = {"workload": w.description, "precision": precision, "chunk_steps": chunk,
+           "encode_MBps": round(n / te / 1e6, 4), "decode_MBps": round(n / td / 1e6, 4),
+           "encode_s": round(te, 2), "decode_s": round(td, 2), "roundtrip": ok,
+           "bits_per_byte": round(8.0 * (clen - (96 + 20 * len(lens))) / n, 4)}
+    log(f"stream: {res}")
+    return res
+
+
 GOLDEN_FILE = os.path.join(ROOT, "tests", "golden", "oracle_sizes.json")
 
 
@@ -515,6 +545,8 @@ def run_extra(torch, E, a):
             extra[name] = large_workload(torch, E, a.precisions.split(","))
         elif name == "ragged_full":
             extra[name] = ragged_full_job(torch, E)
+        elif name == "stream":
+            extra[name] = stream_job(torch, E)
         else:
             extra[name] = extra_workload(torch, E, name, a.warmup, min(a.steps, 200))
     return extra
@@ -534,7 +566,7 @@ def main():
                          "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE readings)")
     ap.add_argument("--extra", default="",
                     help="comma list of further workloads measured after the main one "
-                         "(ragged, ragged_full, large, ablations); reported under "
+                         "(ragged, ragged_full, large, stream, ablations); reported under "
                          "extra_workloads")
     ap.add_argument("--no-size-parity", action="store_true",
                     help="skip the compressed-size comparison with the oracle's stored sizes")

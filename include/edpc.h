@@ -165,6 +165,25 @@ edpc_status edpc_decode_info(const uint8_t* h_in, size_t in_len, edpc_config* cf
 edpc_status edpc_decode(const uint8_t* d_in, size_t in_len, uint8_t* d_out,
                         size_t out_cap, size_t* out_len, void* stream);
 
+/* Host-to-host codec: the same containers as edpc_encode / edpc_decode, for
+ * inputs and outputs in host memory (pinned memory copies fastest).  The
+ * paper pipelines GPU prediction with CPU coding (Sec. 3.3); here the coder
+ * runs on the GPU, and what is pipelined is the data movement: streams pass
+ * through a device window of a few chunks of `chunk_steps` bytes per stream
+ * (chunk_steps >= context), chunk k + 1 moving host -> device on a second
+ * stream while chunk k is coded, and finished payload bytes (decoded bytes)
+ * moving back the same way.  Device memory holds the model, the window and
+ * (encoder) the payload region; the input or output is never resident whole.
+ * encode: EDPC_E_CAPACITY if out_cap is short, with the size in *out_len.
+ * decode: verifies the CRCs; *out_len = bytes decoded.  Synchronous. */
+edpc_status edpc_encode_host(const edpc_config* cfg, const uint8_t* h_in,
+                             const uint64_t* h_lens, size_t n_streams, uint8_t* h_out,
+                             size_t out_cap, size_t* out_len, uint32_t chunk_steps,
+                             void* stream);
+edpc_status edpc_decode_host(const uint8_t* h_in, size_t in_len, uint8_t* h_out,
+                             size_t out_cap, size_t* out_len, uint32_t chunk_steps,
+                             void* stream);
+
 /* ------------------------------------------------------------------------
  * Step-granular sessions: the same codec, advanced a number of model steps
  * at a time (for streaming callers and for timing).  A session keeps

@@ -40,7 +40,7 @@ KCLASS_COUNT = 24
 EXPORTS = [
     "edpc_status_string", "edpc_last_error", "edpc_abi_version", "edpc_config_default",
     "edpc_config_validate", "edpc_encode_bound", "edpc_encode", "edpc_decode_info",
-    "edpc_decode", "edpc_encoder_begin", "edpc_decoder_begin", "edpc_session_run",
+    "edpc_decode", "edpc_encode_host", "edpc_decode_host", "edpc_encoder_begin", "edpc_decoder_begin", "edpc_session_run",
     "edpc_session_progress", "edpc_encoder_finish", "edpc_decoder_finish",
     "edpc_session_destroy", "edpc_session_time_kernels", "edpc_kclass_name", "edpc_model_create", "edpc_model_create_with_kernels", "edpc_model_kernel_id",
     "edpc_model_destroy", "edpc_model_step",
@@ -98,6 +98,9 @@ def lib() -> ctypes.CDLL:
         "edpc_encode": (ctypes.c_int, [cfgp, _P, _U64P, _SZ, _P, _SZ, _SZP, _P]),
         "edpc_decode_info": (ctypes.c_int, [_P, _SZ, cfgp, _SZP, _U64P, _SZ, _SZP, _SZP]),
         "edpc_decode": (ctypes.c_int, [_P, _SZ, _P, _SZ, _SZP, _P]),
+        "edpc_encode_host": (ctypes.c_int, [cfgp, _P, _U64P, _SZ, _P, _SZ, _SZP,
+                                             ctypes.c_uint32, _P]),
+        "edpc_decode_host": (ctypes.c_int, [_P, _SZ, _P, _SZ, _SZP, ctypes.c_uint32, _P]),
         "edpc_encoder_begin": (ctypes.c_int, [cfgp, _P, _U64P, _SZ, _P, ctypes.POINTER(_P)]),
         "edpc_decoder_begin": (ctypes.c_int, [_P, _SZ, _P, _SZ, _P, ctypes.POINTER(_P)]),
         "edpc_session_run": (ctypes.c_int, [_P, ctypes.c_uint64, _U64P]),
@@ -233,6 +236,45 @@ def edpc_decode(container, stream=None):
     _check(lib().edpc_decode(_dptr(container), container.numel(), _dptr(out), out.numel(),
                              ctypes.byref(n), _stream(stream)))
     return out[: n.value], lens
+
+
+def _host_ptr(a):
+    """Pointer of a host buffer: a numpy array or a (pinned) CPU torch tensor."""
+    if isinstance(a, np.ndarray):
+        return ctypes.c_void_p(a.ctypes.data)
+    return ctypes.c_void_p(a.data_ptr())
+
+
+def edpc_encode_host(cfg: edpc_config, h_in, lens, chunk_steps: int, out=None, stream=None):
+    """Compress streams held in host memory (numpy uint8 array or CPU torch
+    tensor, pinned for speed); returns the container as numpy bytes, or its
+    length if ``out`` (a host buffer of at least edpc_encode_bound bytes) is
+    given."""
+    ln = _lens(lens)
+    cap = edpc_encode_bound(cfg, ln)
+    buf = np.empty(cap, dtype=np.uint8) if out is None else out
+    n = ctypes.c_size_t()
+    _check(lib().edpc_encode_host(ctypes.byref(cfg), _host_ptr(h_in), ln.ctypes.data_as(_U64P),
+                                  len(ln), _host_ptr(buf), cap, ctypes.byref(n), chunk_steps,
+                                  _stream(stream)))
+    return buf[: n.value] if out is None else n.value
+
+
+def edpc_decode_host(container, chunk_steps: int, out=None, stream=None):
+    """Decompress a container held in host memory; returns the decoded bytes
+    (numpy) or their count if ``out`` is given."""
+    c = np.ascontiguousarray(np.frombuffer(bytes(container), dtype=np.uint8)) \
+        if not hasattr(container, "data_ptr") and not isinstance(container, np.ndarray) else container
+    head = bytes(np.asarray(c[:16] if isinstance(c, np.ndarray) else c[:16].numpy()))
+    hl = int.from_bytes(head[8:12], "little")
+    hdr = bytes(np.asarray(c[:hl] if isinstance(c, np.ndarray) else c[:hl].numpy()))
+    _, _, _, total = edpc_decode_info(hdr)
+    buf = np.empty(max(total, 1), dtype=np.uint8) if out is None else out
+    n = ctypes.c_size_t()
+    size = c.size if isinstance(c, np.ndarray) else c.numel()
+    _check(lib().edpc_decode_host(_host_ptr(c), size, _host_ptr(buf), total, ctypes.byref(n),
+                                  chunk_steps, _stream(stream)))
+    return buf[: n.value] if out is None else n.value
 
 
 class Session:

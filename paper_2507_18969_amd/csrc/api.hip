@@ -214,6 +214,35 @@ edpc_status edpc_decode(const uint8_t* d_in, size_t in_len, uint8_t* d_out, size
   return st;
 }
 
+edpc_status edpc_encode_host(const edpc_config* cfg, const uint8_t* h_in, const uint64_t* h_lens,
+                             size_t n, uint8_t* h_out, size_t out_cap, size_t* out_len,
+                             uint32_t chunk_steps, void* stream) {
+  return guarded([&] {
+    if (!cfg || !h_lens || !out_len || !h_out) fail(EDPC_E_INVALID_ARG, "NULL argument");
+    uint64_t total = 0;
+    for (size_t i = 0; i < n; ++i) total += h_lens[i];
+    if (total && !h_in) fail(EDPC_E_INVALID_ARG, "h_in is NULL");
+    size_t need = 0;
+    try {
+      *out_len = stream_encode(*cfg, h_in, h_lens, n, h_out, out_cap, chunk_steps, S(stream), &need);
+    } catch (const Error& e) {
+      if (e.status == EDPC_E_CAPACITY) *out_len = need;
+      throw;
+    }
+    return EDPC_OK;
+  });
+}
+
+edpc_status edpc_decode_host(const uint8_t* h_in, size_t in_len, uint8_t* h_out, size_t out_cap,
+                             size_t* out_len, uint32_t chunk_steps, void* stream) {
+  return guarded([&] {
+    if (!h_in || !out_len) fail(EDPC_E_INVALID_ARG, "NULL argument");
+    if (!h_out && out_cap) fail(EDPC_E_INVALID_ARG, "h_out is NULL");
+    *out_len = stream_decode(h_in, in_len, h_out, out_cap, chunk_steps, S(stream));
+    return EDPC_OK;
+  });
+}
+
 edpc_status edpc_decode_info(const uint8_t* h_in, size_t in_len, edpc_config* cfg,
                              size_t* n_streams, uint64_t* h_lens, size_t lens_cap,
                              size_t* header_len, size_t* decoded_len) {

@@ -93,5 +93,21 @@ std::unique_ptr<Session> decoder_begin(const uint8_t* d_in, size_t in_len, uint8
                                        size_t out_cap, hipStream_t s);
 size_t decoder_finish(Session& ss);
 size_t encode_bound(const edpc_config& cfg, const uint64_t* lens, size_t n);
+// Sorting, model, schedule and stream tables of a session (cfg, n, lens, s
+// and decoding already set).
+void common_setup(Session& ss, const KernelConfig* kc);
+// Checks a parsed header against the library (architecture, kernel
+// configuration, model) and returns its kernel configuration.
+KernelConfig header_kernels(const Header& h);
+
+// Host-to-host codec (stream.hip): the same containers as encoder_begin /
+// decoder_begin + finish, with the input (or the decoded output) moving
+// through a device window of a few chunks of `chunk` steps per stream, the
+// copies on a second stream overlapped with the steps.
+size_t stream_encode(const edpc_config& cfg, const uint8_t* h_in, const uint64_t* lens, size_t n,
+                     uint8_t* h_out, size_t out_cap, uint32_t chunk, hipStream_t s,
+                     size_t* required);
+size_t stream_decode(const uint8_t* h_in, size_t in_len, uint8_t* h_out, size_t out_cap,
+                     uint32_t chunk, hipStream_t s);
 
 }  // namespace edpc

@@ -226,7 +226,7 @@ void Session::run(uint64_t k) {
   next = end;
 }
 
-static void common_setup(Session& ss, const KernelConfig* kc) {
+void common_setup(Session& ss, const KernelConfig* kc) {
   const size_t n = ss.n;
   std::vector<uint32_t> perm(n);
   std::iota(perm.begin(), perm.end(), 0u);
@@ -341,6 +341,14 @@ size_t encoder_finish(Session& ss, uint8_t* d_out, size_t out_cap) {
   return total;
 }
 
+KernelConfig header_kernels(const Header& h) {
+  if (h.arch != kArch) fail(EDPC_E_UNSUPPORTED, "container written for another device architecture");
+  KernelConfig kc;
+  if (!KernelConfig::decode(h.kernel_id, &kc)) fail(EDPC_E_UNSUPPORTED, "unknown kernel configuration");
+  Model::validate(h.cfg);
+  return kc;
+}
+
 std::unique_ptr<Session> decoder_begin(const uint8_t* d_in, size_t in_len, uint8_t* d_out,
                                        size_t out_cap, hipStream_t s) {
   std::vector<uint8_t> fixed(std::min<size_t>(in_len, 16));
@@ -358,10 +366,7 @@ std::unique_ptr<Session> decoder_begin(const uint8_t* d_in, size_t in_len, uint8
   hip_check(hipStreamSynchronize(s), "copy");
   st = parse_header(hb.data(), hb.size(), &h, &need, &err);
   if (st != EDPC_OK) fail(st, err);
-  if (h.arch != kArch) fail(EDPC_E_UNSUPPORTED, "container written for another device architecture");
-  KernelConfig kc;
-  if (!KernelConfig::decode(h.kernel_id, &kc)) fail(EDPC_E_UNSUPPORTED, "unknown kernel configuration");
-  Model::validate(h.cfg);
+  KernelConfig kc = header_kernels(h);
   const size_t n = h.lens.size();
   // (parse_header bounded every length and checked both sums)
   if (h.total_pay > in_len || h.header_len > in_len - h.total_pay)

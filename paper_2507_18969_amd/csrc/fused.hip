@@ -665,7 +665,7 @@ __global__ void __launch_bounds__(kFusedThreads, 1) fused_kernel(FusedArgs a) {
       RcDec de = rc.dec;
       rc_consume(de, a.io.pay_in + rc.poff, rc.pcap, (uint32_t)my_cx, (uint32_t)(my_cx + my_qx));
       a.io.dec[rc.s] = de;
-      a.io.dst[rc.off + (uint64_t)st->step] = (uint8_t)my_x;
+      a.io.dst[io_at(a.io, rc.off, (uint64_t)st->step)] = (uint8_t)my_x;
       if (a.head.target_out) a.head.target_out[r0 + my_i] = (uint8_t)my_x;
     }
   }
@@ -905,9 +905,9 @@ __global__ void __launch_bounds__(256) fused_in_kernel(FusedInArgs a) {
         const uint32_t sidx = a.io.slot[r];
         const uint8_t* base = a.decoding ? a.io.dst : a.io.src;
         const uint64_t o = a.io.off[sidx];
-        v = base[o + (uint64_t)(st->step - C + c)];
+        v = base[io_at(a.io, o, (uint64_t)(st->step - C + c))];
         a.ctx[(size_t)r * C + c] = v;
-        if (!a.decoding && c == 0) a.tgt[r] = a.io.src[o + (uint64_t)st->step];
+        if (!a.decoding && c == 0) a.tgt[r] = a.io.src[io_at(a.io, o, (uint64_t)st->step)];
       } else {
         v = a.ctx[(size_t)r * C + c];
       }

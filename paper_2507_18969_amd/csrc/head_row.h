@@ -117,7 +117,7 @@ __device__ __forceinline__ bool head_row(const StepState* __restrict__ st, const
       RcDec de = io.dec[s];
       rc_consume(de, io.pay_in + io.pay_off[s], io.pay_cap[s], (uint32_t)cx, (uint32_t)(cx + qx));
       io.dec[s] = de;
-      io.dst[io.off[s] + (uint64_t)st->step] = (uint8_t)x;
+      io.dst[io_at(io, io.off[s], (uint64_t)st->step)] = (uint8_t)x;
       if (a.target_out) a.target_out[r] = (uint8_t)x;
     }
   }

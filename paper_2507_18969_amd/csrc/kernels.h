@@ -27,7 +27,15 @@ struct StreamIO {
   const uint64_t* pay_cap;    // stream -> payload capacity (encoder) / length (decoder)
   RcEnc* enc;                 // [n_streams]
   RcDec* dec;                 // [n_streams]
+  uint32_t ring;              // 0: a stream's bytes are contiguous from off[s];
+                              // else each stream has a window of `ring` bytes
+                              // and position p lives at off[s] + p % ring
 };
+
+// Address of position p of the stream whose bytes start at `off`.
+__device__ __forceinline__ uint64_t io_at(const StreamIO& io, uint64_t off, uint64_t p) {
+  return off + (io.ring ? (uint64_t)((uint32_t)p % io.ring) : p);
+}
 
 struct HeadArgs {
   const float* logits;  // [rows, 256]
@@ -113,5 +121,12 @@ void k_crc32(const uint8_t* data, const uint64_t* off, const uint64_t* lens, int
              hipStream_t s);
 void k_gather_payloads(const uint8_t* pay, const uint64_t* pay_off, const uint64_t* len,
                        const uint64_t* dst_off, uint8_t* dst, int n, hipStream_t s);
+
+// Streaming encoder: per stream, move the payload bytes that no later carry
+// can change (all written bytes if `all`) from the payload region to
+// out + s * stride, at most `stride` bytes past done[s]; out_len[s] gets the
+// count and done[s] advances by it.
+void k_pay_drain(const RcEnc* enc, const uint8_t* pay, const uint64_t* pay_off, uint64_t* done,
+                 int n, bool all, uint8_t* out, uint32_t stride, uint32_t* out_len, hipStream_t s);
 
 }  // namespace edpc

@@ -83,8 +83,8 @@ __global__ void gather_kernel(const StepState* __restrict__ st, StreamIO io, int
   const uint32_t s = io.slot[r];
   const uint8_t* base = decoding ? io.dst : io.src;
   const uint64_t o = io.off[s];
-  ctx[idx] = base[o + (uint64_t)(i - C + c)];
-  if (!decoding && c == 0) tgt[r] = io.src[o + (uint64_t)i];
+  ctx[idx] = base[io_at(io, o, (uint64_t)(i - C + c))];
+  if (!decoding && c == 0) tgt[r] = io.src[io_at(io, o, (uint64_t)i)];
 }
 
 void k_gather(const StepState* st, StreamIO io, int C, uint8_t* ctx, uint8_t* tgt, int max_rows,
@@ -812,15 +812,13 @@ __global__ void uniform_prefix_kernel(StreamIO io, int n_streams, int C, bool de
     rc_enc_init(e);
     uint8_t* out = io.pay + io.pay_off[s];
     const uint64_t cap = io.pay_cap[s];
-    const uint8_t* in = io.src + io.off[s];
-    for (uint64_t i = 0; i < n; ++i) rc_encode(e, out, cap, 256u * in[i], 256u);
+    for (uint64_t i = 0; i < n; ++i) rc_encode(e, out, cap, 256u * io.src[io_at(io, io.off[s], i)], 256u);
     io.enc[s] = e;
   } else {
     RcDec d;
     const uint8_t* in = io.pay_in + io.pay_off[s];
     const uint64_t plen = io.pay_cap[s];
     rc_dec_init(d, in, plen);
-    uint8_t* out = io.dst + io.off[s];
     for (uint64_t i = 0; i < n; ++i) {
       // largest x with (range * 256x) >> 16 <= d
       uint32_t lo = 0, hi = 256;
@@ -828,7 +826,7 @@ __global__ void uniform_prefix_kernel(StreamIO io, int n_streams, int C, bool de
         const uint32_t mid = (lo + hi) >> 1;
         if (((d.range * (uint64_t)(256u * mid)) >> 16) <= d.d) lo = mid; else hi = mid;
       }
-      out[i] = (uint8_t)lo;
+      io.dst[io_at(io, io.off[s], i)] = (uint8_t)lo;
       rc_consume(d, in, plen, 256u * lo, 256u * lo + 256u);
     }
     io.dec[s] = d;
@@ -942,6 +940,47 @@ void k_gather_payloads(const uint8_t* pay, const uint64_t* pay_off, const uint64
   if (n == 0) return;
   hipLaunchKernelGGL(gather_payloads_kernel, dim3(n), dim3(256), 0, s, pay, pay_off, len, dst_off,
                      dst);
+}
+
+}  // namespace edpc
+
+namespace edpc {
+
+// One wave per stream.  A carry adds one to the last byte before the coder's
+// write position that is not 0xFF and zeroes the 0xFF bytes after it, so the
+// bytes before that byte are final.
+__global__ void __launch_bounds__(64) pay_drain_kernel(const RcEnc* __restrict__ enc,
+                                                       const uint8_t* __restrict__ pay,
+                                                       const uint64_t* __restrict__ pay_off,
+                                                       uint64_t* __restrict__ done, int n, int all,
+                                                       uint8_t* __restrict__ out, uint32_t stride,
+                                                       uint32_t* __restrict__ out_len) {
+  const int s = blockIdx.x;
+  if (s >= n) return;
+  const uint8_t* p = pay + pay_off[s];
+  const uint64_t pos = enc[s].pos, d0 = done[s];
+  uint64_t fin = pos;
+  if (!all) {
+    fin = d0;
+    for (uint64_t i = pos; i > d0; --i)  // wave-uniform scan, usually one step
+      if (p[i - 1] != 0xFF) { fin = i - 1; break; }
+  }
+  if (fin > d0 + stride) fin = d0 + stride;
+  const uint32_t cnt = (uint32_t)(fin > d0 ? fin - d0 : 0);
+  uint8_t* o = out + (size_t)s * stride;
+  for (uint32_t i = threadIdx.x; i < cnt; i += 64) o[i] = p[d0 + i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    out_len[s] = cnt;
+    done[s] = d0 + cnt;
+  }
+}
+
+void k_pay_drain(const RcEnc* enc, const uint8_t* pay, const uint64_t* pay_off, uint64_t* done,
+                 int n, bool all, uint8_t* out, uint32_t stride, uint32_t* out_len, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(pay_drain_kernel, dim3(n), dim3(64), 0, s, enc, pay, pay_off, done, n,
+                     all ? 1 : 0, out, stride, out_len);
 }
 
 }  // namespace edpc
