@@ -296,6 +296,15 @@ edpc_status edpc_model_write_device(edpc_model* m, uint32_t kind, size_t idx,
 edpc_status edpc_model_get_step(const edpc_model* m, uint64_t* tau);
 edpc_status edpc_model_set_step(edpc_model* m, uint64_t tau);
 
+/* FP32 input of refinement block `block` of the last edpc_model_step
+ * (block = blocks: the head's input, i.e. the last block's output), [rows,
+ * context * embed] row-major, copied to d_dst asynchronously on `stream`.
+ * Block j's skip connection S and its output S + X^(k) (Sec. 3.1.1) are
+ * blocks j and j + 1.  The BF16 row-block step keeps no FP32 copy of the
+ * head's input (EDPC_E_UNSUPPORTED); numel must be rows * context * embed. */
+edpc_status edpc_model_activation(const edpc_model* m, uint32_t block, float* d_dst,
+                                  size_t numel, void* stream);
+
 /* Whole training state of a model (what Algorithm 1 adapts online: every
  * parameter with its Adam moments, and the Adam step counter), as one host
  * blob.  Layout (little-endian): "EDPS", u32 version (1), u32 tensor count,
@@ -310,6 +319,22 @@ edpc_status edpc_model_set_step(edpc_model* m, uint64_t tau);
  * (EDPC_E_INVALID_ARG otherwise).  Both synchronise the device. */
 edpc_status edpc_model_get_state(const edpc_model* m, void* h_buf, size_t cap, size_t* len);
 edpc_status edpc_model_set_state(edpc_model* m, const void* h_buf, size_t len);
+
+/* ------------------------------------------------------------------------
+ * Mutual information (the analysis of Sec. 3.1.1): Kraskov's first
+ * estimator (Eq. 7; Kraskov, Stoegbauer & Grassberger 2004) of I(Z; Y) from
+ * c samples, d_z [c, dz] and d_y [c, dy] FP32 row-major device arrays:
+ *   psi(v) + psi(c) - (1/c) sum_i [psi(c_z(i) + 1) + psi(c_y(i) + 1)],
+ * eps_i the distance from sample i to its v-th nearest other sample in the
+ * joint space under the max norm (ties with multiplicity), c_z(i) (c_y(i))
+ * the samples strictly closer than eps_i in z (y) alone.  Distances are FP32.
+ * IFR_{k1->k2} (Eq. 8) is the ratio of two such estimates.  2 <= c <= 32768,
+ * 1 <= v <= min(16, c - 1).  *h_mi in nats; optional d_counts [c, 2] int32
+ * (c_z, c_y) and d_eps [c].  Allocates 8 c^2 bytes of work memory while it
+ * runs; synchronises `stream`. */
+edpc_status edpc_mutual_info(const float* d_z, size_t dz, const float* d_y, size_t dy,
+                             size_t c, uint32_t v, double* h_mi, int32_t* d_counts,
+                             float* d_eps, void* stream);
 
 /* ------------------------------------------------------------------------
  * Range coder alone (the arithmetic-coding step of Sec. 2.1 and of

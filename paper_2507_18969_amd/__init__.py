@@ -46,7 +46,8 @@ EXPORTS = [
     "edpc_model_destroy", "edpc_model_step",
     "edpc_model_tensor_count", "edpc_model_tensor_info", "edpc_model_read", "edpc_model_write",
     "edpc_model_read_device", "edpc_model_write_device",
-    "edpc_model_get_step", "edpc_model_set_step", "edpc_model_get_state",
+    "edpc_model_get_step", "edpc_model_set_step", "edpc_model_activation",
+    "edpc_mutual_info", "edpc_model_get_state",
     "edpc_model_set_state", "edpc_rc_encode", "edpc_rc_decode", "edpc_rc_encode_noalloc",
     "edpc_rc_encode_host", "edpc_rc_decode_host",
 ]
@@ -124,6 +125,9 @@ def lib() -> ctypes.CDLL:
         "edpc_model_write_device": (ctypes.c_int, [_P, ctypes.c_uint32, _SZ, _P, _SZ, _P]),
         "edpc_model_get_step": (ctypes.c_int, [_P, _U64P]),
         "edpc_model_set_step": (ctypes.c_int, [_P, ctypes.c_uint64]),
+        "edpc_model_activation": (ctypes.c_int, [_P, ctypes.c_uint32, _P, _SZ, _P]),
+        "edpc_mutual_info": (ctypes.c_int, [_P, _SZ, _P, _SZ, _SZ, ctypes.c_uint32,
+                                             ctypes.POINTER(ctypes.c_double), _P, _P, _P]),
         "edpc_model_get_state": (ctypes.c_int, [_P, _P, _SZ, _SZP]),
         "edpc_model_set_state": (ctypes.c_int, [_P, _P, _SZ]),
         "edpc_rc_encode": (ctypes.c_int, [_P, _P, _SZ, _SZ, _P, _SZ, _U32P, _P]),
@@ -419,6 +423,13 @@ class Model:
     def edpc_model_set_step(self, tau: int):
         _check(lib().edpc_model_set_step(self.h, tau))
 
+    def edpc_model_activation(self, block: int, out, stream=None):
+        """FP32 input of refinement block `block` of the last step into the
+        device tensor `out` [rows, context * embed]."""
+        _check(lib().edpc_model_activation(self.h, block, _dptr(out), out.numel(),
+                                           _stream(stream)))
+        return out
+
     def edpc_model_kernel_id(self) -> int:
         k = ctypes.c_uint64()
         _check(lib().edpc_model_kernel_id(self.h, ctypes.byref(k)))
@@ -453,6 +464,35 @@ def edpc_rc_encode(d_cum, d_sym, cap_per_stream: int, stream=None):
     _check(lib().edpc_rc_encode(_dptr(d_cum), _dptr(d_sym), n_steps, n_streams, _dptr(out),
                                 cap_per_stream, lens.ctypes.data_as(_U32P), _stream(stream)))
     return out, lens
+
+
+def edpc_mutual_info(d_z, d_y, v: int = 3, counts=None, eps=None, stream=None) -> float:
+    """Kraskov estimate of I(Z; Y) in nats from FP32 device tensors [c, dz]
+    and [c, dy] (rows are samples)."""
+    c, dz = d_z.shape
+    c2, dy = d_y.shape
+    if c != c2:
+        raise ValueError("z and y need the same number of samples")
+    mi = ctypes.c_double()
+    _check(lib().edpc_mutual_info(_dptr(d_z.contiguous()), dz, _dptr(d_y.contiguous()), dy, c, v,
+                                  ctypes.byref(mi), _dptr(counts) if counts is not None else None,
+                                  _dptr(eps) if eps is not None else None, _stream(stream)))
+    return mi.value
+
+
+def block_mutual_info(model, d_ctx, d_target, slots, v: int = 3):
+    """I(S; S + X^(k)) of every refinement block on one batch (Sec. 3.1.1):
+    runs a forward step on the contexts, then estimates the mutual
+    information between each block's input (the skip connection S) and its
+    output.  Returns a list with one value (nats) per block."""
+    import torch
+    model.edpc_model_step(d_ctx, d_target, slots)
+    rows = len(np.asarray(slots))
+    F = model.cfg.context * model.cfg.embed
+    acts = [model.edpc_model_activation(j, torch.empty((rows, F), dtype=torch.float32,
+                                                       device=d_ctx.device))
+            for j in range(model.cfg.blocks + 1)]
+    return [edpc_mutual_info(acts[j], acts[j + 1], v) for j in range(model.cfg.blocks)]
 
 
 def edpc_rc_encode_noalloc(d_cum, d_sym, out, stream=None):

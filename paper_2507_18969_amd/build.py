@@ -19,7 +19,7 @@ CSRC = os.path.join(PKG, "csrc")
 ROOT = os.path.dirname(PKG)
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libedpc.so")
-SOURCES = ["gemm.hip", "gemm_wide.hip", "kernels.hip", "fused.hip", "model.hip", "codec.hip", "stream.hip", "api.hip"]
+SOURCES = ["gemm.hip", "gemm_wide.hip", "kernels.hip", "fused.hip", "model.hip", "codec.hip", "stream.hip", "ksg.hip", "api.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -560,6 +560,32 @@ edpc_status edpc_model_write_device(edpc_model* mh, uint32_t kind, size_t idx, c
   });
 }
 
+edpc_status edpc_model_activation(const edpc_model* mh, uint32_t block, float* d_dst, size_t numel,
+                                  void* stream) {
+  return guarded([&] {
+    if (!mh || !mh->m || !d_dst) fail(EDPC_E_INVALID_ARG, "NULL argument");
+    const Model& m = *mh->m;
+    if (block > (uint32_t)m.N) fail(EDPC_E_INVALID_ARG, "block index out of range");
+    if (m.last_rows == 0) fail(EDPC_E_INVALID_ARG, "no step has run");
+    const float* src = m.block_input((int)block);
+    if (!src) fail(EDPC_E_UNSUPPORTED, "the row-block step keeps no FP32 copy of the head's input");
+    if (numel != (size_t)m.last_rows * m.F) fail(EDPC_E_INVALID_ARG, "numel must be rows * context * embed");
+    hip_check(hipMemcpyAsync(d_dst, src, numel * sizeof(float), hipMemcpyDeviceToDevice, S(stream)),
+              "copy");
+    return EDPC_OK;
+  });
+}
+
+edpc_status edpc_mutual_info(const float* d_z, size_t dz, const float* d_y, size_t dy, size_t c,
+                             uint32_t v, double* h_mi, int32_t* d_counts, float* d_eps,
+                             void* stream) {
+  return guarded([&] {
+    if (!d_z || !d_y || !h_mi) fail(EDPC_E_INVALID_ARG, "NULL argument");
+    *h_mi = mutual_info(d_z, dz, d_y, dy, c, v, d_counts, d_eps, S(stream));
+    return EDPC_OK;
+  });
+}
+
 edpc_status edpc_model_get_step(const edpc_model* mh, uint64_t* tau) {
   if (!mh || !tau) return set_err(EDPC_E_INVALID_ARG, "NULL argument");
   *tau = mh->m->tau;

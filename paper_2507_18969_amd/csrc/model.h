@@ -11,6 +11,10 @@
 
 namespace edpc {
 
+// Kraskov mutual-information estimate (ksg.hip); see edpc_mutual_info.
+double mutual_info(const float* d_z, size_t dz, const float* d_y, size_t dy, size_t c, uint32_t v,
+                   int32_t* d_counts, float* d_eps, hipStream_t s);
+
 // Thrown inside the library, turned into an edpc_status at the C boundary.
 struct Error {
   edpc_status status;
@@ -110,6 +114,7 @@ struct Model {
   std::vector<TensorInfo> tens;
   size_t P = 0;  // shared parameter count (with alignment padding)
   uint64_t tau = 0;
+  int last_rows = 0;  // rows of the last step (activation read-back)
 
   // device state
   float *param = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr;
@@ -195,6 +200,9 @@ struct Model {
   void setup_fused(hipStream_t s);
   void autotune(hipStream_t s);
   static KernelConfig default_config(const edpc_config& c, size_t rows);
+  // FP32 input of refinement block j (j = N: the head's input) of the last
+  // step, [last_rows, F]; null where the launch sequence keeps none.
+  const float* block_input(int j) const;
   static void validate(const edpc_config& c);
 
  private:

@@ -730,9 +730,16 @@ void Model::product(int ps, int j, int R, hipStream_t s) {
   }
 }
 
+const float* Model::block_input(int j) const {
+  if (j < 0 || j > N) return nullptr;
+  if (kc.fused && j == N) return nullptr;  // the row-block step keeps only a BF16 copy
+  return Hs[j];
+}
+
 void Model::step(StepMode mode, const StreamIO& io, const StepOutputs& out, int grid_rows,
                  hipStream_t s) {
   const int R = grid_rows;
+  last_rows = grid_rows;
   // ---- forward: Eq. 1 through Eqs. 14-16 and 9-13 -------------------------
   const bool backward = out.backward || out.update || out.keep_fdm_grad;
   HeadArgs ha;
