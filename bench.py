@@ -341,6 +341,48 @@ def stream_job(torch, E, chunk=4096, precision="bf16"):
     return res
 
 
+def ifr_analysis(torch, E, train_steps=512, rows=1024, v=3):
+    """The information-flow analysis of Sec. 3.1.1 on synthetic data: models
+    with k = 1, 2, 3 branches per refinement block (context 16, embed 16,
+    latent 64, 2 blocks x hidden 128, FP32) are trained online for
+    `train_steps` steps over `rows` streams of the ragged mixture (the same
+    update as the codec), then each block's I(S; S + X^(k)) is estimated on
+    the next step's batch (Kraskov, v neighbours, one sample per stream) and
+    IFR_{k1->k2} = I^(k1) / I^(k2) (Eq. 8) is formed per block."""
+    import gen
+    base = dict(gen.WORKLOADS["small"].model)
+    C = base["context"]
+    data, lens = gen.make_streams("ragged", prefix=C + train_steps + 1, n_streams=rows)
+    st = np.frombuffer(data.tobytes(), dtype=np.uint8).reshape(rows, -1)
+    slots = np.arange(rows)
+    out = {"model": "context 16, embed 16, latent 64, 2 blocks x hidden 128, FP32",
+           "train_steps": train_steps, "samples": rows, "neighbours": v,
+           "source": "ragged mixture (Markov, uniform, runs, sine), first bytes of each stream"}
+    mi = {}
+    for k in (1, 2, 3):
+        keys = ("context", "embed", "latent", "blocks", "hidden", "lr", "beta1", "beta2", "eps",
+                "seed")
+        cfg = E.edpc_config_default(precision="fp32", branches=k, **{x: base[x] for x in keys})
+        m = E.Model(cfg, rows, rows)
+        t0 = time.perf_counter()
+        for i in range(C, C + train_steps):
+            m.edpc_model_step(torch.as_tensor(np.ascontiguousarray(st[:, i - C:i])).to("cuda"),
+                              torch.as_tensor(np.ascontiguousarray(st[:, i])).to("cuda"), slots,
+                              flags=E.EDPC_STEP_UPDATE)
+        torch.cuda.synchronize()
+        i = C + train_steps
+        ctx = torch.as_tensor(np.ascontiguousarray(st[:, i - C:i])).to("cuda")
+        tgt = torch.as_tensor(np.ascontiguousarray(st[:, i])).to("cuda")
+        mi[k] = E.block_mutual_info(m, ctx, tgt, slots, v)
+        out[f"k{k}"] = {"mi_nats_per_block": [round(x, 5) for x in mi[k]],
+                        "train_s": round(time.perf_counter() - t0, 2)}
+        del m
+    for a, b in ((1, 2), (1, 3), (2, 3)):
+        out[f"IFR_{a}to{b}"] = [round(x / y, 4) for x, y in zip(mi[a], mi[b])]
+    log(f"ifr: {out}")
+    return out
+
+
 GOLDEN_FILE = os.path.join(ROOT, "tests", "golden", "oracle_sizes.json")
 
 
@@ -387,6 +429,9 @@ ABLATIONS = (
     ("low_rank", {"low_rank": True}),
     ("k3", {"branches": 3}),
     ("one_block", {"blocks": 1}),
+    # the base model on the layer-by-layer products, so that the speed column
+    # compares the variants (which all run layer by layer) like with like
+    ("base_layerwise", {"layerwise": True}),
 )
 
 
@@ -397,14 +442,20 @@ def ablation_cfg(E, base, over, precision):
             "beta2", "eps", "seed")
     return E.edpc_config_default(precision=precision, autotune=True,
                                  lte=m.get("lte", True), low_rank=m.get("low_rank", False),
+                                 layerwise=m.get("layerwise", False),
                                  **{k: m[k] for k in keys})
 
 
-def ablation_workload(torch, E, warmup, steps, precision="bf16"):
-    """Encoder steady-state rate and device memory of the Table 4 variants on one
-    model (context 16, embed 16, latent 64, 2 blocks x hidden 128, k = 2) over the
-    1024-stream order-2 Markov input (prefixes).  Memory is what the session holds
-    on the device (free-memory drop from begin to after the first steps)."""
+def ablation_workload(torch, E, warmup, steps, precision="bf16", ratio_bytes=1024):
+    """The Table 4 variants on one model (context 16, embed 16, latent 64,
+    2 blocks x hidden 128, k = 2), each with
+    * speed: encoder steady state over the 1024-stream order-2 Markov input;
+    * memory: the session's device memory (free-memory drop from begin to
+      after the first steps);
+    * ratio: bits/byte of a whole encode of 1024 streams of the ragged
+      mixture cut to `ratio_bytes` bytes (a source the model partly learns),
+      and of the 64-stream x 256-byte mixture prefix whose oracle size is
+      stored (tests/golden/oracle_sizes.json, ablation_* cases)."""
     import gen
     w = gen.WORKLOADS["mid_bf16"]
     base = dict(gen.WORKLOADS["small"].model)
@@ -414,8 +465,13 @@ def ablation_workload(torch, E, warmup, steps, precision="bf16"):
     data, lens = gen.make_streams(w, prefix=prefix)
     d_in = torch.as_tensor(data).to("cuda")
     rows = int((lens > C + warmup).sum())
+    mdata, mlens = gen.make_streams("ragged", prefix=ratio_bytes, n_streams=1024)
+    d_mix = torch.as_tensor(mdata).to("cuda")
+    with open(GOLDEN_FILE) as f:
+        gold = json.load(f)
     out = {"model": "context 16, embed 16, latent 64, 2 blocks x hidden 128, k = 2",
-           "streams": int(len(lens)), "precision": precision}
+           "streams": int(len(lens)), "precision": precision,
+           "ratio_input": f"1024 mixture streams x {ratio_bytes} B"}
     for name, over in ABLATIONS:
         cfg = ablation_cfg(E, base, over, precision)
         torch.cuda.synchronize()
@@ -426,12 +482,26 @@ def ablation_workload(torch, E, warmup, steps, precision="bf16"):
         kern = enc.edpc_session_time_kernels(4)
         enc.edpc_session_destroy()
         torch.cuda.synchronize()
+        cont = E.edpc_encode(cfg, d_mix, mlens)
+        torch.cuda.synchronize()
+        bpb = 8.0 * (cont.numel() - (96 + 20 * len(mlens))) / mlens.sum()
         out[name] = {"encode_MBps": round(done * rows / (ms * 1e-3) / 1e6, 4),
                      "ms_per_step": round(ms / done, 4), "steps": int(done),
                      "session_MB": round((free0 - free1) / 1e6, 1),
-                     "row_block_step": kern["fused_rowblock_step"][1] > 0}
+                     "row_block_step": kern["fused_rowblock_step"][1] > 0,
+                     "bits_per_byte": round(bpb, 4)}
+        g = gold.get("ablation_" + name.replace("_layerwise", ""))
+        if g:
+            gd, gl = gen.make_streams(g["workload"], prefix=g["prefix"], n_streams=g["n_streams"])
+            c2 = E.edpc_encode(cfg, torch.as_tensor(gd).to("cuda"), gl)
+            torch.cuda.synchronize()
+            pay = c2.numel() - (96 + 20 * len(gl))
+            o = sum(g["payload_bytes"])
+            out[name]["prefix_bits_per_byte"] = round(8.0 * pay / gl.sum(), 4)
+            out[name]["prefix_oracle_bits_per_byte"] = round(8.0 * o / gl.sum(), 4)
+            out[name]["prefix_rel_diff"] = round((pay - o) / o, 6)
         log(f"ablation {name}: {out[name]}")
-    del d_in
+    del d_in, d_mix
     torch.cuda.empty_cache()
     return out
 
@@ -547,6 +617,8 @@ def run_extra(torch, E, a):
             extra[name] = ragged_full_job(torch, E)
         elif name == "stream":
             extra[name] = stream_job(torch, E)
+        elif name == "ifr":
+            extra[name] = ifr_analysis(torch, E)
         else:
             extra[name] = extra_workload(torch, E, name, a.warmup, min(a.steps, 200))
     return extra
@@ -566,7 +638,7 @@ def main():
                          "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE readings)")
     ap.add_argument("--extra", default="",
                     help="comma list of further workloads measured after the main one "
-                         "(ragged, ragged_full, large, stream, ablations); reported under "
+                         "(ragged, ragged_full, large, stream, ifr, ablations); reported under "
                          "extra_workloads")
     ap.add_argument("--no-size-parity", action="store_true",
                     help="skip the compressed-size comparison with the oracle's stored sizes")

@@ -18,6 +18,9 @@ Cases:
   skewed_mid_64   the skewed source, 64 streams x 512 B, mid model
   skewed_wide     the skewed source, 1024 streams x 256 B, mid model (the
                   1024-row launch of the benchmarked configuration)
+  ablation_*      the Table 4 / 5 variants (base, w/o LTE, low-rank, three
+                  branches, one block) of the small model on 64 mixture
+                  streams cut to 256 bytes
 """
 
 from __future__ import annotations
@@ -59,6 +62,20 @@ CASES = {
     "skewed_mid_64": ("skewed_mid", 512, 64, {}),
     "skewed_wide": ("skewed_mid", 256, None, {}),
 }
+
+# Table 4 / Table 5 variants on the small model, 64 streams of the ragged
+# mixture cut to 256 bytes: base, w/o LTE (per-stream F x F FDM), per-stream
+# low-rank factors, three branches, one block
+_ABL_BASE = dict(context=16, embed=16, latent=64, blocks=2, hidden=128)
+ABLATION_CASES = {
+    "base": {},
+    "wo_lte": {"latent": 256, "lte": False},
+    "low_rank": {"low_rank": True},
+    "k3": {"branches": 3},
+    "one_block": {"blocks": 1},
+}
+for _name, _over in ABLATION_CASES.items():
+    CASES["ablation_" + _name] = ("ragged", 256, 64, dict(_ABL_BASE, **_over))
 
 
 def case_input(name):

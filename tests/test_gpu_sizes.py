@@ -15,7 +15,10 @@ make_oracle_golden.py (which calls only oracle/) on the same seeded inputs:
 * ragged_wide: all 4096 streams of the ragged mixture workload cut to 96
   bytes (every row block of the 4096-row launch);
 * small_zero_lr, mid_slice, ragged_prefix: the static model, a 4 x 512 slice
-  and 32 ragged mixture streams.
+  and 32 ragged mixture streams;
+* ablation_*: the Table 4 / 5 variants of the small model (base, w/o LTE,
+  per-stream low-rank factors, three branches, one block) on 64 mixture
+  streams x 256 B.
 
 By causality a prefix in time codes exactly like the start of the full job.
 """
@@ -61,26 +64,32 @@ def _encode(E, cfg, data, lens):
     return cont
 
 
-# (golden case, precision, layer-by-layer BF16 products)
+# (golden case, precision, layer-by-layer BF16 products, row-block step expected)
 CASES = [
-    ("mid_prefix", "bf16", False), ("mid_prefix", "fp32", False),
-    ("skewed_small", "fp32", False), ("skewed_small", "bf16", False),
-    ("skewed_mid_64", "fp32", False), ("skewed_mid_64", "bf16", False),
-    ("skewed_mid_64", "bf16", True),
-    ("skewed_wide", "bf16", False), ("skewed_wide", "fp32", False),
-    ("ragged_wide", "bf16", False),
-    ("small_zero_lr", "fp32", False), ("mid_slice", "fp32", False),
-    ("mid_slice", "bf16", False), ("ragged_prefix", "bf16", False),
+    ("mid_prefix", "bf16", False, True), ("mid_prefix", "fp32", False, False),
+    ("skewed_small", "fp32", False, False), ("skewed_small", "bf16", False, True),
+    ("skewed_mid_64", "fp32", False, False), ("skewed_mid_64", "bf16", False, True),
+    ("skewed_mid_64", "bf16", True, False),
+    ("skewed_wide", "bf16", False, True), ("skewed_wide", "fp32", False, False),
+    ("ragged_wide", "bf16", False, True),
+    ("small_zero_lr", "fp32", False, False), ("mid_slice", "fp32", False, False),
+    ("mid_slice", "bf16", False, True), ("ragged_prefix", "bf16", False, True),
+    # the Table 4 / 5 variants (64 mixture streams x 256 B); only the base and
+    # one-block models have the row-block step
+    ("ablation_base", "fp32", False, False), ("ablation_base", "bf16", False, True),
+    ("ablation_wo_lte", "fp32", False, False), ("ablation_wo_lte", "bf16", False, False),
+    ("ablation_low_rank", "fp32", False, False), ("ablation_low_rank", "bf16", False, False),
+    ("ablation_k3", "fp32", False, False), ("ablation_k3", "bf16", False, False),
+    ("ablation_one_block", "fp32", False, False), ("ablation_one_block", "bf16", False, True),
 ]
 
 
-@pytest.mark.parametrize("case,precision,layerwise", CASES)
-def test_size_parity_and_roundtrip(E, case, precision, layerwise):
+@pytest.mark.parametrize("case,precision,layerwise,fused_expected", CASES)
+def test_size_parity_and_roundtrip(E, case, precision, layerwise, fused_expected):
     data, lens, model = case_input(case)
     cfg = lib_cfg(E, model, precision, layerwise=layerwise)
     cont = _encode(E, cfg, data, lens)
     kid = int.from_bytes(cont[76:84].cpu().numpy().tobytes(), "little")
-    fused_expected = precision == "bf16" and not layerwise
     assert (kid >> 47) & 1 == int(fused_expected)
     raw = cont.cpu().numpy().tobytes()
     got_lens, pays = parse_container(raw)
