@@ -39,7 +39,7 @@ def state():
     return om, st[:, pos - C:pos].copy(), st[:, pos].copy()
 
 
-def _fd(om, ctx, tgt, name, idx, eps=1e-3):
+def _fd(om, ctx, tgt, name, idx, eps=1e-4):
     slots = np.arange(ROWS)
     arr = om.U if name == "U" else om.p[name]
     flat = arr.reshape(-1)
@@ -68,6 +68,11 @@ def test_step_function_gradients_vs_finite_differences(E, state, precision, rtol
     loss = E.StepFunction.apply(m, d_ctx, d_tgt, np.arange(ROWS), *tensors)
     (2.0 * loss).backward()  # the incoming gradient scales the adjoint
     c = om.forward(ctx.astype(np.int64), np.arange(ROWS))
+    # loss = mean of -ln p_x; to first order |d loss| <= 2 max_v |dz_v|.  BF16:
+    # a chain of D = 2 N + 3 = 11 BF16 products with 8-bit operands gives
+    # |dz| up to sqrt(D) 2^-8 max|z| ~ 0.09 at this state (max|z| 7.1), 0.18
+    # on the loss; 2e-2 is nine times tighter than that first-order bound.
+    # FP32: the same chain at 2^-24 over K = 512-term sums gives ~1e-5.
     lt = 1e-4 if precision == "fp32" else 2e-2
     assert abs(loss.item() - OModel.loss(c, tgt.astype(np.int64))) < lt
     g_or, dU = om.backward(c, tgt.astype(np.int64))
@@ -84,10 +89,12 @@ def test_step_function_gradients_vs_finite_differences(E, state, precision, rtol
         idx = np.union1d(idx, np.argsort(-np.abs(go))[:8])  # include the largest entries
         fd = np.array([_fd(om, ctx64, tgt64, name, int(i)) for i in idx])
         scale = np.abs(go).max() + 1e-12
-        # the oracle's adjoint against its own central differences (eps 1e-3:
-        # truncation error of order eps^2 times the third derivative)
+        # the oracle's adjoint against its own central differences: the error
+        # is the truncation eps^2 / 6 times the third derivative (measured
+        # 1.3e-5 of the scale at eps 1e-3 and 1.3e-7 at 1e-4, as eps^2
+        # predicts); FP64 cancellation adds ~ |loss| 2^-52 / eps = 3e-12
         fd_err = np.abs(fd - go[idx]).max() / scale
-        assert fd_err <= 1e-4, (name, fd_err)
+        assert fd_err <= 1e-6, (name, fd_err)
         # the GPU adjoint against the oracle's adjoint and the differences
         err = np.abs(gg[idx] - go[idx]).max() / scale
         assert err <= rtol, (name, err)
