@@ -15,7 +15,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libedpc.so")
+# EDPC_LIB names another build of the same library (the host-sanitizer build
+# of build.py --sanitize); by default the in-tree libedpc.so is loaded
+LIB_PATH = os.environ.get("EDPC_LIB") or os.path.join(_HERE, "libedpc.so")
 
 EDPC_OK = 0
 STATUS = {0: "EDPC_OK", -1: "EDPC_E_INVALID_ARG", -2: "EDPC_E_NOMEM", -3: "EDPC_E_CAPACITY",

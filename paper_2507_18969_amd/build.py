@@ -3,6 +3,10 @@
 Usage: python -m paper_2507_18969_amd.build [--jobs N]
 Every translation unit under csrc/ is compiled to an object in _build/ and
 linked into paper_2507_18969_amd/libedpc.so.
+
+With --sanitize the host code (not the device code) is compiled with
+AddressSanitizer and UndefinedBehaviorSanitizer into _build/sanitize/libedpc.so,
+for host-only tests run with the ASan runtime preloaded (EDPC_LIB names it).
 """
 
 from __future__ import annotations
@@ -31,36 +35,57 @@ FLAGS = [
 ]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+# host-side sanitizers only: every -fsanitize sits behind -Xarch_host, so the
+# gfx950 code object is built exactly as in the product library
+SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer",
+            "-Xarch_host", "-g"]
+SAN_BUILD = os.path.join(BUILD, "sanitize")
+SAN_LIB = os.path.join(SAN_BUILD, "libedpc.so")
+
+
+def asan_runtime() -> str:
+    """Path of the compiler's ASan runtime (to preload into a host process)."""
+    r = subprocess.run([HIPCC, "-print-file-name=libclang_rt.asan-x86_64.so"],
+                       capture_output=True, text=True)
+    return r.stdout.strip()
+
+
+def _compile(src: str, sanitize: bool = False) -> str:
+    out = SAN_BUILD if sanitize else BUILD
+    obj = os.path.join(out, os.path.splitext(src)[0] + ".o")
+    cmd = [HIPCC, *FLAGS, *(SANITIZE if sanitize else []), "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr}")
     return obj
 
 
-def build(jobs: int = 5, verbose: bool = True) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+def build(jobs: int = 5, verbose: bool = True, sanitize: bool = False) -> str:
+    os.makedirs(SAN_BUILD if sanitize else BUILD, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
+        objs = list(ex.map(lambda src: _compile(src, sanitize), SOURCES))
+    lib = SAN_LIB if sanitize else LIB
+    tmp = lib + ".tmp"
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *(SANITIZE if sanitize else []),
+           *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     if verbose:
-        print(f"built {LIB}")
-    return LIB
+        print(f"built {lib}")
+    return lib
 
 
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=5)
+    ap.add_argument("--sanitize", action="store_true",
+                    help="host ASan + UBSan build into _build/sanitize/libedpc.so")
     a = ap.parse_args()
     try:
-        build(a.jobs)
+        build(a.jobs, sanitize=a.sanitize)
     except RuntimeError as e:
         print(e, file=sys.stderr)
         sys.exit(1)

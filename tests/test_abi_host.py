@@ -184,3 +184,66 @@ def test_config_flags_for_launch_choices():
     c.flags |= 0x40
     with pytest.raises(E.EdpcError):
         E.edpc_config_validate(c)
+
+
+def _exact_buffer(data: bytes):
+    """A malloc'd copy of exactly len(data) bytes (so a read past its end is
+    a heap overflow that the sanitizer build reports)."""
+    import ctypes
+    libc = ctypes.CDLL(None)
+    libc.malloc.restype = ctypes.c_void_p
+    libc.malloc.argtypes = [ctypes.c_size_t]
+    libc.free.argtypes = [ctypes.c_void_p]
+    p = libc.malloc(max(len(data), 1))
+    ctypes.memmove(p, data, len(data))
+    return p, libc
+
+
+def test_decode_info_survives_mutated_headers():
+    # random field corruptions with the header CRC recomputed (so parsing gets
+    # past the checksum) and random truncations: every call either succeeds
+    # with a consistent result or reports a documented error
+    import ctypes
+    r = np.random.default_rng(11)
+    for it in range(600):
+        n = int(r.integers(1, 6))
+        lens = [int(x) for x in r.integers(0, 1 << 20, size=n)]
+        pays = [min(2 * l + 2, int(r.integers(0, 2 * l + 3))) if l else 0 for l in lens]
+        h = bytearray(_header(lens, pays, [0] * n))
+        for _ in range(int(r.integers(1, 4))):
+            h[int(r.integers(0, len(h) - 4))] = int(r.integers(0, 256))
+        struct.pack_into("<I", h, len(h) - 4, zlib.crc32(bytes(h[:-4])))
+        cut = len(h) if r.random() < 0.7 else int(r.integers(0, len(h)))
+        p, libc = _exact_buffer(bytes(h[:cut]))
+        try:
+            cfg = E.edpc_config()
+            cnt, hl, dl = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+            st = E.lib().edpc_decode_info(ctypes.c_void_p(p), cut, ctypes.byref(cfg), ctypes.byref(cnt),
+                                          None, 0, ctypes.byref(hl), ctypes.byref(dl))
+            assert st in (0, -1, -4, -5, -6), (it, st)
+            if st == 0:
+                assert hl.value <= cut and cnt.value == (hl.value - 96) // 20
+        finally:
+            libc.free(ctypes.c_void_p(p))
+
+
+def test_host_decoder_reads_only_its_payload():
+    # random payloads of every short length against peaked and flat CDFs: the
+    # host decoder stops at in_len (garbage in, symbols out, no overread)
+    import ctypes
+    r = np.random.default_rng(12)
+    for it in range(300):
+        n = int(r.integers(1, 40))
+        z = r.standard_normal((n, 256)) * r.choice([0.5, 8.0, 30.0])
+        p = np.exp(z - z.max(1, keepdims=True))
+        p /= p.sum(1, keepdims=True)
+        cum = np.ascontiguousarray(cumulative(quantize(p)), dtype=np.uint32)
+        pay = r.integers(0, 256, size=int(r.integers(0, 12)), dtype=np.uint8).tobytes()
+        buf, libc = _exact_buffer(pay)
+        sym = np.zeros(n, dtype=np.uint8)
+        try:
+            st = E.lib().edpc_rc_decode_host(cum.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(buf),
+                                             len(pay), n, sym.ctypes.data_as(ctypes.c_void_p))
+            assert st == 0
+        finally:
+            libc.free(ctypes.c_void_p(buf))
