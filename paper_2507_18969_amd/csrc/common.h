@@ -100,6 +100,15 @@ __device__ __forceinline__ uint4 ld_global16(const void* p) {
 __device__ __forceinline__ void st_global16(void* p, uint4 x) {
   *(__attribute__((address_space(1))) u32x4*)p = __builtin_bit_cast(u32x4, x);
 }
+// A 16-byte load issued unconditionally: where `ok` is false it reads 16
+// zero bytes kept in device memory.  With no branch around the load and no
+// select after it, the compiler counts outstanding loads exactly and needs
+// the data only where it is consumed, so tiles staged ahead stay in flight
+// under the matrix products instead of being waited for right away.
+__device__ __align__(16) static const uint32_t kZero16[4] = {0u, 0u, 0u, 0u};
+__device__ __forceinline__ uint4 ld_global16_or_zero(const void* p, bool ok) {
+  return ld_global16(ok ? p : (const void*)kZero16);
+}
 
 // p[0] + p[stride] + ... + p[(n-1) stride], added strictly in index order;
 // the loads are issued 32 at a time so their latencies overlap (slots past n

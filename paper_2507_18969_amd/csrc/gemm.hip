@@ -109,10 +109,8 @@ struct Stage {
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
           const int gk = k0 + kb * 8 + i;
-          uint4 val = make_uint4(0, 0, 0, 0);
-          if (b < NBLK && gr < rows_valid && gk < K)
-            val = ld_global16(src + ((long long)gk * ld + gr) * esz);
-          reg[8 * p + i] = val;
+          reg[8 * p + i] = ld_global16_or_zero(src + ((long long)gk * ld + gr) * esz,
+                                               b < NBLK && gr < rows_valid && gk < K);
         }
       }
       return;
@@ -120,21 +118,17 @@ struct Stage {
 #pragma unroll
     for (int p = 0; p < PER_THREAD; ++p) {
       const int v = threadIdx.x + p * kThreads;
-      uint4 val = make_uint4(0, 0, 0, 0);
-      if (v < NVEC) {
-        if constexpr (KMAJOR) {
-          const int row = v / (BK / VEC), kq = v % (BK / VEC);
-          const int gr = row0 + row, gk = k0 + kq * VEC;
-          if (gr < rows_valid && gk < K)
-            val = ld_global16(src + ((long long)gr * ld + gk) * esz);
-        } else {
-          const int k = v / (ROWS / VEC), rq = v % (ROWS / VEC);
-          const int gr = row0 + rq * VEC, gk = k0 + k;
-          if (gr < rows_valid && gk < K)
-            val = ld_global16(src + ((long long)gk * ld + gr) * esz);
-        }
+      if constexpr (KMAJOR) {
+        const int row = v / (BK / VEC), kq = v % (BK / VEC);
+        const int gr = row0 + row, gk = k0 + kq * VEC;
+        reg[p] = ld_global16_or_zero(src + ((long long)gr * ld + gk) * esz,
+                                     v < NVEC && gr < rows_valid && gk < K);
+      } else {
+        const int k = v / (ROWS / VEC), rq = v % (ROWS / VEC);
+        const int gr = row0 + rq * VEC, gk = k0 + k;
+        reg[p] = ld_global16_or_zero(src + ((long long)gk * ld + gr) * esz,
+                                     v < NVEC && gr < rows_valid && gk < K);
       }
-      reg[p] = val;
     }
   }
 
@@ -257,6 +251,9 @@ struct TileCompute {
               sb[q][b].template load<BKM>((const char*)B + b * bstride * esz, ldb, n0, N,
                                           kq + ST * BK, K);
           }
+          // keep the loads' consumers (the transposes of the next stores)
+          // below the products, so that the loads stay in flight under them
+          __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
           for (int kk = 0; kk < BK; kk += Op::KSTEP) {
             typename Op::Frag fa[TM];
