@@ -570,6 +570,32 @@ def fused_roofline(w, kern, rows, precision):
             "algorithmic_flops_per_launch": flops, "avg_launch_us": round(per_launch_s * 1e6, 2)}
 
 
+# Per-CU limit on L2 reads in flight and the mean L2 read latency the
+# row-block kernel sees (rocprofv3 TCP_TCC_READ_REQ(_LATENCY) counters of the
+# 1024-stream BF16 step): the rate at which one CU can stream operands from L2.
+CU_L2_READS_IN_FLIGHT = 64
+CU_L2_READ_LATENCY_CYCLES = 290
+CLOCK_GHZ = 2.4
+
+
+def fused_stream_bound(w, kern, rows):
+    """The bound the row-block kernel actually meets: every workgroup (one
+    per CU, 16 rows) streams each BF16 weight of its products twice (forward
+    and adjoint orientation) from L2, and a CU can keep only so many L2 reads
+    in flight.  Achieved = those bytes over the launch time, per CU clock."""
+    if w.precision != "bf16" or "fused_rowblock_step" not in kern:
+        return None
+    ms, launches = kern["fused_rowblock_step"]
+    per_launch_s = ms / launches * 1e-3
+    weight_bytes = 2 * 2 * dense_flops_per_row(w.model)  # two orientations x 2 bytes
+    achieved = weight_bytes / (per_launch_s * CLOCK_GHZ * 1e9)
+    limit = CU_L2_READS_IN_FLIGHT * 128 / CU_L2_READ_LATENCY_CYCLES
+    return {"kernel": "fused_rowblock_step", "bound": "per-CU L2 reads in flight",
+            "achieved": round(achieved, 2), "limit": round(limit, 2), "unit": "B/clk/CU",
+            "frac": round(achieved / limit, 3), "bytes_per_workgroup": weight_bytes,
+            "workgroups": (rows + 15) // 16}
+
+
 def dominant_roofline(w, kern, rows, precision):
     """Roofline of the kernel with the largest share of the step."""
     share = {k: v[0] for k, v in kern.items() if v[1]}
@@ -687,6 +713,7 @@ def main():
         "kernels_ms_per_step": kern,
         "roofline": dominant_roofline(w, r["kernels"], rows, main_p),
         "roofline_hbm": fdm_roofline(w, r["kernels"], rows),
+        "fused_stream_bound": fused_stream_bound(w, r["kernels"], rows),
     }
     if "bf16" in res and "fp32" in res:
         line["bf16_over_fp32_encode"] = round(res["bf16"]["encode"] / res["fp32"]["encode"], 3)
