@@ -634,7 +634,7 @@ def cpu_baseline(w, data, lens, n_model_steps):
 
 def run_extra(torch, E, a):
     extra = {}
-    for name in [x for x in a.extra.split(",") if x]:
+    for name in [x for x in a.extra.split(",") if x and x != "none"]:
         if name == "ablations":
             extra[name] = ablation_workload(torch, E, a.warmup, min(a.steps, 200))
         elif name == "large":
@@ -662,10 +662,11 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="after timing, run a 256 MiB device copy (the reference kernel for "
                          "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE readings)")
-    ap.add_argument("--extra", default="",
+    ap.add_argument("--extra", default="large",
                     help="comma list of further workloads measured after the main one "
-                         "(ragged, ragged_full, large, stream, ifr, ablations); reported under "
-                         "extra_workloads")
+                         "(ragged, ragged_full, large, stream, ifr, ablations; 'none' for "
+                         "none); reported under extra_workloads.  Default: the 16384-stream "
+                         "large model (encode and decode in both precisions, about 10 s)")
     ap.add_argument("--no-size-parity", action="store_true",
                     help="skip the compressed-size comparison with the oracle's stored sizes")
     ap.add_argument("--only-extra", action="store_true",
