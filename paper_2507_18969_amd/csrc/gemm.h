@@ -106,12 +106,23 @@ bool wide_tile_supported(int tile, bool bf16, EpiKind epi, int nb);
 // matrices (1..3) for the gated products.
 hipError_t launch_gemm(int tile, bool bf16, bool a_kmajor, bool b_kmajor, EpiKind epi, int nb,
                        const GemmArgs& g, int grid_m_max, hipStream_t s);
+// `part`: scratch of wgrad_part_floats(tile) floats for the balanced launch of
+// wide tiles (used when a table has at least kWgradRanges tiles), or null.
 hipError_t launch_wgrad(int tile, bool bf16, const WgradProblem* d_probs, int n_probs,
-                        int total_tiles, const StepState* st, hipStream_t s);
+                        int total_tiles, const StepState* st, float* part, hipStream_t s);
 // Wide tiles (gemm_wide.hip), reached through the two launchers above.
 hipError_t launch_gemm_wide(int tile, bool a_kmajor, bool b_kmajor, EpiKind epi, int nb,
                             const GemmArgs& g, int grid_m_max, hipStream_t s);
 hipError_t launch_wgrad_wide(int tile, const WgradProblem* d_probs, int n_probs, int total_tiles,
-                             const StepState* st, hipStream_t s);
+                             const StepState* st, float* part, hipStream_t s);
+
+// Weight gradients of wide tiles with at least this many tiles run as this
+// many equal ranges of K chunks (one work-group each, one per CU of the
+// part), with tiles cut by a range boundary summed in two parts.
+constexpr int kWgradRanges = 256;
+inline size_t wgrad_part_floats(int tile) {
+  const TileShape t = tile_shape(tile);
+  return 2 * (size_t)(kWgradRanges - 1) * t.bm * t.bn;
+}
 
 }  // namespace edpc

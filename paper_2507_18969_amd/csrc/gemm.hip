@@ -469,10 +469,10 @@ static hipError_t launch_wp(int tile, const WgradProblem* p, int n, int tt, cons
 }
 
 hipError_t launch_wgrad(int tile, bool bf16, const WgradProblem* d_probs, int n_probs,
-                        int total_tiles, const StepState* st, hipStream_t s) {
+                        int total_tiles, const StepState* st, float* part, hipStream_t s) {
   if (tile >= TILE_W128x128) {
     if (!bf16) return hipErrorInvalidValue;
-    return launch_wgrad_wide(tile, d_probs, n_probs, total_tiles, st, s);
+    return launch_wgrad_wide(tile, d_probs, n_probs, total_tiles, st, part, s);
   }
   return bf16 ? launch_wp<true>(tile, d_probs, n_probs, total_tiles, st, s)
               : launch_wp<false>(tile, d_probs, n_probs, total_tiles, st, s);

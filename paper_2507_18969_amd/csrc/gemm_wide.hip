@@ -133,10 +133,11 @@ struct WideCompute {
   typedef f32x16 Acc;
   Acc acc[T::TM][T::TN];
 
-  // A rows [m0, m0 + BM) valid below M; B rows as WideStage; K in chunks.
+  // A rows [m0, m0 + BM) valid below M; B rows as WideStage; k in [kb, K)
+  // in chunks of 64 from kb.
   __device__ __forceinline__ void run(const bf16_t* A, int lda, int m0, int M, const bf16_t* B,
                                       int ldb, int b0, int blim0, int bhalf, int b1, int blim1,
-                                      int K, char* smem) {
+                                      int kb, int K, char* smem) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int wm = wave / T::WN, wn = wave % T::WN;
@@ -151,9 +152,9 @@ struct WideCompute {
     auto lds_b = [&](int s) { return lds + s * (T::LDS_A + T::LDS_B) + T::LDS_A; };
     WideStage<T::BM, AK> sa;
     WideStage<T::BN, BKM> sb;
-    const int nchunks = (K + kWideBK - 1) / kWideBK;
-    sa.load(A, lda, m0, M, T::BM, 0, 0, 0, K);
-    sb.load(B, ldb, b0, blim0, bhalf, b1, blim1, 0, K);
+    const int nchunks = (K - kb + kWideBK - 1) / kWideBK;
+    sa.load(A, lda, m0, M, T::BM, 0, 0, kb, K);
+    sb.load(B, ldb, b0, blim0, bhalf, b1, blim1, kb, K);
     sa.store(lds_a(0));
     sb.store(lds_b(0));
     __syncthreads();
@@ -162,8 +163,8 @@ struct WideCompute {
     for (int c = 0; c < nchunks; ++c) {
       const bool more = c + 1 < nchunks;
       if (more) {
-        sa.load(A, lda, m0, M, T::BM, 0, 0, (c + 1) * kWideBK, K);
-        sb.load(B, ldb, b0, blim0, bhalf, b1, blim1, (c + 1) * kWideBK, K);
+        sa.load(A, lda, m0, M, T::BM, 0, 0, kb + (c + 1) * kWideBK, K);
+        sb.load(B, ldb, b0, blim0, bhalf, b1, blim1, kb + (c + 1) * kWideBK, K);
       }
       const bf16_t* la = lds_a(c & 1);
       const bf16_t* lb = lds_b(c & 1);
@@ -366,13 +367,26 @@ __global__ void __launch_bounds__(kWideThreads) gemm_wide_kernel(GemmArgs g) {
     n0 = tx * (T::BN / 2);
     const int bro = (int)(g.b_branch_stride / g.ldb);  // rows between the branch matrices
     wc.run((const bf16_t*)g.A, g.lda, m0, M, (const bf16_t*)g.B, g.ldb, n0, N, T::BN / 2,
-           bro + n0, bro + N, K, smem);
+           bro + n0, bro + N, 0, K, smem);
   } else {
     n0 = tx * T::BN;
-    wc.run((const bf16_t*)g.A, g.lda, m0, M, (const bf16_t*)g.B, g.ldb, n0, N, T::BN, 0, 0, K,
+    wc.run((const bf16_t*)g.A, g.lda, m0, M, (const bf16_t*)g.B, g.ldb, n0, N, T::BN, 0, 0, 0, K,
            smem);
   }
   wide_epilogue<T, EPI>(wc.acc, g, nullptr, m0, n0, M, N, smem);
+}
+
+// Problem and output origin of tile `tile` of a grouped weight-gradient table.
+template <class T>
+__device__ __forceinline__ WgradProblem wgrad_tile(const WgradProblem* __restrict__ probs,
+                                                   int n_probs, int tile, int* m0, int* n0) {
+  int p = 0;
+  while (p + 1 < n_probs && tile >= probs[p + 1].tile_begin) ++p;
+  const WgradProblem pr = probs[p];
+  const int t = tile - pr.tile_begin;
+  *m0 = (t / pr.tiles_n) * T::BM;
+  *n0 = (t % pr.tiles_n) * T::BN;
+  return pr;
 }
 
 // Weight gradients dW = dOut^T In over grouped problems (K = active rows).
@@ -380,18 +394,80 @@ template <class T>
 __global__ void __launch_bounds__(kWideThreads) wgrad_wide_kernel(const WgradProblem* __restrict__ probs,
                                                                   int n_probs, const StepState* st) {
   extern __shared__ __align__(16) char smem[];
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  int p = 0;
-  while (p + 1 < n_probs && tile >= probs[p + 1].tile_begin) ++p;
-  const WgradProblem pr = probs[p];
-  const int t = tile - pr.tile_begin;
-  const int m0 = (t / pr.tiles_n) * T::BM, n0 = (t % pr.tiles_n) * T::BN;
+  int m0, n0;
+  const WgradProblem pr = wgrad_tile<T>(probs, n_probs, xcd_tile(blockIdx.x, gridDim.x), &m0, &n0);
   const int K = st->rows;
   WideCompute<T, false, false> wc;
   wc.run((const bf16_t*)pr.dout, pr.M, m0, pr.M, (const bf16_t*)pr.in, pr.N, n0, pr.N, T::BN, 0,
-         0, K, smem);
+         0, 0, K, smem);
   GemmArgs unused;
   wide_epilogue<T, EPI_WGRAD_OUT>(wc.acc, unused, pr.dw, m0, n0, pr.M, pr.N, smem);
+}
+
+// The same products balanced over the CUs when there are more tiles than
+// CUs (one tile per work-group would leave most CUs idle for the last
+// round).  The K chunks of all tiles, in tile order, form kWgradRanges equal
+// ranges, one per work-group (XCD x takes a contiguous band of ranges, so
+// neighbouring tiles share its L2).  With at least as many tiles as ranges a
+// range boundary cuts a tile at most once: the work-group before boundary b
+// sums the tile's lower K chunks into scratch slot 2b, the one after it the
+// upper chunks into slot 2b + 1, and wgrad_fixup_kernel adds the two (lower
+// first).  Uncut tiles are summed exactly as by wgrad_wide_kernel.
+template <class T>
+__global__ void __launch_bounds__(kWideThreads) wgrad_wide_split_kernel(
+    const WgradProblem* __restrict__ probs, int n_probs, const StepState* st, int total_tiles,
+    float* __restrict__ part) {
+  extern __shared__ __align__(16) char smem[];
+  const int K = st->rows;
+  const long long nck = (K + kWideBK - 1) / kWideBK;
+  const long long U = (long long)total_tiles * nck;
+  const int w = xcd_tile(blockIdx.x, kWgradRanges);  // this work-group's range
+  long long u = (long long)w * U / kWgradRanges;
+  const long long u1 = (long long)(w + 1) * U / kWgradRanges;
+  GemmArgs unused;
+  while (u < u1) {
+    const int tile = (int)(u / nck);
+    const long long c0 = u % nck, c1 = min(nck, c0 + (u1 - u));
+    int m0, n0;
+    const WgradProblem pr = wgrad_tile<T>(probs, n_probs, tile, &m0, &n0);
+    WideCompute<T, false, false> wc;
+    wc.run((const bf16_t*)pr.dout, pr.M, m0, pr.M, (const bf16_t*)pr.in, pr.N, n0, pr.N, T::BN,
+           0, 0, (int)(c0 * kWideBK), (int)min((long long)K, c1 * kWideBK), smem);
+    if (c0 == 0 && c1 == nck) {
+      wide_epilogue<T, EPI_WGRAD_OUT>(wc.acc, unused, pr.dw, m0, n0, pr.M, pr.N, smem);
+    } else {  // lower part: boundary w follows; upper part: boundary w - 1 precedes
+      const long long slot = c0 == 0 ? 2LL * w : 2LL * (w - 1) + 1;
+      wide_epilogue<T, EPI_WGRAD_OUT>(wc.acc, unused, part + slot * (T::BM * T::BN), 0, 0, T::BM,
+                                      T::BN, smem);
+    }
+    u += c1 - c0;
+    __syncthreads();  // the epilogue's LDS before the next tile's staging
+  }
+}
+
+// dW of every tile cut by a range boundary = lower part + upper part.
+template <class T>
+__global__ void __launch_bounds__(256) wgrad_fixup_kernel(const WgradProblem* __restrict__ probs,
+                                                          int n_probs, const StepState* st,
+                                                          int total_tiles,
+                                                          const float* __restrict__ part) {
+  const int b = blockIdx.x;  // boundary between ranges b and b + 1
+  const long long nck = (st->rows + kWideBK - 1) / kWideBK;
+  if (nck == 0) return;  // no rows: the split kernel wrote nothing
+  const long long U = (long long)total_tiles * nck;
+  const long long ub = (long long)(b + 1) * U / kWgradRanges;
+  if (ub % nck == 0) return;  // at a tile edge: no tile was cut
+  int m0, n0;
+  const WgradProblem pr = wgrad_tile<T>(probs, n_probs, (int)(ub / nck), &m0, &n0);
+  const float* lo = part + (size_t)(2 * b) * (T::BM * T::BN);
+  const float* hi = lo + T::BM * T::BN;
+  for (int e = threadIdx.x; e < T::BM * T::BN / 4; e += 256) {
+    const int i = (4 * e) / T::BN, j = (4 * e) % T::BN;
+    const int m = m0 + i, n = n0 + j;
+    if (m >= pr.M || n >= pr.N) continue;  // N is a multiple of 4
+    const float4 x = ld4(lo + (size_t)i * T::BN + j), y = ld4(hi + (size_t)i * T::BN + j);
+    st4(pr.dw + (size_t)m * pr.N + n, make_float4(x.x + y.x, x.y + y.y, x.z + y.z, x.w + y.w));
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -448,14 +524,24 @@ hipError_t launch_gemm_wide(int tile, bool a_kmajor, bool b_kmajor, EpiKind epi,
 
 template <class T>
 static hipError_t launch_wgrad_wide_t(const WgradProblem* d_probs, int n_probs, int total_tiles,
-                                      const StepState* st, hipStream_t s) {
+                                      const StepState* st, float* part, hipStream_t s) {
   if (total_tiles == 0) return hipSuccess;
   static bool attr = false;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute((const void*)wgrad_wide_kernel<T>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, T::SMEM);
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void*)wgrad_wide_split_kernel<T>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, T::SMEM);
     if (e != hipSuccess) return e;
     attr = true;
+  }
+  if (part && total_tiles >= kWgradRanges) {
+    hipLaunchKernelGGL((wgrad_wide_split_kernel<T>), dim3(kWgradRanges), dim3(kWideThreads), T::SMEM,
+                       s, d_probs, n_probs, st, total_tiles, part);
+    hipLaunchKernelGGL((wgrad_fixup_kernel<T>), dim3(kWgradRanges - 1), dim3(256), 0, s, d_probs,
+                       n_probs, st, total_tiles, (const float*)part);
+    return hipGetLastError();
   }
   hipLaunchKernelGGL((wgrad_wide_kernel<T>), dim3(total_tiles), dim3(kWideThreads), T::SMEM, s,
                      d_probs, n_probs, st);
@@ -463,12 +549,12 @@ static hipError_t launch_wgrad_wide_t(const WgradProblem* d_probs, int n_probs, 
 }
 
 hipError_t launch_wgrad_wide(int tile, const WgradProblem* d_probs, int n_probs, int total_tiles,
-                             const StepState* st, hipStream_t s) {
+                             const StepState* st, float* part, hipStream_t s) {
   switch (tile) {
-    case TILE_W128x128: return launch_wgrad_wide_t<WideTile<128, 128, 4, false>>(d_probs, n_probs, total_tiles, st, s);
-    case TILE_W256x128: return launch_wgrad_wide_t<WideTile<256, 128, 4, false>>(d_probs, n_probs, total_tiles, st, s);
-    case TILE_W128x256: return launch_wgrad_wide_t<WideTile<128, 256, 2, false>>(d_probs, n_probs, total_tiles, st, s);
-    case TILE_W256x256: return launch_wgrad_wide_t<WideTile<256, 256, 2, false>>(d_probs, n_probs, total_tiles, st, s);
+    case TILE_W128x128: return launch_wgrad_wide_t<WideTile<128, 128, 4, false>>(d_probs, n_probs, total_tiles, st, part, s);
+    case TILE_W256x128: return launch_wgrad_wide_t<WideTile<256, 128, 4, false>>(d_probs, n_probs, total_tiles, st, part, s);
+    case TILE_W128x256: return launch_wgrad_wide_t<WideTile<128, 256, 2, false>>(d_probs, n_probs, total_tiles, st, part, s);
+    case TILE_W256x256: return launch_wgrad_wide_t<WideTile<256, 256, 2, false>>(d_probs, n_probs, total_tiles, st, part, s);
   }
   return hipErrorInvalidValue;
 }

@@ -41,7 +41,7 @@ enum ProductSlot : int {
 
 // Kernel configuration: one tile id per product slot, plus the numerics
 // revision of the kernels.  Encoded into 64 bits for the container.
-constexpr uint32_t kNumericsRevision = 4;
+constexpr uint32_t kNumericsRevision = 5;
 struct KernelConfig {
   int tile[PS_COUNT];
   bool fused = false;  // BF16 row-block fused step (bit 47 of the id)
@@ -144,6 +144,7 @@ struct Model {
     WgradProblem* d = nullptr;
     int n = 0, tiles = 0;
   } wg_tab[TILE_COUNT];
+  float* wg_part = nullptr;  // scratch of the balanced wide-tile weight-gradient launch
   ColsumJob* d_cs = nullptr;
   int n_cs = 0, cs_blocks = 0, cs_cols = 0;
   float* cs_partial = nullptr;

@@ -398,6 +398,12 @@ void Model::build_tables(hipStream_t s) {
                              hipMemcpyHostToDevice, s), "copy");
   }
 
+  size_t part_floats = 0;  // wide tiles with more tiles than the split launch's ranges
+  for (int tile = TILE_W128x128; tile < TILE_COUNT; ++tile)
+    if (bf16 && wg_tab[tile].tiles >= kWgradRanges)
+      part_floats = std::max(part_floats, wgrad_part_floats(tile));
+  if (part_floats) wg_part = dalloc<float>(part_floats);
+
   // column sums: bias gradients, LayerNorm affine gradients
   std::vector<ColsumJob> cs;
   auto addc = [&](const float* src, int cols, int ld, float* dst, const float* h,
@@ -723,7 +729,8 @@ void Model::product(int ps, int j, int R, hipStream_t s) {
       return gemm(ps, true, false, EPI_STORE, 1, g, R, s);
     case PS_WGRAD: {
       const WgTable& t = wg_tab[kc.tile[PS_WGRAD]];
-      TIMED(PS_WGRAD, hip_check(launch_wgrad(kc.tile[PS_WGRAD], bf16, t.d, t.n, t.tiles, st, s),
+      TIMED(PS_WGRAD, hip_check(launch_wgrad(kc.tile[PS_WGRAD], bf16, t.d, t.n, t.tiles, st,
+                                             wg_part, s),
                                 "wgrad launch"));
       return;
     }

@@ -92,7 +92,7 @@ def test_encode_bound():
         E.edpc_encode_bound(c, [])
 
 
-def _header(lens, pay_lens, crcs, cfg=None, version=1, kernel=4 << 48, arch=950):
+def _header(lens, pay_lens, crcs, cfg=None, version=1, kernel=5 << 48, arch=950):
     """Container header written from the documented layout (independent of
     the library's writer)."""
     c = cfg or E.edpc_config_default()

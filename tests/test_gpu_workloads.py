@@ -84,3 +84,40 @@ def test_large_prefix_roundtrip_bf16_vs_fp32_size(E):
         del cont, out
         torch.cuda.empty_cache()
     assert abs(sizes["bf16"] - sizes["fp32"]) / sizes["fp32"] <= 0.005
+
+
+def test_large_split_weight_gradients_match_one_pass_tiles(E):
+    # The large model's weight-gradient table has 312 wide 256 x 256 tiles,
+    # more than the 256 ranges of the balanced launch, so tiles cut by a
+    # range boundary are summed in two parts (lower K chunks first).  The
+    # 4-wave 128 x 64 tile sums every tile's K chunks in one pass with the
+    # same MFMA sequence: uncut entries must be bit-identical to it, cut ones
+    # within the rounding of the one extra addition.  320 rows = 5 chunks of
+    # 64 per tile, 1560 chunks in all, 6 or 7 per range.
+    banner("large split weight gradients, 320 rows")
+    rows, C = 320, LARGE["context"]
+    data, _ = gen.make_streams("large", prefix=C + 1, n_streams=rows)
+    st = np.frombuffer(data.tobytes(), dtype=np.uint8).reshape(rows, -1)
+    d_ctx = torch.as_tensor(st[:, :C].copy()).to("cuda")
+    d_tgt = torch.as_tensor(st[:, C].copy()).to("cuda")
+    cfg = lib_cfg(E, LARGE, "bf16")
+    rev = E.Model(cfg, 1, 1).edpc_model_kernel_id() >> 48
+    wide = (rev << 48) | sum(10 << (4 * i) for i in range(11))  # every product on w256x256
+    one_pass = (wide & ~(0xF << 40)) | (4 << 40)                  # weight gradients on 128 x 64
+    grads = {}
+    for name, kid in (("split", wide), ("one_pass", one_pass)):
+        m = E.Model(cfg, rows, rows, kid)
+        m.edpc_model_step(d_ctx, d_tgt, np.arange(rows), flags=E.EDPC_STEP_BACKWARD)
+        torch.cuda.synchronize()
+        grads[name] = {n: m.edpc_model_read(n, E.EDPC_KIND_GRAD) for n in m.names
+                       if n in ("wh", "w1", "w2") or (n.startswith("blk") and ".w" in n)}
+        del m
+        torch.cuda.empty_cache()
+    exact = total = 0
+    for n, a in grads["split"].items():
+        b = grads["one_pass"][n]
+        scale = np.abs(b).max() + 1e-30
+        assert np.abs(a - b).max() <= 1e-5 * scale, n
+        exact += int((a == b).sum())
+        total += a.size
+    assert exact >= total // 4 and exact < total, (exact, total)
