@@ -107,7 +107,8 @@ bool wide_tile_supported(int tile, bool bf16, EpiKind epi, int nb);
 hipError_t launch_gemm(int tile, bool bf16, bool a_kmajor, bool b_kmajor, EpiKind epi, int nb,
                        const GemmArgs& g, int grid_m_max, hipStream_t s);
 // `part`: scratch of wgrad_part_floats(tile) floats for the balanced launch of
-// wide tiles (used when a table has at least kWgradRanges tiles), or null.
+// wide tiles (taken when a table has at least kWgradRanges tiles), or null for
+// one work-group per tile.
 hipError_t launch_wgrad(int tile, bool bf16, const WgradProblem* d_probs, int n_probs,
                         int total_tiles, const StepState* st, float* part, hipStream_t s);
 // Wide tiles (gemm_wide.hip), reached through the two launchers above.
@@ -116,13 +117,13 @@ hipError_t launch_gemm_wide(int tile, bool a_kmajor, bool b_kmajor, EpiKind epi,
 hipError_t launch_wgrad_wide(int tile, const WgradProblem* d_probs, int n_probs, int total_tiles,
                              const StepState* st, float* part, hipStream_t s);
 
-// Weight gradients of wide tiles with at least this many tiles run as this
-// many equal ranges of K chunks (one work-group each, one per CU of the
-// part), with tiles cut by a range boundary summed in two parts.
+// Balanced weight gradients of wide tiles: this many equal ranges of K
+// chunks (one work-group each, one per CU of the part); tiles cut by range
+// boundaries are summed in parts, two scratch tiles per range.
 constexpr int kWgradRanges = 256;
 inline size_t wgrad_part_floats(int tile) {
   const TileShape t = tile_shape(tile);
-  return 2 * (size_t)(kWgradRanges - 1) * t.bm * t.bn;
+  return 2 * (size_t)kWgradRanges * t.bm * t.bn;
 }
 
 }  // namespace edpc

@@ -404,15 +404,18 @@ __global__ void __launch_bounds__(kWideThreads) wgrad_wide_kernel(const WgradPro
   wide_epilogue<T, EPI_WGRAD_OUT>(wc.acc, unused, pr.dw, m0, n0, pr.M, pr.N, smem);
 }
 
-// The same products balanced over the CUs when there are more tiles than
-// CUs (one tile per work-group would leave most CUs idle for the last
-// round).  The K chunks of all tiles, in tile order, form kWgradRanges equal
+// The same products balanced over the CUs, for tables with at least as many
+// tiles as CUs, where one work-group per tile leaves most CUs idle in the
+// last, short round of tiles (measured slower than one work-group per tile
+// for smaller tables, where the parts cost more than the shorter K loops
+// save).  The K chunks of all tiles, in tile order, form kWgradRanges equal
 // ranges, one per work-group (XCD x takes a contiguous band of ranges, so
-// neighbouring tiles share its L2).  With at least as many tiles as ranges a
-// range boundary cuts a tile at most once: the work-group before boundary b
-// sums the tile's lower K chunks into scratch slot 2b, the one after it the
-// upper chunks into slot 2b + 1, and wgrad_fixup_kernel adds the two (lower
-// first).  Uncut tiles are summed exactly as by wgrad_wide_kernel.
+// neighbouring tiles share its L2).  A tile summed whole by one range is
+// written directly, with wgrad_wide_kernel's summation order.  A tile cut
+// by range boundaries is summed in parts: range w writes the part it starts
+// inside a tile (or that lies inside one) to scratch slot 2w + 1, and the
+// part it ends inside a tile to slot 2w; wgrad_fixup_kernel adds a cut
+// tile's parts in K order.
 template <class T>
 __global__ void __launch_bounds__(kWideThreads) wgrad_wide_split_kernel(
     const WgradProblem* __restrict__ probs, int n_probs, const StepState* st, int total_tiles,
@@ -435,8 +438,8 @@ __global__ void __launch_bounds__(kWideThreads) wgrad_wide_split_kernel(
            0, 0, (int)(c0 * kWideBK), (int)min((long long)K, c1 * kWideBK), smem);
     if (c0 == 0 && c1 == nck) {
       wide_epilogue<T, EPI_WGRAD_OUT>(wc.acc, unused, pr.dw, m0, n0, pr.M, pr.N, smem);
-    } else {  // lower part: boundary w follows; upper part: boundary w - 1 precedes
-      const long long slot = c0 == 0 ? 2LL * w : 2LL * (w - 1) + 1;
+    } else {
+      const long long slot = c0 != 0 ? 2LL * w + 1 : 2LL * w;
       wide_epilogue<T, EPI_WGRAD_OUT>(wc.acc, unused, part + slot * (T::BM * T::BN), 0, 0, T::BM,
                                       T::BN, smem);
     }
@@ -445,28 +448,35 @@ __global__ void __launch_bounds__(kWideThreads) wgrad_wide_split_kernel(
   }
 }
 
-// dW of every tile cut by a range boundary = lower part + upper part.
+// dW of every cut tile: its parts added in K order (ranges wa .. wb, empty
+// ranges skipped).  One work-group per tile; uncut tiles return at once.
 template <class T>
 __global__ void __launch_bounds__(256) wgrad_fixup_kernel(const WgradProblem* __restrict__ probs,
                                                           int n_probs, const StepState* st,
                                                           int total_tiles,
                                                           const float* __restrict__ part) {
-  const int b = blockIdx.x;  // boundary between ranges b and b + 1
+  const int t = blockIdx.x;
   const long long nck = (st->rows + kWideBK - 1) / kWideBK;
   if (nck == 0) return;  // no rows: the split kernel wrote nothing
   const long long U = (long long)total_tiles * nck;
-  const long long ub = (long long)(b + 1) * U / kWgradRanges;
-  if (ub % nck == 0) return;  // at a tile edge: no tile was cut
+  // the range holding chunk u: the last w with floor(w U / R) <= u
+  auto range_of = [&](long long u) { return (int)(((u + 1) * kWgradRanges + U - 1) / U - 1); };
+  const int wa = range_of((long long)t * nck), wb = range_of((long long)t * nck + nck - 1);
+  if (wa == wb) return;  // summed whole by range wa
   int m0, n0;
-  const WgradProblem pr = wgrad_tile<T>(probs, n_probs, (int)(ub / nck), &m0, &n0);
-  const float* lo = part + (size_t)(2 * b) * (T::BM * T::BN);
-  const float* hi = lo + T::BM * T::BN;
-  for (int e = threadIdx.x; e < T::BM * T::BN / 4; e += 256) {
+  const WgradProblem pr = wgrad_tile<T>(probs, n_probs, t, &m0, &n0);
+  constexpr int TE = T::BM * T::BN;
+  for (int e = threadIdx.x; e < TE / 4; e += 256) {
     const int i = (4 * e) / T::BN, j = (4 * e) % T::BN;
     const int m = m0 + i, n = n0 + j;
     if (m >= pr.M || n >= pr.N) continue;  // N is a multiple of 4
-    const float4 x = ld4(lo + (size_t)i * T::BN + j), y = ld4(hi + (size_t)i * T::BN + j);
-    st4(pr.dw + (size_t)m * pr.N + n, make_float4(x.x + y.x, x.y + y.y, x.z + y.z, x.w + y.w));
+    float4 a = ld4(part + (size_t)(2 * wa) * TE + 4 * e);
+    for (int r = wa + 1; r <= wb; ++r) {
+      if ((long long)r * U / kWgradRanges == (long long)(r + 1) * U / kWgradRanges) continue;
+      const float4 b = ld4(part + (size_t)(2 * r + 1) * TE + 4 * e);
+      a = make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w);
+    }
+    st4(pr.dw + (size_t)m * pr.N + n, a);
   }
 }
 
@@ -539,7 +549,7 @@ static hipError_t launch_wgrad_wide_t(const WgradProblem* d_probs, int n_probs, 
   if (part && total_tiles >= kWgradRanges) {
     hipLaunchKernelGGL((wgrad_wide_split_kernel<T>), dim3(kWgradRanges), dim3(kWideThreads), T::SMEM,
                        s, d_probs, n_probs, st, total_tiles, part);
-    hipLaunchKernelGGL((wgrad_fixup_kernel<T>), dim3(kWgradRanges - 1), dim3(256), 0, s, d_probs,
+    hipLaunchKernelGGL((wgrad_fixup_kernel<T>), dim3(total_tiles), dim3(256), 0, s, d_probs,
                        n_probs, st, total_tiles, (const float*)part);
     return hipGetLastError();
   }

@@ -145,6 +145,7 @@ struct Model {
     int n = 0, tiles = 0;
   } wg_tab[TILE_COUNT];
   float* wg_part = nullptr;  // scratch of the balanced wide-tile weight-gradient launch
+  size_t wg_part_floats = 0;
   ColsumJob* d_cs = nullptr;
   int n_cs = 0, cs_blocks = 0, cs_cols = 0;
   float* cs_partial = nullptr;

@@ -398,11 +398,12 @@ void Model::build_tables(hipStream_t s) {
                              hipMemcpyHostToDevice, s), "copy");
   }
 
-  size_t part_floats = 0;  // wide tiles with more tiles than the split launch's ranges
-  for (int tile = TILE_W128x128; tile < TILE_COUNT; ++tile)
-    if (bf16 && wg_tab[tile].tiles >= kWgradRanges)
-      part_floats = std::max(part_floats, wgrad_part_floats(tile));
-  if (part_floats) wg_part = dalloc<float>(part_floats);
+  // scratch of the balanced weight-gradient launch (wide tiles, large tables)
+  if (bf16 && kc.tile[PS_WGRAD] >= TILE_W128x128 &&
+      wg_tab[kc.tile[PS_WGRAD]].tiles >= kWgradRanges) {
+    wg_part_floats = wgrad_part_floats(kc.tile[PS_WGRAD]);
+    wg_part = dalloc<float>(wg_part_floats);
+  }
 
   // column sums: bias gradients, LayerNorm affine gradients
   std::vector<ColsumJob> cs;
@@ -859,6 +860,26 @@ void Model::autotune(hipStream_t s) {
   hip_check(hipEventCreate(&e1), "event");
   KTimer* saved = timer;
   timer = nullptr;
+  // the wide weight-gradient candidates run the balanced launch: scratch for
+  // the largest of them during the trials, then for the tile chosen
+  struct Scratch {
+    void* p = nullptr;
+    hipStream_t s;
+    ~Scratch() {
+      if (p) {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(p);
+      }
+    }
+  } trial;
+  trial.s = s;
+  float* const kept_part = wg_part;
+  if (bf16) {
+    size_t most = 0;
+    for (int t = TILE_W128x128; t < TILE_COUNT; ++t) most = std::max(most, wgrad_part_floats(t));
+    hip_check(hipMalloc(&trial.p, most * sizeof(float)), "hipMalloc");
+    wg_part = (float*)trial.p;
+  }
   for (int ps = 0; ps < PS_COUNT; ++ps) {
     const bool per_block = ps == PS_GATE || ps == PS_OUT || ps == PS_GATE_BWD || ps == PS_DZ;
     if (per_block && N == 0) continue;
@@ -884,6 +905,13 @@ void Model::autotune(hipStream_t s) {
       if (ms < best_ms) { best_ms = ms; best = t; }
     }
     kc.tile[ps] = best;
+  }
+  wg_part = kept_part;
+  if (bf16 && kc.tile[PS_WGRAD] >= TILE_W128x128 &&
+      wg_tab[kc.tile[PS_WGRAD]].tiles >= kWgradRanges &&
+      wgrad_part_floats(kc.tile[PS_WGRAD]) > wg_part_floats) {
+    wg_part_floats = wgrad_part_floats(kc.tile[PS_WGRAD]);
+    wg_part = dalloc<float>(wg_part_floats);
   }
   timer = saved;
   (void)hipEventDestroy(e0);

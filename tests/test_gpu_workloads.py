@@ -86,24 +86,30 @@ def test_large_prefix_roundtrip_bf16_vs_fp32_size(E):
     assert abs(sizes["bf16"] - sizes["fp32"]) / sizes["fp32"] <= 0.005
 
 
-def test_large_split_weight_gradients_match_one_pass_tiles(E):
-    # The large model's weight-gradient table has 312 wide 256 x 256 tiles,
-    # more than the 256 ranges of the balanced launch, so tiles cut by a
-    # range boundary are summed in two parts (lower K chunks first).  The
-    # 4-wave 128 x 64 tile sums every tile's K chunks in one pass with the
-    # same MFMA sequence: uncut entries must be bit-identical to it, cut ones
-    # within the rounding of the one extra addition.  320 rows = 5 chunks of
-    # 64 per tile, 1560 chunks in all, 6 or 7 per range.
-    banner("large split weight gradients, 320 rows")
-    rows, C = 320, LARGE["context"]
-    data, _ = gen.make_streams("large", prefix=C + 1, n_streams=rows)
+@pytest.mark.parametrize("case", ["large_w256x256_320rows", "mid_w128x128_300rows"])
+def test_split_weight_gradients_match_one_pass_tiles(E, case):
+    # The balanced weight-gradient launch of the wide tiles cuts the K chunks
+    # of all tiles into 256 equal ranges; a tile that one range covers is
+    # summed as by one work-group per tile, a cut tile in parts added in K
+    # order.  The 4-wave 128 x 64 tile sums every tile's K chunks in one pass
+    # with the same MFMA sequence: uncut entries must be bit-identical to it,
+    # cut ones within the rounding of the extra additions.
+    #  * large model, 320 rows: 312 tiles of 256 x 256, 5 chunks each, 6 or 7
+    #    chunks per range, so every tile is cut at most once;
+    #  * 1024-stream model (layer-by-layer), 300 rows: 112 tiles of 128 x 128,
+    #    fewer than the ranges, so one work-group per tile: bit-identical.
+    model, rows, tile, wl = {"large_w256x256_320rows": (LARGE, 320, 10, "large"),
+                             "mid_w128x128_300rows": (MID, 300, 7, "mid_bf16")}[case]
+    banner(f"split weight gradients {case}")
+    C = model["context"]
+    data, _ = gen.make_streams(wl, prefix=C + 1, n_streams=rows)
     st = np.frombuffer(data.tobytes(), dtype=np.uint8).reshape(rows, -1)
     d_ctx = torch.as_tensor(st[:, :C].copy()).to("cuda")
     d_tgt = torch.as_tensor(st[:, C].copy()).to("cuda")
-    cfg = lib_cfg(E, LARGE, "bf16")
+    cfg = lib_cfg(E, model, "bf16", layerwise=True)
     rev = E.Model(cfg, 1, 1).edpc_model_kernel_id() >> 48
-    wide = (rev << 48) | sum(10 << (4 * i) for i in range(11))  # every product on w256x256
-    one_pass = (wide & ~(0xF << 40)) | (4 << 40)                  # weight gradients on 128 x 64
+    wide = (rev << 48) | sum(tile << (4 * i) for i in range(11))  # every product on the wide tile
+    one_pass = (wide & ~(0xF << 40)) | (4 << 40)                   # weight gradients on 128 x 64
     grads = {}
     for name, kid in (("split", wide), ("one_pass", one_pass)):
         m = E.Model(cfg, rows, rows, kid)
@@ -120,4 +126,7 @@ def test_large_split_weight_gradients_match_one_pass_tiles(E):
         assert np.abs(a - b).max() <= 1e-5 * scale, n
         exact += int((a == b).sum())
         total += a.size
-    assert exact >= total // 4 and exact < total, (exact, total)
+    if tile == 10:
+        assert total // 4 <= exact < total, (exact, total)
+    else:
+        assert exact == total, (exact, total)
