@@ -26,6 +26,10 @@ LIB = os.path.join(PKG, "libedpc.so")
 SOURCES = ["gemm.hip", "gemm_wide.hip", "kernels.hip", "fused.hip", "model.hip", "codec.hip", "stream.hip", "ksg.hip", "api.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+# roctx, for the named host-side ranges (csrc/trace.h) that profilers record
+ROCTX_LINK = ["-L" + os.path.join(ROCM, "lib"), "-lrocprofiler-sdk-roctx",
+              "-Wl,-rpath," + os.path.join(ROCM, "lib")]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # packed FP32 instructions disabled for every kernel
@@ -68,7 +72,7 @@ def build(jobs: int = 5, verbose: bool = True, sanitize: bool = False) -> str:
     lib = SAN_LIB if sanitize else LIB
     tmp = lib + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *(SANITIZE if sanitize else []),
-           *objs, "-o", tmp]
+           *objs, *ROCTX_LINK, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")

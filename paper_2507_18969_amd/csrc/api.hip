@@ -6,6 +6,7 @@
 #include <string>
 
 #include "codec.h"
+#include "trace.h"
 
 using namespace edpc;
 
@@ -25,7 +26,8 @@ edpc_status set_err(edpc_status st, const std::string& msg) {
 }
 
 template <class F>
-edpc_status guarded(F&& f) {
+edpc_status guarded(const char* name, F&& f) {
+  TraceRange range(name);
   try {
     g_last_error.clear();
     return f();
@@ -82,7 +84,7 @@ edpc_status edpc_config_default(edpc_config* cfg) {
 }
 
 edpc_status edpc_config_validate(const edpc_config* cfg) {
-  return guarded([&] {
+  return guarded("edpc_config_validate", [&] {
     if (!cfg) fail(EDPC_E_INVALID_ARG, "cfg is NULL");
     Model::validate(*cfg);
     return EDPC_OK;
@@ -91,7 +93,7 @@ edpc_status edpc_config_validate(const edpc_config* cfg) {
 
 edpc_status edpc_encode_bound(const edpc_config* cfg, const uint64_t* h_lens, size_t n,
                               size_t* bound) {
-  return guarded([&] {
+  return guarded("edpc_encode_bound", [&] {
     if (!cfg || !bound || (n && !h_lens)) fail(EDPC_E_INVALID_ARG, "NULL argument");
     Model::validate(*cfg);
     if (n == 0) fail(EDPC_E_INVALID_ARG, "n_streams must be >= 1");
@@ -102,7 +104,7 @@ edpc_status edpc_encode_bound(const edpc_config* cfg, const uint64_t* h_lens, si
 
 edpc_status edpc_encoder_begin(const edpc_config* cfg, const uint8_t* d_in, const uint64_t* h_lens,
                                size_t n, void* stream, edpc_session** out) {
-  return guarded([&] {
+  return guarded("edpc_encoder_begin", [&] {
     if (!cfg || !out || !h_lens) fail(EDPC_E_INVALID_ARG, "NULL argument");
     *out = nullptr;
     uint64_t total = 0;
@@ -117,7 +119,7 @@ edpc_status edpc_encoder_begin(const edpc_config* cfg, const uint8_t* d_in, cons
 
 edpc_status edpc_decoder_begin(const uint8_t* d_in, size_t in_len, uint8_t* d_out, size_t out_cap,
                                void* stream, edpc_session** out) {
-  return guarded([&] {
+  return guarded("edpc_decoder_begin", [&] {
     if (!d_in || !out) fail(EDPC_E_INVALID_ARG, "NULL argument");
     *out = nullptr;
     std::unique_ptr<edpc_session> h(new edpc_session());
@@ -128,7 +130,7 @@ edpc_status edpc_decoder_begin(const uint8_t* d_in, size_t in_len, uint8_t* d_ou
 }
 
 edpc_status edpc_session_run(edpc_session* s, uint64_t n_steps, uint64_t* done) {
-  return guarded([&] {
+  return guarded("edpc_session_run", [&] {
     if (!s || !s->s) fail(EDPC_E_INVALID_ARG, "NULL session");
     const uint64_t before = s->s->next;
     s->s->run(n_steps);
@@ -145,7 +147,7 @@ edpc_status edpc_session_progress(const edpc_session* s, uint64_t* step, uint64_
 }
 
 edpc_status edpc_encoder_finish(edpc_session* s, uint8_t* d_out, size_t out_cap, size_t* out_len) {
-  return guarded([&] {
+  return guarded("edpc_encoder_finish", [&] {
     if (!s || !s->s || s->s->decoding) fail(EDPC_E_INVALID_ARG, "not an encoder session");
     if (!out_len) fail(EDPC_E_INVALID_ARG, "out_len is NULL");
     try {
@@ -159,7 +161,7 @@ edpc_status edpc_encoder_finish(edpc_session* s, uint8_t* d_out, size_t out_cap,
 }
 
 edpc_status edpc_decoder_finish(edpc_session* s, size_t* out_len) {
-  return guarded([&] {
+  return guarded("edpc_decoder_finish", [&] {
     if (!s || !s->s || !s->s->decoding) fail(EDPC_E_INVALID_ARG, "not a decoder session");
     const size_t n = decoder_finish(*s->s);
     if (out_len) *out_len = n;
@@ -171,7 +173,7 @@ void edpc_session_destroy(edpc_session* s) { delete s; }
 
 edpc_status edpc_session_time_kernels(edpc_session* s, uint64_t n_steps, float* h_ms,
                                       uint32_t* h_launches) {
-  return guarded([&] {
+  return guarded("edpc_session_time_kernels", [&] {
     if (!s || !s->s || !h_ms || !h_launches) fail(EDPC_E_INVALID_ARG, "NULL argument");
     KTimer timer;
     Model& m = *s->s->model;
@@ -217,7 +219,7 @@ edpc_status edpc_decode(const uint8_t* d_in, size_t in_len, uint8_t* d_out, size
 edpc_status edpc_encode_host(const edpc_config* cfg, const uint8_t* h_in, const uint64_t* h_lens,
                              size_t n, uint8_t* h_out, size_t out_cap, size_t* out_len,
                              uint32_t chunk_steps, void* stream) {
-  return guarded([&] {
+  return guarded("edpc_encode_host", [&] {
     if (!cfg || !h_lens || !out_len || !h_out) fail(EDPC_E_INVALID_ARG, "NULL argument");
     uint64_t total = 0;
     for (size_t i = 0; i < n; ++i) total += h_lens[i];
@@ -235,7 +237,7 @@ edpc_status edpc_encode_host(const edpc_config* cfg, const uint8_t* h_in, const 
 
 edpc_status edpc_decode_host(const uint8_t* h_in, size_t in_len, uint8_t* h_out, size_t out_cap,
                              size_t* out_len, uint32_t chunk_steps, void* stream) {
-  return guarded([&] {
+  return guarded("edpc_decode_host", [&] {
     if (!h_in || !out_len) fail(EDPC_E_INVALID_ARG, "NULL argument");
     if (!h_out && out_cap) fail(EDPC_E_INVALID_ARG, "h_out is NULL");
     *out_len = stream_decode(h_in, in_len, h_out, out_cap, chunk_steps, S(stream));
@@ -246,7 +248,7 @@ edpc_status edpc_decode_host(const uint8_t* h_in, size_t in_len, uint8_t* h_out,
 edpc_status edpc_decode_info(const uint8_t* h_in, size_t in_len, edpc_config* cfg,
                              size_t* n_streams, uint64_t* h_lens, size_t lens_cap,
                              size_t* header_len, size_t* decoded_len) {
-  return guarded([&] {
+  return guarded("edpc_decode_info", [&] {
     if (!h_in) fail(EDPC_E_INVALID_ARG, "h_in is NULL");
     Header h;
     size_t need = 0;
@@ -273,7 +275,7 @@ edpc_status edpc_decode_info(const uint8_t* h_in, size_t in_len, edpc_config* cf
 
 edpc_status edpc_model_create(const edpc_config* cfg, size_t n_slots, size_t max_rows,
                               edpc_model** out) {
-  return guarded([&] {
+  return guarded("edpc_model_create", [&] {
     if (!cfg || !out) fail(EDPC_E_INVALID_ARG, "NULL argument");
     *out = nullptr;
     std::unique_ptr<edpc_model> h(new edpc_model());
@@ -290,7 +292,7 @@ edpc_status edpc_model_create(const edpc_config* cfg, size_t n_slots, size_t max
 edpc_status edpc_model_create_with_kernels(const edpc_config* cfg, size_t n_slots,
                                            size_t max_rows, uint64_t kernel_id,
                                            edpc_model** out) {
-  return guarded([&] {
+  return guarded("edpc_model_create_with_kernels", [&] {
     if (!cfg || !out) fail(EDPC_E_INVALID_ARG, "NULL argument");
     *out = nullptr;
     if (kernel_id == 0) return edpc_model_create(cfg, n_slots, max_rows, out);
@@ -328,7 +330,7 @@ void edpc_model_destroy(edpc_model* m) {
 edpc_status edpc_model_step(edpc_model* mh, const uint8_t* d_ctx, const uint8_t* d_target,
                             const uint32_t* h_slot, size_t rows, float* d_probs, uint32_t* d_cum,
                             float* d_loss, uint32_t flags, void* stream) {
-  return guarded([&] {
+  return guarded("edpc_model_step", [&] {
     if (!mh || !mh->m) fail(EDPC_E_INVALID_ARG, "NULL model");
     Model& m = *mh->m;
     if (flags & ~(EDPC_STEP_BACKWARD | EDPC_STEP_UPDATE | EDPC_STEP_KEEP_FDM_GRAD))
@@ -495,7 +497,7 @@ extern "C" {
 
 edpc_status edpc_model_read(const edpc_model* mh, uint32_t kind, size_t idx, float* h_dst,
                             size_t numel) {
-  return guarded([&] {
+  return guarded("edpc_model_read", [&] {
     if (!mh || !h_dst) fail(EDPC_E_INVALID_ARG, "NULL argument");
     if (kind == EDPC_KIND_OPERAND_NT || kind == EDPC_KIND_OPERAND_NN) {
       read_operand(*mh->m, kind, idx, h_dst, numel);
@@ -512,7 +514,7 @@ edpc_status edpc_model_read(const edpc_model* mh, uint32_t kind, size_t idx, flo
 
 edpc_status edpc_model_write(edpc_model* mh, uint32_t kind, size_t idx, const float* h_src,
                              size_t numel) {
-  return guarded([&] {
+  return guarded("edpc_model_write", [&] {
     if (!mh || !h_src) fail(EDPC_E_INVALID_ARG, "NULL argument");
     Model& m = *mh->m;
     size_t ne = 0;
@@ -532,7 +534,7 @@ edpc_status edpc_model_write(edpc_model* mh, uint32_t kind, size_t idx, const fl
 
 edpc_status edpc_model_read_device(const edpc_model* mh, uint32_t kind, size_t idx, float* d_dst,
                                    size_t numel, void* stream) {
-  return guarded([&] {
+  return guarded("edpc_model_read_device", [&] {
     if (!mh || !d_dst) fail(EDPC_E_INVALID_ARG, "NULL argument");
     size_t ne = 0;
     float* p = tensor_ptr(*mh->m, kind, idx, &ne, false);
@@ -544,7 +546,7 @@ edpc_status edpc_model_read_device(const edpc_model* mh, uint32_t kind, size_t i
 
 edpc_status edpc_model_write_device(edpc_model* mh, uint32_t kind, size_t idx, const float* d_src,
                                     size_t numel, void* stream) {
-  return guarded([&] {
+  return guarded("edpc_model_write_device", [&] {
     if (!mh || !d_src) fail(EDPC_E_INVALID_ARG, "NULL argument");
     Model& m = *mh->m;
     size_t ne = 0;
@@ -562,7 +564,7 @@ edpc_status edpc_model_write_device(edpc_model* mh, uint32_t kind, size_t idx, c
 
 edpc_status edpc_model_activation(const edpc_model* mh, uint32_t block, float* d_dst, size_t numel,
                                   void* stream) {
-  return guarded([&] {
+  return guarded("edpc_model_activation", [&] {
     if (!mh || !mh->m || !d_dst) fail(EDPC_E_INVALID_ARG, "NULL argument");
     const Model& m = *mh->m;
     if (block > (uint32_t)m.N) fail(EDPC_E_INVALID_ARG, "block index out of range");
@@ -579,7 +581,7 @@ edpc_status edpc_model_activation(const edpc_model* mh, uint32_t block, float* d
 edpc_status edpc_mutual_info(const float* d_z, size_t dz, const float* d_y, size_t dy, size_t c,
                              uint32_t v, double* h_mi, int32_t* d_counts, float* d_eps,
                              void* stream) {
-  return guarded([&] {
+  return guarded("edpc_mutual_info", [&] {
     if (!d_z || !d_y || !h_mi) fail(EDPC_E_INVALID_ARG, "NULL argument");
     *h_mi = mutual_info(d_z, dz, d_y, dy, c, v, d_counts, d_eps, S(stream));
     return EDPC_OK;
@@ -644,7 +646,7 @@ std::string tensor_name(const Model& m, size_t i) {
 extern "C" {
 
 edpc_status edpc_model_get_state(const edpc_model* mh, void* h_buf, size_t cap, size_t* len) {
-  return guarded([&] {
+  return guarded("edpc_model_get_state", [&] {
     if (!mh || !mh->m || !len) fail(EDPC_E_INVALID_ARG, "NULL argument");
     Model& m = *mh->m;
     // size first: the blob is written only when it fits
@@ -691,7 +693,7 @@ edpc_status edpc_model_get_state(const edpc_model* mh, void* h_buf, size_t cap, 
 }
 
 edpc_status edpc_model_set_state(edpc_model* mh, const void* h_buf, size_t len) {
-  return guarded([&] {
+  return guarded("edpc_model_set_state", [&] {
     if (!mh || !mh->m || !h_buf) fail(EDPC_E_INVALID_ARG, "NULL argument");
     Model& m = *mh->m;
     BlobReader r{(const uint8_t*)h_buf, len};
@@ -747,7 +749,7 @@ edpc_status edpc_model_set_state(edpc_model* mh, const void* h_buf, size_t len) 
 edpc_status edpc_rc_encode(const uint32_t* d_cum, const uint8_t* d_sym, size_t n_steps,
                            size_t n_streams, uint8_t* d_out, size_t cap, uint32_t* h_out_lens,
                            void* stream) {
-  return guarded([&] {
+  return guarded("edpc_rc_encode", [&] {
     if (!d_cum || !d_sym || !d_out || !h_out_lens) fail(EDPC_E_INVALID_ARG, "NULL argument");
     if (n_streams == 0) fail(EDPC_E_INVALID_ARG, "n_streams must be >= 1");
     if (cap < 2 * n_steps + 2) fail(EDPC_E_INVALID_ARG, "cap_per_stream < 2 * n_steps + 2");
@@ -799,7 +801,7 @@ extern "C" {
 edpc_status edpc_rc_encode_noalloc(const uint32_t* d_cum, const uint8_t* d_sym, size_t n_steps,
                                    size_t n_streams, uint8_t* d_out, size_t cap,
                                    uint32_t* h_out_lens, void* stream) {
-  return guarded([&] {
+  return guarded("edpc_rc_encode_noalloc", [&] {
     if (!d_cum || !d_sym || !d_out || !h_out_lens) fail(EDPC_E_INVALID_ARG, "NULL argument");
     if (n_streams == 0) fail(EDPC_E_INVALID_ARG, "n_streams must be >= 1");
     if (n_streams > EDPC_RC_NOALLOC_MAX_STREAMS)
@@ -826,7 +828,7 @@ edpc_status edpc_rc_encode_noalloc(const uint32_t* d_cum, const uint8_t* d_sym, 
 edpc_status edpc_rc_decode(const uint32_t* d_cum, const uint8_t* d_in, const uint32_t* h_in_lens,
                            size_t cap, size_t n_steps, size_t n_streams, uint8_t* d_sym,
                            void* stream) {
-  return guarded([&] {
+  return guarded("edpc_rc_decode", [&] {
     if (!d_cum || !d_in || !h_in_lens || !d_sym) fail(EDPC_E_INVALID_ARG, "NULL argument");
     if (n_streams == 0) fail(EDPC_E_INVALID_ARG, "n_streams must be >= 1");
     hipStream_t s = S(stream);

@@ -1,5 +1,6 @@
 // Multi-stream codec sessions and the container.
 #include "codec.h"
+#include "trace.h"
 
 #include <algorithm>
 #include <cstdlib>
@@ -197,6 +198,7 @@ void Session::run(uint64_t k) {
         auto it = graphs.find(b);
         if (it == graphs.end()) {
           if (!cap) hip_check(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "stream");
+          TraceRange range("graph capture");
           hipGraph_t g = nullptr;
           hip_check(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "capture");
           try {
@@ -214,13 +216,17 @@ void Session::run(uint64_t k) {
           it = graphs.emplace(b, ex).first;
         }
         // the captured steps advance from the device step counter
+        TraceRange range("graph window");
         k_step_set(model->st, (int)i - 1, s);
         hip_check(hipGraphLaunch(it->second, s), "graph launch");
         i += graph_steps;
         continue;
       }
     }
-    step_direct(i, rows, true, s);
+    {
+      TraceRange range("direct step");
+      step_direct(i, rows, true, s);
+    }
     ++i;
   }
   next = end;
@@ -240,7 +246,10 @@ void common_setup(Session& ss, const KernelConfig* kc) {
   ss.model.reset(new Model(ss.cfg, n, rows, kc));
   ss.model->init_params(ss.s);
   ss.model->build_tables(ss.s);
-  if (!ss.decoding && (ss.cfg.flags & EDPC_CFG_AUTOTUNE)) ss.model->autotune(ss.s);
+  if (!ss.decoding && (ss.cfg.flags & EDPC_CFG_AUTOTUNE)) {
+    TraceRange range("autotune");
+    ss.model->autotune(ss.s);
+  }
   hip_check(hipMemcpyAsync(ss.model->slot, perm.data(), std::min(n, rows) * sizeof(uint32_t),
                            hipMemcpyHostToDevice, ss.s), "copy");
   ss.d_lens_sorted = ss.dalloc<int64_t>(n);
@@ -305,6 +314,7 @@ std::unique_ptr<Session> encoder_begin(const edpc_config& cfg, const uint8_t* d_
 
 size_t encoder_finish(Session& ss, uint8_t* d_out, size_t out_cap) {
   ss.run(ss.maxlen);
+  TraceRange range("container");
   k_rc_finish(ss.io, (int)ss.n, ss.s);
   std::vector<RcEnc> enc(ss.n);
   Header h;

@@ -1,6 +1,7 @@
 // Model object and the launch sequence of one step (Algorithm 1, lines
 // "Model", "Encode/Decode", "loss", "backward", "update").
 #include "model.h"
+#include "trace.h"
 
 #include <cmath>
 #include <cstdlib>
@@ -746,6 +747,7 @@ const float* Model::block_input(int j) const {
 
 void Model::step(StepMode mode, const StreamIO& io, const StepOutputs& out, int grid_rows,
                  hipStream_t s) {
+  TraceRange range(kc.fused ? "step (row-block)" : "step (layer by layer)");
   const int R = grid_rows;
   last_rows = grid_rows;
   // ---- forward: Eq. 1 through Eqs. 14-16 and 9-13 -------------------------

@@ -25,6 +25,7 @@
 #include <thread>
 
 #include "codec.h"
+#include "trace.h"
 
 namespace edpc {
 
@@ -194,6 +195,7 @@ size_t stream_encode(const edpc_config& cfg, const uint8_t* h_in, const uint64_t
   const uint64_t maxlen = ss->maxlen;
   const uint64_t nchunks = (maxlen + T - 1) / T;
   for (uint64_t k = 0; k < nchunks; ++k) {
+    TraceRange range("encode chunk");
     const int b = (int)(k & 1);
     // staging b was last copied for chunk k - 2
     if (k >= 2) hip_check(hipEventSynchronize(ev_h2d[b].e), "sync");
@@ -336,6 +338,7 @@ size_t stream_decode(const uint8_t* h_in, size_t in_len, uint8_t* h_out, size_t 
   const uint64_t maxlen = ss->maxlen;
   const uint64_t nchunks = (maxlen + T - 1) / T;
   for (uint64_t k = 0; k < nchunks; ++k) {
+    TraceRange range("decode chunk");
     const uint32_t slot = (uint32_t)(k % S);
     // the slot's previous chunk (k - S) must have left for the host
     if (k >= S) hip_check(hipStreamWaitEvent(s, ev_d2h[slot].e, 0), "wait");
