@@ -112,3 +112,24 @@ def test_host_codec_errors(E):
     with pytest.raises(E.EdpcError) as ei:
         E.edpc_decode_host(bad.tobytes(), 32)
     assert ei.value.status == -5
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_all_streams_empty(E, precision):
+    # every stream empty: the container is the header alone (96 bytes with its
+    # CRC, 20 per stream), with empty payloads, through the device-resident and
+    # the host-to-host codecs alike, and it decodes to nothing
+    cfg = lib_cfg(E, SMALL, precision)
+    lens = np.zeros(3, dtype=np.int64)
+    flat = np.zeros(0, dtype=np.uint8)
+    dev = E.edpc_encode(cfg, torch.empty(0, dtype=torch.uint8, device="cuda"), lens)
+    torch.cuda.synchronize()
+    want = dev.cpu().numpy().tobytes()
+    assert len(want) == 96 + 20 * 3
+    got = E.edpc_encode_host(cfg, flat, lens, 32).tobytes()
+    assert got == want
+    _, lens_back, hl, total = E.edpc_decode_info(want)
+    assert list(lens_back) == [0, 0, 0] and hl == len(want) and total == 0
+    out, _ = E.edpc_decode(dev)
+    assert out.numel() == 0
+    assert E.edpc_decode_host(got, 32).size == 0
