@@ -25,6 +25,8 @@ from __future__ import annotations
 
 import math
 
+import functools
+
 import numpy as np
 
 _GAMMA = np.uint64(0x9E3779B97F4A7C15)
@@ -79,18 +81,25 @@ def _rank_from_uniform(u: np.ndarray, cdf: np.ndarray) -> np.ndarray:
     return np.minimum(r, len(cdf) - 1).astype(np.int64)
 
 
+@functools.lru_cache(maxsize=4)
 def markov_order2_table(order: int, table_seed: int = TABLE_SEED) -> np.ndarray:
     """65536 x 256 table of seeded permutations of the byte alphabet.
 
     Row c is the permutation for context key c: symbols sorted by the
     SplitMix64 key ``splitmix64(k_c + j)``, ``k_c = splitmix64(seed ^ (o<<56) ^ c)``.
-    Entry ``[c, r]`` is the symbol of 0-based rank r.
+    Entry ``[c, r]`` is the symbol of 0-based rank r.  Built in row blocks
+    (same result, less memory at once) and kept per process, read-only.
     """
-    c = np.arange(65536, dtype=np.uint64)
-    kc = splitmix64(_u64(table_seed) ^ np.uint64(order << 56) ^ c)
-    with np.errstate(over="ignore"):
-        keys = splitmix64(kc[:, None] + np.arange(256, dtype=np.uint64)[None, :])
-    return np.argsort(keys, axis=1, kind="stable").astype(np.uint8)
+    out = np.empty((65536, 256), dtype=np.uint8)
+    j = np.arange(256, dtype=np.uint64)[None, :]
+    for c0 in range(0, 65536, 4096):
+        c = np.arange(c0, c0 + 4096, dtype=np.uint64)
+        kc = splitmix64(_u64(table_seed) ^ np.uint64(order << 56) ^ c)
+        with np.errstate(over="ignore"):
+            keys = splitmix64(kc[:, None] + j)
+        out[c0:c0 + 4096] = np.argsort(keys, axis=1, kind="stable")
+    out.setflags(write=False)
+    return out
 
 
 def stream_seed(s, table_seed: int = TABLE_SEED):
