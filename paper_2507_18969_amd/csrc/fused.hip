@@ -427,23 +427,30 @@ __global__ void __launch_bounds__(kFusedThreads, 1) fused_kernel(FusedArgs a) {
   if (w == NW - 1) {
     // the last wave stages the coder inputs of the block's rows
     if (lane < BM) {
-      RowCoder rc = {};
+      // field by field into LDS (a local RowCoder filled under these
+      // branches is kept in scratch memory by the compiler)
+      RowCoder& rc = sCode[lane];
+      uint32_t s = 0u;
+      int32_t tgt = 0;
+      uint64_t poff = 0, pcap = 0, off = 0;
       if (lane < nr) {
         const int r = r0 + lane;
-        rc.s = a.io.slot ? a.io.slot[r] : 0u;
-        if (mode != 2 && a.head.target) rc.tgt = a.head.target[r];
-        if (mode == 1) {
-          rc.enc = a.io.enc[rc.s];
-          rc.poff = a.io.pay_off[rc.s];
-          rc.pcap = a.io.pay_cap[rc.s];
-        } else if (mode == 2) {
-          rc.dec = a.io.dec[rc.s];
-          rc.poff = a.io.pay_off[rc.s];
-          rc.pcap = a.io.pay_cap[rc.s];
-          rc.off = a.io.off[rc.s];
+        s = a.io.slot ? a.io.slot[r] : 0u;
+        if (mode != 2 && a.head.target) tgt = a.head.target[r];
+        if (mode != 0) {
+          poff = a.io.pay_off[s];
+          pcap = a.io.pay_cap[s];
         }
+        if (mode == 2) off = a.io.off[s];
       }
-      sCode[lane] = rc;
+      const bool live = lane < nr;
+      rc.enc = live && mode == 1 ? a.io.enc[s] : RcEnc{};
+      rc.dec = live && mode == 2 ? a.io.dec[s] : RcDec{};
+      rc.poff = poff;
+      rc.pcap = pcap;
+      rc.off = off;
+      rc.s = s;
+      rc.tgt = tgt;
     }
   } else {
     // the others stage the FDM output

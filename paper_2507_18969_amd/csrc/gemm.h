@@ -33,7 +33,7 @@ struct GemmArgs {
   int m_rows, k_rows;
   // epilogue
   const float* bias;
-  int bias_branch_stride;
+  int bias_branch_stride;     // GATE_FWD: elements between branch biases; GATE_BWD: branch count k
   const float* resid;
   int ld_resid;
   float* out32;

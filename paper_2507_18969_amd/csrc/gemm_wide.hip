@@ -222,22 +222,28 @@ __device__ __forceinline__ void st4bf(bf16_t* p, float4 v) {
 // batch before the accumulators go through LDS.
 // EPI_WGRAD_OUT: dw = acc (ld = N), used by the weight-gradient kernel.
 constexpr int EPI_WGRAD_OUT = 16;
+// EPI_GATE_BWD with the branch count nb (1..3) fixed at compile time, so that
+// the branch values of an item stay in registers (indexed by a runtime count
+// they would live in scratch memory).
+constexpr int epi_gate_bwd(int nb) { return 32 + nb; }
+constexpr int gate_bwd_branches(int epi) { return epi > 32 && epi <= 35 ? epi - 32 : 0; }
 
 template <int EPI>
 struct EpiPre {  // global operands of one item (four columns of one row)
-  static constexpr int N = EPI == EPI_GATE_BWD ? 3 : (EPI == EPI_STORE ? 1 : 0);
-  static constexpr int EB = EPI == EPI_GATE_BWD ? 4 : 8;  // items per batch
+  static constexpr int NB = gate_bwd_branches(EPI);
+  static constexpr int N = NB > 0 ? NB : (EPI == EPI_STORE ? 1 : 0);
+  static constexpr int EB = NB > 0 ? 4 : 8;  // items per batch
   float4 v[N > 0 ? N : 1];
 };
 
 template <class T, int EPI>
 __device__ __forceinline__ void wide_epilogue(const typename WideCompute<T, true, true>::Acc (&acc)[T::TM][T::TN],
                                               const GemmArgs& g, float* dw, int m0, int n0, int M,
-                                              int N, char* smem) {
+                                              int N, char* smem, int tid) {
   constexpr int HR = T::BM / 2, LDE = T::BN + 4;
   float* lds = (float*)smem;
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
   const int wm = wave / T::WN, wn = wave % T::WN;
   constexpr int WROWS = T::BM / T::WM;  // rows per wave
   // output columns of the tile handled per half-tile row (gated: per branch)
@@ -245,8 +251,9 @@ __device__ __forceinline__ void wide_epilogue(const typename WideCompute<T, true
   constexpr int ITEMS = HR * COLS / 4;
   static_assert(kWideThreads % (COLS / 4) == 0, "a thread keeps its columns");
   constexpr int EB = EpiPre<EPI>::EB;
+  constexpr int NB = EpiPre<EPI>::NB;  // gated backward: branch count
   // a thread's items all lie in the same four columns
-  const int c = 4 * (threadIdx.x % (COLS / 4));
+  const int c = 4 * (tid % (COLS / 4));
   const int n = n0 + c;
   const bool col_ok = n < N;
   float4 bias0 = make_float4(0.f, 0.f, 0.f, 0.f), bias1 = bias0;
@@ -265,8 +272,9 @@ __device__ __forceinline__ void wide_epilogue(const typename WideCompute<T, true
     if (it >= ITEMS || m >= M || !col_ok) return;
     if constexpr (EPI == EPI_STORE) {
       if (g.resid) p.v[0] = ld4(g.resid + (size_t)m * g.ld_resid + n);
-    } else if constexpr (EPI == EPI_GATE_BWD) {
-      for (int b = 0; b < g.bias_branch_stride; ++b)
+    } else if constexpr (NB > 0) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
         p.v[b] = ld4(g.aux + (size_t)m * g.ld_aux + b * g.aux_branch + n);
     }
   };
@@ -297,24 +305,28 @@ __device__ __forceinline__ void wide_epilogue(const typename WideCompute<T, true
                                    gelu_f(a0.z * a1.z), gelu_f(a0.w * a1.w));
       if (g.out32) st4(g.out32 + (size_t)m * g.ld_out32 + n, o);
       if (g.out16) st4bf(g.out16 + (size_t)m * g.ld_out16 + n, o);
-    } else {  // EPI_GATE_BWD: dP = acc * GeLU'(prod a); dX_b = dP * prod_{c != b} a_c
-      const int nbr = g.bias_branch_stride;
+    } else {  // gated backward: dP = acc * GeLU'(prod a); dX_b = dP * prod_{c != b} a_c
+      static_assert(NB > 0, "unknown epilogue");
       const float* av = (const float*)p.v;
       const float* vv = (const float*)&v;
-      float o[3][4];
+      float o[NB][4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         float prod = av[e];
-        for (int b = 1; b < nbr; ++b) prod *= av[4 * b + e];
+#pragma unroll
+        for (int b = 1; b < NB; ++b) prod *= av[4 * b + e];
         const float dp = vv[e] * gelu_grad_f(prod);
-        for (int b = 0; b < nbr; ++b) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
           float x = dp;
-          for (int cc = 0; cc < nbr; ++cc)
+#pragma unroll
+          for (int cc = 0; cc < NB; ++cc)
             if (cc != b) x *= av[4 * cc + e];
           o[b][e] = x;
         }
       }
-      for (int b = 0; b < nbr; ++b) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
         const float4 ob = make_float4(o[b][0], o[b][1], o[b][2], o[b][3]);
         if (g.out32) st4(g.out32 + (size_t)m * g.ld_out32 + b * g.aux_branch + n, ob);
         if (g.out16) st4bf(g.out16 + (size_t)m * g.ld_out16 + b * g.aux_branch + n, ob);
@@ -326,7 +338,7 @@ __device__ __forceinline__ void wide_epilogue(const typename WideCompute<T, true
     EpiPre<EPI> pre[EB];
     // first batch of operand reads in flight before the half goes through LDS
 #pragma unroll
-    for (int e = 0; e < EB; ++e) fetch(h, threadIdx.x + e * kWideThreads, pre[e]);
+    for (int e = 0; e < EB; ++e) fetch(h, tid + e * kWideThreads, pre[e]);
     __syncthreads();  // the K loop (or the previous half) is done with LDS
     if (wm * WROWS >= h * HR && wm * WROWS < (h + 1) * HR) {
 #pragma unroll
@@ -343,10 +355,10 @@ __device__ __forceinline__ void wide_epilogue(const typename WideCompute<T, true
     for (int b0 = 0; b0 < ITEMS; b0 += EB * kWideThreads) {
       if (b0 > 0) {
 #pragma unroll
-        for (int e = 0; e < EB; ++e) fetch(h, b0 + threadIdx.x + e * kWideThreads, pre[e]);
+        for (int e = 0; e < EB; ++e) fetch(h, b0 + tid + e * kWideThreads, pre[e]);
       }
 #pragma unroll
-      for (int e = 0; e < EB; ++e) finish(h, b0 + threadIdx.x + e * kWideThreads, pre[e]);
+      for (int e = 0; e < EB; ++e) finish(h, b0 + tid + e * kWideThreads, pre[e]);
     }
   }
 }
@@ -373,7 +385,7 @@ __global__ void __launch_bounds__(kWideThreads) gemm_wide_kernel(GemmArgs g) {
     wc.run((const bf16_t*)g.A, g.lda, m0, M, (const bf16_t*)g.B, g.ldb, n0, N, T::BN, 0, 0, 0, K,
            smem);
   }
-  wide_epilogue<T, EPI>(wc.acc, g, nullptr, m0, n0, M, N, smem);
+  wide_epilogue<T, EPI>(wc.acc, g, nullptr, m0, n0, M, N, smem, threadIdx.x);
 }
 
 // Problem and output origin of tile `tile` of a grouped weight-gradient table.
@@ -401,7 +413,17 @@ __global__ void __launch_bounds__(kWideThreads) wgrad_wide_kernel(const WgradPro
   wc.run((const bf16_t*)pr.dout, pr.M, m0, pr.M, (const bf16_t*)pr.in, pr.N, n0, pr.N, T::BN, 0,
          0, 0, K, smem);
   GemmArgs unused;
-  wide_epilogue<T, EPI_WGRAD_OUT>(wc.acc, unused, pr.dw, m0, n0, pr.M, pr.N, smem);
+  wide_epilogue<T, EPI_WGRAD_OUT>(wc.acc, unused, pr.dw, m0, n0, pr.M, pr.N, smem, threadIdx.x);
+}
+
+// The thread index behind an empty asm statement.  Values the epilogue
+// derives from it are then computed where they are used: taken from
+// threadIdx.x directly, the compiler hoists them out of the split kernel's
+// loop over tiles, keeps them live across the K loop, and spills them.
+__device__ __forceinline__ int opaque_thread_index() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
 }
 
 // The same products balanced over the CUs, for tables with at least as many
@@ -436,13 +458,13 @@ __global__ void __launch_bounds__(kWideThreads) wgrad_wide_split_kernel(
     WideCompute<T, false, false> wc;
     wc.run((const bf16_t*)pr.dout, pr.M, m0, pr.M, (const bf16_t*)pr.in, pr.N, n0, pr.N, T::BN,
            0, 0, (int)(c0 * kWideBK), (int)min((long long)K, c1 * kWideBK), smem);
-    if (c0 == 0 && c1 == nck) {
-      wide_epilogue<T, EPI_WGRAD_OUT>(wc.acc, unused, pr.dw, m0, n0, pr.M, pr.N, smem);
-    } else {
-      const long long slot = c0 != 0 ? 2LL * w + 1 : 2LL * w;
-      wide_epilogue<T, EPI_WGRAD_OUT>(wc.acc, unused, part + slot * (T::BM * T::BN), 0, 0, T::BM,
-                                      T::BN, smem);
-    }
+    // a whole tile goes to dW, a part to its slot ([BM][BN], origin 0)
+    const bool whole = c0 == 0 && c1 == nck;
+    const long long slot = c0 != 0 ? 2LL * w + 1 : 2LL * w;
+    float* dst = whole ? pr.dw : part + slot * (T::BM * T::BN);
+    wide_epilogue<T, EPI_WGRAD_OUT>(wc.acc, unused, dst, whole ? m0 : 0, whole ? n0 : 0,
+                                    whole ? pr.M : T::BM, whole ? pr.N : T::BN, smem,
+                                    opaque_thread_index());
     u += c1 - c0;
     __syncthreads();  // the epilogue's LDS before the next tile's staging
   }
@@ -510,7 +532,15 @@ static hipError_t launch_wide_t(bool ak, bool bk, EpiKind epi, int nb, const Gem
     if (epi == EPI_GATE_FWD && nb == 2) return launch_wide_one<G, true, true, EPI_GATE_FWD>(g, gm, s);
   } else if (ak && !bk) {
     if (epi == EPI_STORE) return launch_wide_one<P, true, false, EPI_STORE>(g, gm, s);
-    if (epi == EPI_GATE_BWD) return launch_wide_one<P, true, false, EPI_GATE_BWD>(g, gm, s);
+    if (epi == EPI_GATE_BWD) {
+      // one B matrix (W_o); the branch count k travels in bias_branch_stride
+      switch (g.bias_branch_stride) {
+        case 1: return launch_wide_one<P, true, false, epi_gate_bwd(1)>(g, gm, s);
+        case 2: return launch_wide_one<P, true, false, epi_gate_bwd(2)>(g, gm, s);
+        case 3: return launch_wide_one<P, true, false, epi_gate_bwd(3)>(g, gm, s);
+        default: return hipErrorInvalidValue;
+      }
+    }
   }
   return hipErrorInvalidValue;
 }

@@ -8,11 +8,17 @@
 
 namespace edpc {
 
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
 // Softmax (Eq. 1) and quantised 16-bit CDF of one row, one wave per row.
+// The per-lane quadruples are vectors so that a runtime element index
+// (row_pick) selects among registers: on plain arrays the compiler turns
+// the selection into a load from a computed address and keeps the whole
+// struct in scratch memory.
 struct RowCdf {
-  float p[4];   // probabilities of symbols 4l .. 4l+3
-  int q[4];     // frequencies
-  int cum[4];   // exclusive prefix sums of the frequencies
+  f32x4 p;      // probabilities of symbols 4l .. 4l+3
+  i32x4 q;      // frequencies
+  i32x4 cum;    // exclusive prefix sums of the frequencies
   float m, S;   // largest logit and the sum of exp(z - m)
 };
 
@@ -65,9 +71,12 @@ __device__ __forceinline__ int row_decode_symbol(const RowCdf& c, uint64_t d, ui
 __device__ __forceinline__ void row_pick(const RowCdf& c, const float z[4], int x, int* cx, int* qx,
                                          float* zx) {
   const int jx = x & 3;
-  *cx = __shfl(jx == 0 ? c.cum[0] : jx == 1 ? c.cum[1] : jx == 2 ? c.cum[2] : c.cum[3], x >> 2, 64);
-  *qx = __shfl(jx == 0 ? c.q[0] : jx == 1 ? c.q[1] : jx == 2 ? c.q[2] : c.q[3], x >> 2, 64);
-  *zx = __shfl(jx == 0 ? z[0] : jx == 1 ? z[1] : jx == 2 ? z[2] : z[3], x >> 2, 64);
+  const int c0 = c.cum[0], c1 = c.cum[1], c2 = c.cum[2], c3 = c.cum[3];
+  const int q0 = c.q[0], q1 = c.q[1], q2 = c.q[2], q3 = c.q[3];
+  const float z0 = z[0], z1 = z[1], z2 = z[2], z3 = z[3];
+  *cx = __shfl(jx == 0 ? c0 : jx == 1 ? c1 : jx == 2 ? c2 : c3, x >> 2, 64);
+  *qx = __shfl(jx == 0 ? q0 : jx == 1 ? q1 : jx == 2 ? q2 : q3, x >> 2, 64);
+  *zx = __shfl(jx == 0 ? z0 : jx == 1 ? z1 : jx == 2 ? z2 : z3, x >> 2, 64);
 }
 
 // Optional per-row outputs: probabilities and the CDF with its closing 2^16.

@@ -237,6 +237,21 @@ def test_bf16_update_wide_tiles(E, tile):
                  sample_rows=range(0, 300, 37), kernel_id=kid)
 
 
+PS_GATE_BWD = 6  # product slot of the gated adjoint (dP and the branch adjoints)
+
+
+@pytest.mark.parametrize("branches", [1, 2, 3])
+def test_bf16_update_wide_gated_adjoint(E, branches):
+    # the gated adjoint alone on a wide tile (its epilogue is compiled per
+    # branch count), every other product on the library's default tiles
+    model = dict(MID, branches=branches)
+    cfg = lib_cfg(E, model, "bf16", layerwise=True)
+    kid = E.Model(cfg, 1, 1).edpc_model_kernel_id()
+    kid = (kid & ~(0xF << (4 * PS_GATE_BWD))) | (WIDE_TILES["w256x128"] << (4 * PS_GATE_BWD))
+    _update_case(E, model, rows=300, om_steps=4, wl="mid_bf16", layerwise=True,
+                 sample_rows=range(0, 300, 37), kernel_id=kid)
+
+
 def test_wide_tiles_refused_where_they_do_not_apply(E):
     # FP32 models and three-branch gated products have no wide tile
     for model, prec in ((SMALL, "fp32"), (dict(SMALL, branches=3), "bf16")):
