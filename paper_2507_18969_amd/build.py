@@ -14,6 +14,7 @@ from __future__ import annotations
 import argparse
 import concurrent.futures as cf
 import os
+import re
 import shutil
 import subprocess
 import sys
@@ -55,20 +56,56 @@ def asan_runtime() -> str:
     return r.stdout.strip()
 
 
-def _compile(src: str, sanitize: bool = False) -> str:
+# per-kernel register, scratch and LDS use of the product build, from the
+# compiler's resource-usage remarks (one row per kernel)
+RESOURCES = os.path.join(BUILD, "kernel_resources.tsv")
+RESOURCE_FIELDS = [("VGPRs", "vgprs"), ("AGPRs", "agprs"), ("ScratchSize [bytes/lane]", "scratch"),
+                   ("VGPRs Spill", "vgpr_spill"), ("SGPRs Spill", "sgpr_spill"),
+                   ("LDS Size [bytes/block]", "lds"), ("Occupancy [waves/SIMD]", "occupancy")]
+_REMARK = re.compile(r"remark:\s+(.+?): (.+?) \[-Rpass-analysis=kernel-resource-usage\]")
+
+
+def _resources(src: str, stderr: str) -> list:
+    rows, cur = [], None
+    keys = dict(RESOURCE_FIELDS)
+    for m in _REMARK.finditer(stderr):
+        k, v = m.group(1).strip(), m.group(2).strip()
+        if k == "Function Name":
+            cur = {"source": src, "kernel": v}
+            rows.append(cur)
+        elif cur is not None and k in keys:
+            cur[keys[k]] = v
+    return rows
+
+
+def _compile(src: str, sanitize: bool = False):
     out = SAN_BUILD if sanitize else BUILD
     obj = os.path.join(out, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, *(SANITIZE if sanitize else []), "-c", os.path.join(CSRC, src), "-o", obj]
+    remarks = [] if sanitize else ["-Rpass-analysis=kernel-resource-usage"]
+    cmd = [HIPCC, *FLAGS, *(SANITIZE if sanitize else []), *remarks, "-c", os.path.join(CSRC, src),
+           "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr}")
-    return obj
+    return obj, _resources(src, r.stderr)
+
+
+def _write_resources(rows: list) -> None:
+    cols = ["source", "kernel"] + [c for _, c in RESOURCE_FIELDS]
+    with open(RESOURCES + ".tmp", "w") as f:
+        f.write("\t".join(cols) + "\n")
+        for row in sorted(rows, key=lambda r: (r["source"], r["kernel"])):
+            f.write("\t".join(str(row.get(c, "")) for c in cols) + "\n")
+    os.replace(RESOURCES + ".tmp", RESOURCES)
 
 
 def build(jobs: int = 5, verbose: bool = True, sanitize: bool = False) -> str:
     os.makedirs(SAN_BUILD if sanitize else BUILD, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
-        objs = list(ex.map(lambda src: _compile(src, sanitize), SOURCES))
+        done = list(ex.map(lambda src: _compile(src, sanitize), SOURCES))
+    objs = [o for o, _ in done]
+    if not sanitize:
+        _write_resources([row for _, rows in done for row in rows])
     lib = SAN_LIB if sanitize else LIB
     tmp = lib + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *(SANITIZE if sanitize else []),
