@@ -445,14 +445,36 @@ __global__ void __launch_bounds__(kWideThreads) wgrad_wide_split_kernel(
   extern __shared__ __align__(16) char smem[];
   const int K = st->rows;
   const long long nck = (K + kWideBK - 1) / kWideBK;
+  if (nck == 0) return;  // no rows: nothing to sum (the fixup returns too)
   const long long U = (long long)total_tiles * nck;
   const int w = xcd_tile(blockIdx.x, kWgradRanges);  // this work-group's range
-  long long u = (long long)w * U / kWgradRanges;
+  const long long u0 = (long long)w * U / kWgradRanges;
   const long long u1 = (long long)(w + 1) * U / kWgradRanges;
+  // The range's segments (one per tile it touches) run with the first one
+  // last: every later segment starts at K chunk 0, and with equal range
+  // lengths the work-groups then stay within a few K chunks of each other,
+  // so tiles that share an operand panel read it from L2 together (in range
+  // order, the work-groups of an XCD sit at scattered K offsets and each
+  // streams its panels from HBM).  Each segment is summed as before.
+  const long long first_end = min(u1, (u0 / nck + 1) * nck);
+  long long v = first_end;
+  bool first_done = u0 >= first_end;
   GemmArgs unused;
-  while (u < u1) {
-    const int tile = (int)(u / nck);
-    const long long c0 = u % nck, c1 = min(nck, c0 + (u1 - u));
+  for (;;) {
+    long long a, b;
+    if (v < u1) {
+      a = v;
+      b = min(u1, (v / nck + 1) * nck);
+      v = b;
+    } else if (!first_done) {
+      a = u0;
+      b = first_end;
+      first_done = true;
+    } else {
+      break;
+    }
+    const int tile = (int)(a / nck);
+    const long long c0 = a % nck, c1 = c0 + (b - a);
     int m0, n0;
     const WgradProblem pr = wgrad_tile<T>(probs, n_probs, tile, &m0, &n0);
     WideCompute<T, false, false> wc;
@@ -465,7 +487,6 @@ __global__ void __launch_bounds__(kWideThreads) wgrad_wide_split_kernel(
     wide_epilogue<T, EPI_WGRAD_OUT>(wc.acc, unused, dst, whole ? m0 : 0, whole ? n0 : 0,
                                     whole ? pr.M : T::BM, whole ? pr.N : T::BN, smem,
                                     opaque_thread_index());
-    u += c1 - c0;
     __syncthreads();  // the epilogue's LDS before the next tile's staging
   }
 }
