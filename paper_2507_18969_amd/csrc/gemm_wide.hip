@@ -21,13 +21,29 @@ constexpr int kWideBK = 64;
 constexpr int kWideLds = kWideBK + 8;  // LDS row stride (bf16): 144 bytes
 
 // LDS element offset of the 16-byte chunk `chunk` (8 k values) of tile row
-// `row`: chunks are XOR-swizzled by the row's group of 8, so that eight
-// consecutive lanes hit distinct banks both when they read one chunk of
-// eight consecutive rows (MFMA operands), when they write eight chunks of
-// one row (K-major staging) and when they write one chunk of rows eight
-// apart (the transposed staging of the other layout).
+// `row` (rows of 144 bytes).  gfx950's LDS serves a 16-byte access 16 lanes
+// at a time over 64 four-byte banks, so a pass is conflict-free when its 16
+// lanes hit 16 distinct 16-byte bank groups; the row stride is 9 groups.
+// * Tiles staged K-major: no swizzle.  MFMA operand reads (16 consecutive
+//   rows at one chunk: 9 r mod 16) and the staging stores (kmajor_row: rows
+//   r and r + 8, 8 chunks each, 8 groups apart) are both conflict-free.
+// * Tiles staged from the other layout (8 x 8 blocks transposed in
+//   registers): chunks XOR-swizzled by the row's group of 8, which leaves
+//   2-way conflicts on a 64-bank LDS.  A conflict-free placement needs either
+//   a lane map whose global loads read 8 k rows of 128 bytes instead of 2
+//   runs of 512 bytes (slower for the HBM-bound weight gradients) or a
+//   swizzle that changes with the fragment index (more address registers).
+template <bool KMAJOR>
 __device__ __forceinline__ int wide_lds_off(int row, int chunk) {
+  if constexpr (KMAJOR) return row * kWideLds + 8 * chunk;
   return row * kWideLds + 8 * (chunk ^ ((row >> 3) & 7));
+}
+
+// Tile row of 16-byte vector v in the K-major staging (chunk v & 7): lanes
+// 8q .. 8q + 7 take one row's 8 chunks, and the two rows of a 16-lane pass
+// are 8 apart.
+__device__ __forceinline__ int kmajor_row(int v) {
+  return 16 * (v >> 7) + ((v >> 4) & 7) + 8 * ((v >> 3) & 1);
 }
 
 // Global -> registers -> LDS staging of one [ROWS x 64] operand tile, stored
@@ -39,6 +55,7 @@ __device__ __forceinline__ int wide_lds_off(int row, int chunk) {
 // lim0 / lim1.
 template <int ROWS, bool KMAJOR>
 struct WideStage {
+  static_assert(kWideBK == 64 && ROWS % 16 == 0, "8 chunks a row, rows in groups of 16");
   static constexpr int NV = ROWS * kWideBK / 8;                     // 16-byte vectors
   static constexpr int NBLK = (ROWS / 8) * (kWideBK / 8);           // 8 x 8 blocks
   static constexpr int VPT = (NV + kWideThreads - 1) / kWideThreads;
@@ -52,7 +69,7 @@ struct WideStage {
 #pragma unroll
       for (int p = 0; p < VPT; ++p) {
         const int v = threadIdx.x + p * kWideThreads;
-        const int i = v / (kWideBK / 8), kq = v % (kWideBK / 8);
+        const int i = kmajor_row(v), kq = v & 7;
         const int gk = k0 + kq * 8;
         const bool second = i >= half;
         const int grow = second ? base1 + (i - half) : base0 + i;
@@ -84,8 +101,7 @@ struct WideStage {
       for (int p = 0; p < VPT; ++p) {
         const int v = threadIdx.x + p * kWideThreads;
         if (v >= NV) continue;
-        const int i = v / (kWideBK / 8), kq = v % (kWideBK / 8);
-        *(uint4*)(lds + wide_lds_off(i, kq)) = r[p];
+        *(uint4*)(lds + wide_lds_off<true>(kmajor_row(v), v & 7)) = r[p];
       }
     } else {
 #pragma unroll
@@ -103,7 +119,7 @@ struct WideStage {
 #pragma unroll
           for (int t = 0; t < 4; ++t)
             o[t] = __builtin_amdgcn_perm(w[4 * (2 * t + 1) + q2], w[4 * (2 * t) + q2], sel);
-          *(uint4*)(lds + wide_lds_off(rb * 8 + j, kb)) = make_uint4(o[0], o[1], o[2], o[3]);
+          *(uint4*)(lds + wide_lds_off<false>(rb * 8 + j, kb)) = make_uint4(o[0], o[1], o[2], o[3]);
         }
       }
     }
@@ -175,11 +191,11 @@ struct WideCompute {
 #pragma unroll
         for (int i = 0; i < T::TM; ++i)
           fa[i] = __builtin_bit_cast(
-              bf16x8, *(const uint4*)(la + wide_lds_off(wm * (T::BM / T::WM) + i * 32 + lrow, ch)));
+              bf16x8, *(const uint4*)(la + wide_lds_off<AK>(wm * (T::BM / T::WM) + i * 32 + lrow, ch)));
 #pragma unroll
         for (int j = 0; j < T::TN; ++j)
           fb[j] = __builtin_bit_cast(
-              bf16x8, *(const uint4*)(lb + wide_lds_off(T::col_block(wn, j) + lrow, ch)));
+              bf16x8, *(const uint4*)(lb + wide_lds_off<BKM>(T::col_block(wn, j) + lrow, ch)));
 #pragma unroll
         for (int i = 0; i < T::TM; ++i)
 #pragma unroll
