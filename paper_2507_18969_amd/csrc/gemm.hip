@@ -82,12 +82,28 @@ __device__ __forceinline__ void transpose8x8_bf16(const uint4* in, uint4* out) {
   }
 }
 
+// 8 x 8 block b of a row-contiguous BF16 operand tile with 16 chunks of 8 k
+// (BK = 128): row block rb, chunk kb.  The 16 lanes of an LDS store pass take
+// 2 adjacent row blocks x 8 chunks: a 272-byte row is 17 16-byte bank groups,
+// so the two row blocks start 8 groups apart and the 16 stores fill all 16
+// groups of gfx950's 64-bank LDS (one row block x 16 chunks would fill 2).  A
+// wave covers 8 row blocks x 8 chunks, so each global load still reads whole
+// 128-byte lines.
+template <int ROWS>
+__device__ __forceinline__ void blk_of(int b, int& rb, int& kb) {
+  constexpr int U4 = ROWS / 16 < 4 ? ROWS / 16 : 4;  // row-block pairs a wave covers
+  const int g = b >> 4, u = (g % U4) + U4 * (g / (2 * U4)), v = (g / U4) & 1;
+  rb = 2 * u + ((b >> 3) & 1);
+  kb = 8 * v + (b & 7);
+}
+
 template <bool BF, int ROWS, int BK>
 struct Stage {
   static constexpr int VEC = BF ? 8 : 4;                 // elements per 16-byte vector
   static constexpr int NVEC = ROWS * BK / VEC;           // vectors per tile
   static constexpr int PER_THREAD = (NVEC + kThreads - 1) / kThreads;
   static constexpr int NBLK = (ROWS / 8) * (BK / 8);     // 8 x 8 blocks (BF16, row-contiguous)
+  static_assert(!BF || (BK == 128 && ROWS % 16 == 0), "blk_of: 16 chunks, row blocks in pairs");
   static constexpr int BLK_PER_THREAD = (NBLK + kThreads - 1) / kThreads;
   static constexpr int NREG = PER_THREAD > 8 * BLK_PER_THREAD ? PER_THREAD : 8 * BLK_PER_THREAD;
   static constexpr int STRIDE = BF ? (BK + 8) : (ROWS + 4);  // LDS row stride (elements)
@@ -104,7 +120,8 @@ struct Stage {
 #pragma unroll
       for (int p = 0; p < BLK_PER_THREAD; ++p) {
         const int b = threadIdx.x + p * kThreads;
-        const int kb = b / (ROWS / 8), rb = b % (ROWS / 8);
+        int rb, kb;
+        blk_of<ROWS>(b, rb, kb);
         const int gr = row0 + rb * 8;
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
@@ -140,7 +157,8 @@ struct Stage {
       for (int p = 0; p < BLK_PER_THREAD; ++p) {
         const int b = threadIdx.x + p * kThreads;
         if (b >= NBLK) continue;
-        const int kb = b / (ROWS / 8), rb = b % (ROWS / 8);
+        int rb, kb;
+        blk_of<ROWS>(b, rb, kb);
         uint4 t[8];
         transpose8x8_bf16(&reg[8 * p], t);
 #pragma unroll
