@@ -506,13 +506,26 @@ def ablation_workload(torch, E, warmup, steps, precision="bf16", ratio_bytes=102
     return out
 
 
-def source_digest():
+def source_code(text):
+    """Kernel source text without comments and whitespace (a comment edit does
+    not change the code the counter readings belong to)."""
+    import re
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
+def source_digest(read=None):
     """Digest of the kernel sources the stored counter readings belong to."""
     import hashlib
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2507_18969_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        if read is None:
+            with open(os.path.join(ROOT, "paper_2507_18969_amd", "csrc", name), "r") as f:
+                text = f.read()
+        else:
+            text = read(name)
+        h.update(source_code(text).encode())
     return h.hexdigest()[:16]
 
 

@@ -87,8 +87,9 @@ __device__ __forceinline__ void transpose8x8_bf16(const uint4* in, uint4* out) {
 // 2 adjacent row blocks x 8 chunks: a 272-byte row is 17 16-byte bank groups,
 // so the two row blocks start 8 groups apart and the 16 stores fill all 16
 // groups of gfx950's 64-bank LDS (one row block x 16 chunks would fill 2).  A
-// wave covers 8 row blocks x 8 chunks, so each global load still reads whole
-// 128-byte lines.
+// wave covers 8 row blocks x 8 chunks (ROWS >= 64; 4 x 16 at ROWS = 32), so
+// each global load reads whole 128-byte lines (half lines at ROWS = 32, as
+// before).
 template <int ROWS>
 __device__ __forceinline__ void blk_of(int b, int& rb, int& kb) {
   constexpr int U4 = ROWS / 16 < 4 ? ROWS / 16 : 4;  // row-block pairs a wave covers

@@ -11,10 +11,9 @@ namespace edpc {
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 
 // Softmax (Eq. 1) and quantised 16-bit CDF of one row, one wave per row.
-// The per-lane quadruples are vectors so that a runtime element index
-// (row_pick) selects among registers: on plain arrays the compiler turns
-// the selection into a load from a computed address and keeps the whole
-// struct in scratch memory.
+// The per-lane quadruples are vectors, so that row_cdf's runtime index
+// (the remainder's bin) is a register insert; an array indexed at run time
+// keeps the whole struct in scratch memory.
 struct RowCdf {
   f32x4 p;      // probabilities of symbols 4l .. 4l+3
   i32x4 q;      // frequencies
@@ -71,6 +70,8 @@ __device__ __forceinline__ int row_decode_symbol(const RowCdf& c, uint64_t d, ui
 __device__ __forceinline__ void row_pick(const RowCdf& c, const float z[4], int x, int* cx, int* qx,
                                          float* zx) {
   const int jx = x & 3;
+  // copied out first: a choice among loads of the struct is turned into one
+  // load from a computed address, which would put the struct in scratch
   const int c0 = c.cum[0], c1 = c.cum[1], c2 = c.cum[2], c3 = c.cum[3];
   const int q0 = c.q[0], q1 = c.q[1], q2 = c.q[2], q3 = c.q[3];
   const float z0 = z[0], z1 = z[1], z2 = z[2], z3 = z[3];
