@@ -237,6 +237,22 @@ def test_bf16_update_wide_tiles(E, tile):
                  sample_rows=range(0, 300, 37), kernel_id=kid)
 
 
+# the 4-wave BF16 tiles (tile ids of the kernel configuration)
+SMALL_TILES = {"32x32": 0, "64x32": 1, "32x64": 2, "64x64": 3, "128x64": 4, "64x128": 5,
+               "128x128": 6}
+
+
+@pytest.mark.parametrize("tile", sorted(SMALL_TILES))
+def test_bf16_update_small_tiles(E, tile):
+    # every product of the layer-by-layer step on one 4-wave tile shape, so
+    # that each shape's staging of both operand layouts (the transposed 8 x 8
+    # blocks of the weight gradients and input adjoints) meets the oracle;
+    # 100 rows leave a ragged last row tile for every height
+    kid = _uniform_kernel_id(E, lib_cfg(E, MID, "bf16", layerwise=True), SMALL_TILES[tile])
+    _update_case(E, MID, rows=100, om_steps=4, wl="mid_bf16", layerwise=True,
+                 sample_rows=range(0, 100, 13), kernel_id=kid)
+
+
 PS_GATE_BWD = 6  # product slot of the gated adjoint (dP and the branch adjoints)
 
 
