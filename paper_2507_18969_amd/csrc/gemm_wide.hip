@@ -28,15 +28,18 @@ constexpr int kWideLds = kWideBK + 8;  // LDS row stride (bf16): 144 bytes
 //   rows at one chunk: 9 r mod 16) and the staging stores (kmajor_row: rows
 //   r and r + 8, 8 chunks each, 8 groups apart) are both conflict-free.
 // * Tiles staged from the other layout (8 x 8 blocks transposed in
-//   registers): chunks XOR-swizzled by the row's group of 8, which leaves
-//   2-way conflicts on a 64-bank LDS.  A conflict-free placement needs either
-//   a lane map whose global loads read 8 k rows of 128 bytes instead of 2
-//   runs of 512 bytes (slower for the HBM-bound weight gradients) or a
-//   swizzle that changes with the fragment index (more address registers).
-template <bool KMAJOR>
+//   registers, SWZ = 4): chunks XOR-swizzled by the row's group of 16.  That
+//   is constant over the 16 rows an MFMA read pass takes and spreads the
+//   transposed stores (16 lanes: one chunk of 16 row blocks of 8, i.e. 8
+//   groups of 16 rows) over all 16 bank groups.
+// * The same when both operands come from the other layout (the weight
+//   gradients, SWZ = 3): XOR by the row's group of 8, 2-way conflicted on a
+//   64-bank LDS, since the 16-row swizzle changes with the fragment index
+//   and there the extra address registers spill.
+template <int SWZ>
 __device__ __forceinline__ int wide_lds_off(int row, int chunk) {
-  if constexpr (KMAJOR) return row * kWideLds + 8 * chunk;
-  return row * kWideLds + 8 * (chunk ^ ((row >> 3) & 7));
+  if constexpr (SWZ == 0) return row * kWideLds + 8 * chunk;
+  return row * kWideLds + 8 * (chunk ^ ((row >> SWZ) & 7));
 }
 
 // Tile row of 16-byte vector v in the K-major staging (chunk v & 7): lanes
@@ -53,7 +56,7 @@ __device__ __forceinline__ int kmajor_row(int v) {
 // Tile row i maps to global row base0 + i (i < half) or base1 + i - half
 // (K-major only: the two branch matrices of the gated product), valid below
 // lim0 / lim1.
-template <int ROWS, bool KMAJOR>
+template <int ROWS, bool KMAJOR, int SWZ = 0>
 struct WideStage {
   static_assert(kWideBK == 64 && ROWS % 16 == 0, "8 chunks a row, rows in groups of 16");
   static constexpr int NV = ROWS * kWideBK / 8;                     // 16-byte vectors
@@ -101,7 +104,7 @@ struct WideStage {
       for (int p = 0; p < VPT; ++p) {
         const int v = threadIdx.x + p * kWideThreads;
         if (v >= NV) continue;
-        *(uint4*)(lds + wide_lds_off<true>(kmajor_row(v), v & 7)) = r[p];
+        *(uint4*)(lds + wide_lds_off<0>(kmajor_row(v), v & 7)) = r[p];
       }
     } else {
 #pragma unroll
@@ -119,7 +122,7 @@ struct WideStage {
 #pragma unroll
           for (int t = 0; t < 4; ++t)
             o[t] = __builtin_amdgcn_perm(w[4 * (2 * t + 1) + q2], w[4 * (2 * t) + q2], sel);
-          *(uint4*)(lds + wide_lds_off<false>(rb * 8 + j, kb)) = make_uint4(o[0], o[1], o[2], o[3]);
+          *(uint4*)(lds + wide_lds_off<SWZ>(rb * 8 + j, kb)) = make_uint4(o[0], o[1], o[2], o[3]);
         }
       }
     }
@@ -147,6 +150,9 @@ struct WideTile {
 template <class T, bool AK, bool BKM>
 struct WideCompute {
   typedef f32x16 Acc;
+  // LDS placement of each operand (see wide_lds_off)
+  static constexpr int SWA = AK ? 0 : (BKM ? 4 : 3);
+  static constexpr int SWB = BKM ? 0 : (AK ? 4 : 3);
   Acc acc[T::TM][T::TN];
 
   // A rows [m0, m0 + BM) valid below M; B rows as WideStage; k in [kb, K)
@@ -166,8 +172,8 @@ struct WideCompute {
     bf16_t* lds = (bf16_t*)smem;
     auto lds_a = [&](int s) { return lds + s * (T::LDS_A + T::LDS_B); };
     auto lds_b = [&](int s) { return lds + s * (T::LDS_A + T::LDS_B) + T::LDS_A; };
-    WideStage<T::BM, AK> sa;
-    WideStage<T::BN, BKM> sb;
+    WideStage<T::BM, AK, SWA> sa;
+    WideStage<T::BN, BKM, SWB> sb;
     const int nchunks = (K - kb + kWideBK - 1) / kWideBK;
     sa.load(A, lda, m0, M, T::BM, 0, 0, kb, K);
     sb.load(B, ldb, b0, blim0, bhalf, b1, blim1, kb, K);
@@ -191,11 +197,11 @@ struct WideCompute {
 #pragma unroll
         for (int i = 0; i < T::TM; ++i)
           fa[i] = __builtin_bit_cast(
-              bf16x8, *(const uint4*)(la + wide_lds_off<AK>(wm * (T::BM / T::WM) + i * 32 + lrow, ch)));
+              bf16x8, *(const uint4*)(la + wide_lds_off<SWA>(wm * (T::BM / T::WM) + i * 32 + lrow, ch)));
 #pragma unroll
         for (int j = 0; j < T::TN; ++j)
           fb[j] = __builtin_bit_cast(
-              bf16x8, *(const uint4*)(lb + wide_lds_off<BKM>(T::col_block(wn, j) + lrow, ch)));
+              bf16x8, *(const uint4*)(lb + wide_lds_off<SWB>(T::col_block(wn, j) + lrow, ch)));
 #pragma unroll
         for (int i = 0; i < T::TM; ++i)
 #pragma unroll
