@@ -311,6 +311,47 @@ def ragged_full_job(torch, E):
     return res
 
 
+def rows_sweep(torch, E, counts=(16, 64, 256, 1024, 2048, 4096), warmup=80, steps=400):
+    """Step time of the 1024-stream model (BF16, row-block step) against the
+    number of active streams, and the ragged job's time predicted from it: the
+    ragged mixture runs the same model while its active set shrinks, so its
+    rate follows from this curve and its row counts per step."""
+    import gen
+    w = gen.WORKLOADS["mid_bf16"]
+    cfg = lib_cfg(E, w.model, "bf16")
+    pts = []
+    for rows in counts:
+        # the workload has 1024 streams; larger sets repeat them (the step
+        # time does not depend on the bytes)
+        base, blens = gen.make_streams(w, prefix=w.model["context"] + warmup + steps + 16,
+                                       n_streams=min(rows, len(w.lens())))
+        rep = max(1, rows // len(blens))
+        data = np.tile(base.reshape(len(blens), -1), (rep, 1)).reshape(-1)
+        lens = np.tile(blens, rep)
+        d_in = torch.as_tensor(data).to("cuda")
+        enc = E.edpc_encoder_begin(cfg, d_in, lens)
+        enc.edpc_session_run(warmup)
+        done, ms, _ = time_session(torch, enc, 0, steps)
+        enc.edpc_session_destroy()
+        pts.append((int(len(lens)), ms / done))
+        log(f"rows: {len(lens)} active streams: {ms / done:.4f} ms/step")
+        del d_in
+    r = gen.WORKLOADS["ragged"]
+    ls = np.sort(r.lens())
+    active = len(ls) - np.searchsorted(ls, np.arange(int(ls[-1])), side="right")
+    t = np.interp(active, [p[0] for p in pts], [p[1] for p in pts])
+    res = {"model": w.description, "precision": "bf16",
+           "ms_per_step": {str(k): round(v, 4) for k, v in pts},
+           "MBps": {str(k): round(k / (v * 1e-3) / 1e6, 3) for k, v in pts},
+           "ragged_predicted_s": round(float(t.sum()) / 1e3, 1),
+           "ragged_time_share_at_most_1024_rows": round(float(t[active <= 1024].sum() / t.sum()), 3),
+           "ragged_byte_share_at_most_1024_rows": round(float(active[active <= 1024].sum()
+                                                              / active.sum()), 3)}
+    log(f"rows: {res}")
+    torch.cuda.empty_cache()
+    return res
+
+
 def stream_job(torch, E, chunk=4096, precision="bf16"):
     """End-to-end host-to-host rate of the 1024-stream workload: the whole
     64 MiB encoded from pinned host memory into host memory and decoded back
@@ -658,6 +699,8 @@ def run_extra(torch, E, a):
             extra[name] = stream_job(torch, E)
         elif name == "ifr":
             extra[name] = ifr_analysis(torch, E)
+        elif name == "rows":
+            extra[name] = rows_sweep(torch, E)
         else:
             extra[name] = extra_workload(torch, E, name, a.warmup, min(a.steps, 200))
     return extra
@@ -677,7 +720,7 @@ def main():
                          "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE readings)")
     ap.add_argument("--extra", default="large",
                     help="comma list of further workloads measured after the main one "
-                         "(ragged, ragged_full, large, stream, ifr, ablations; 'none' for "
+                         "(ragged, ragged_full, large, stream, ifr, ablations, rows; 'none' for "
                          "none); reported under extra_workloads.  Default: the 16384-stream "
                          "large model (encode and decode in both precisions, about 10 s)")
     ap.add_argument("--no-size-parity", action="store_true",
