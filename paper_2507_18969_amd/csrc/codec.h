@@ -80,7 +80,8 @@ struct Session {
   int rows_at(uint64_t i) const;
   int bucket(int rows) const;
   void run(uint64_t k);
-  void step_direct(uint64_t i, int grid_rows, bool explicit_step, hipStream_t st);
+  // explicit_step: step i; else step st->base + rel (rel-th step of a window)
+  void step_direct(uint64_t i, int grid_rows, bool explicit_step, hipStream_t st, int rel = 1);
   template <class T>
   T* dalloc(size_t n);
 };

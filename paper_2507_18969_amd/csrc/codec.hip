@@ -167,18 +167,22 @@ int Session::bucket(int rows) const {
   return std::min(b, (int)model->max_rows);
 }
 
-void Session::step_direct(uint64_t i, int grid_rows, bool explicit_step, hipStream_t st) {
+void Session::step_direct(uint64_t i, int grid_rows, bool explicit_step, hipStream_t st, int rel) {
   KTimer* timer = model->timer;
   StepOutputs out;
   out.update = true;
+  if (model->kc.fused) {
+    // the row-block step's first kernel forms the step state
+    const StepSched sc{sched, explicit_step ? 1 : 2, explicit_step ? (int)i : rel};
+    model->step(decoding ? MODE_DECODE : MODE_ENCODE, io, out, grid_rows, st, &sc);
+    return;
+  }
   if (timer) timer->begin(KC_SCHEDULE, st);
   k_step_schedule(model->st, sched, explicit_step ? (int)i : -1, st);
   if (timer) timer->end(st);
-  if (!model->kc.fused) {  // the fused path gathers inside its first kernel
-    if (timer) timer->begin(KC_GATHER, st);
-    k_gather(model->st, io, model->C, model->ctx, model->tgt, grid_rows, decoding, st);
-    if (timer) timer->end(st);
-  }
+  if (timer) timer->begin(KC_GATHER, st);
+  k_gather(model->st, io, model->C, model->ctx, model->tgt, grid_rows, decoding, st);
+  if (timer) timer->end(st);
   model->step(decoding ? MODE_DECODE : MODE_ENCODE, io, out, grid_rows, st);
 }
 
@@ -202,7 +206,7 @@ void Session::run(uint64_t k) {
           hipGraph_t g = nullptr;
           hip_check(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "capture");
           try {
-            for (int q = 0; q < graph_steps; ++q) step_direct(0, b, false, cap);
+            for (int q = 0; q < graph_steps; ++q) step_direct(0, b, false, cap, q + 1);
           } catch (...) {
             (void)hipStreamEndCapture(cap, &g);
             if (g) (void)hipGraphDestroy(g);

@@ -26,7 +26,7 @@ struct StepState {
   float bc1, bc2;    // Adam bias corrections 1 - beta^tau
   uint32_t tau;      // Adam step number (1 for the first update)
   int32_t model;     // 1 if the model runs this step (step >= context)
-  int32_t pad;
+  int32_t base;      // step before a captured window; its steps count from it
 };
 
 // Adam constants (Kingma & Ba 2015; lr from the configuration).

@@ -95,7 +95,12 @@ struct FusedArgs {
 // Row-block kernel before the FDM: context gather (streams) or staged
 // contexts, byte embedding, LTE down-projection (Eq. 14).
 struct FusedInArgs {
-  const StepState* st;
+  StepState* st;
+  // sched_mode 0: the step state is already set; 1: the kernel sets it for
+  // step sched_step, 2: for step st->base + sched_step (steps of a captured
+  // window), from the stream lengths in sched
+  int sched_mode, sched_step;
+  Schedule sched;
   int gather;             // 1: read the contexts from the streams; 0: use ctx / tgt as staged
   int decoding;
   StreamIO io;

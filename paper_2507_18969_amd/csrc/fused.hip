@@ -896,8 +896,18 @@ __global__ void __launch_bounds__(256) fused_in_kernel(FusedInArgs a) {
   constexpr int BM = kFusedRows, LDA = F + 8;
   __shared__ __align__(16) bf16_t sA[BM][LDA];
   __shared__ uint8_t sC[BM][256];
-  const StepState* st = a.st;
-  const int rows = st->rows;
+  StepState* st = a.st;
+  int step, rows;
+  if (a.sched_mode == 0) {
+    step = st->step;
+    rows = st->rows;
+  } else {
+    // every workgroup finds the step's rows; the first one records the step
+    // state for the later kernels (none of this launch reads st->step)
+    step = a.sched_mode == 1 ? a.sched_step : st->base + a.sched_step;
+    rows = active_rows(a.sched, step);
+    if (blockIdx.x == 0 && threadIdx.x == 0) write_step_state(st, a.sched, step, rows);
+  }
   const int r0 = blockIdx.x * BM;
   if (r0 >= rows) return;
   const int nr = min(BM, rows - r0);
@@ -912,9 +922,9 @@ __global__ void __launch_bounds__(256) fused_in_kernel(FusedInArgs a) {
         const uint32_t sidx = a.io.slot[r];
         const uint8_t* base = a.decoding ? a.io.dst : a.io.src;
         const uint64_t o = a.io.off[sidx];
-        v = base[io_at(a.io, o, (uint64_t)(st->step - C + c))];
+        v = base[io_at(a.io, o, (uint64_t)(step - C + c))];
         a.ctx[(size_t)r * C + c] = v;
-        if (!a.decoding && c == 0) a.tgt[r] = a.io.src[io_at(a.io, o, (uint64_t)st->step)];
+        if (!a.decoding && c == 0) a.tgt[r] = a.io.src[io_at(a.io, o, (uint64_t)step)];
       } else {
         v = a.ctx[(size_t)r * C + c];
       }

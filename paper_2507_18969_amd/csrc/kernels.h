@@ -50,8 +50,39 @@ struct HeadArgs {
   int want_grad;
 };
 
+// Number of streams longer than `step`, the active rows of that step (Alg. 1:
+// a stream takes part while it has bytes left).  A blockDim.x-way search of
+// the decreasing lengths; every thread of the workgroup must call it, and each
+// gets the count.
+__device__ inline int active_rows(const Schedule& sc, int step) {
+  const int64_t nt = blockDim.x, t = threadIdx.x;
+  int64_t lo = 0, hi = sc.n;  // the count lies in [lo, hi]
+  while (lo < hi) {
+    const int64_t chunk = (hi - lo + nt - 1) / nt;
+    const int64_t i = lo + t * chunk;
+    const int c = __syncthreads_count(i < hi && sc.lens_sorted[i] > (int64_t)step);
+    const int64_t nlo = c == 0 ? lo : lo + (c - 1) * chunk + 1;
+    hi = min(lo + c * chunk, hi);
+    lo = nlo;
+  }
+  return (int)lo;
+}
+
+// The step state of step `step` with `rows` active rows (one thread writes).
+__device__ inline void write_step_state(StepState* st, const Schedule& sc, int step, int rows) {
+  st->step = step;
+  st->rows = rows;
+  st->inv_rows = rows > 0 ? 1.0f / (float)rows : 0.0f;
+  st->model = step >= sc.context ? 1 : 0;
+  const uint32_t tau = step >= sc.context ? (uint32_t)(step - sc.context + 1) : 0u;
+  st->tau = tau;
+  st->bc1 = adam_bias_correction(sc.beta1, tau);
+  st->bc2 = adam_bias_correction(sc.beta2, tau);
+}
+
 // step >= 0: state for that step; step < 0: the step after st->step.
 void k_step_schedule(StepState* st, Schedule sc, int step, hipStream_t s);
+// st->step = st->base = step (the step before a window of relative steps)
 void k_step_set(StepState* st, int step, hipStream_t s);
 void k_step_explicit(StepState* st, int rows, uint32_t tau, float beta1, float beta2, hipStream_t s);
 

@@ -19,26 +19,9 @@ constexpr int kScheduleThreads = 256;
 __global__ void __launch_bounds__(kScheduleThreads) step_schedule_kernel(StepState* st, Schedule sc,
                                                                          int step) {
   if (step < 0) step = st->step + 1;
-  const int64_t t = threadIdx.x;
-  int64_t lo = 0, hi = sc.n;  // the count lies in [lo, hi]
-  while (lo < hi) {
-    const int64_t chunk = (hi - lo + kScheduleThreads - 1) / kScheduleThreads;
-    const int64_t i = lo + t * chunk;
-    const int c = __syncthreads_count(i < hi && sc.lens_sorted[i] > (int64_t)step);
-    const int64_t nlo = c == 0 ? lo : lo + (c - 1) * chunk + 1;
-    hi = min(lo + c * chunk, hi);
-    lo = nlo;
-  }
+  const int rows = active_rows(sc, step);
   __syncthreads();  // every thread has read st->step
-  if (t != 0) return;
-  st->step = step;
-  st->rows = (int)lo;
-  st->inv_rows = lo > 0 ? 1.0f / (float)lo : 0.0f;
-  st->model = step >= sc.context ? 1 : 0;
-  const uint32_t tau = step >= sc.context ? (uint32_t)(step - sc.context + 1) : 0u;
-  st->tau = tau;
-  st->bc1 = adam_bias_correction(sc.beta1, tau);
-  st->bc2 = adam_bias_correction(sc.beta2, tau);
+  if (threadIdx.x == 0) write_step_state(st, sc, step, rows);
 }
 
 void k_step_schedule(StepState* st, Schedule sc, int step, hipStream_t s) {
@@ -46,7 +29,10 @@ void k_step_schedule(StepState* st, Schedule sc, int step, hipStream_t s) {
 }
 
 __global__ void step_set_kernel(StepState* st, int step) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) st->step = step;
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    st->step = step;
+    st->base = step;
+  }
 }
 
 void k_step_set(StepState* st, int step, hipStream_t s) {

@@ -93,6 +93,14 @@ struct KTimer {
 
 enum StepMode : int { MODE_PLAIN = 0, MODE_ENCODE = 1, MODE_DECODE = 2 };
 
+// Step state to be set inside the step: mode 1 for step `step`, mode 2 for
+// step st->base + step.
+struct StepSched {
+  Schedule sc;
+  int mode;
+  int step;
+};
+
 struct StepOutputs {
   float* probs = nullptr;
   uint32_t* cum = nullptr;
@@ -158,7 +166,7 @@ struct Model {
   FragJob* d_frag_jobs = nullptr;
   int n_frag_jobs = 0, total_frags = 0;
   FusedArgs fa;
-  FusedInArgs fin;
+  FusedInArgs fin{};
   FusedOutArgs fout;
   float* fused_emb_partial = nullptr;
   AdamJob* d_adam_jobs = nullptr;
@@ -195,8 +203,10 @@ struct Model {
   void build_tables(hipStream_t s);
   // One step on rows already staged in ctx/tgt/slot with st set; grid_rows
   // bounds the launch grids (>= st->rows).
+  // sched: when given, the row-block step's first kernel sets the step state
+  // itself (see FusedInArgs); other steps take it as already set.
   void step(StepMode mode, const StreamIO& io, const StepOutputs& out, int grid_rows,
-            hipStream_t s);
+            hipStream_t s, const StepSched* sched = nullptr);
 
   void product(int ps, int j, int R, hipStream_t s);
   void setup_fused(hipStream_t s);

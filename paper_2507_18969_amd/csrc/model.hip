@@ -746,7 +746,7 @@ const float* Model::block_input(int j) const {
 }
 
 void Model::step(StepMode mode, const StreamIO& io, const StepOutputs& out, int grid_rows,
-                 hipStream_t s) {
+                 hipStream_t s, const StepSched* sched) {
   TraceRange range(kc.fused ? "step (row-block)" : "step (layer by layer)");
   const int R = grid_rows;
   last_rows = grid_rows;
@@ -773,6 +773,11 @@ void Model::step(StepMode mode, const StreamIO& io, const StepOutputs& out, int 
     fi.gather = mode == MODE_PLAIN ? 0 : 1;
     fi.decoding = mode == MODE_DECODE ? 1 : 0;
     fi.io = io;
+    if (sched) {  // the step state is formed here, not by a launch of its own
+      fi.sched = sched->sc;
+      fi.sched_mode = sched->mode;
+      fi.sched_step = sched->step;
+    }
     TIMED(KC_EMBED, hip_check(launch_fused_in(F, L, fi, R, s), "fused in launch"));
     TIMED(KC_FDM_FWD, k_fdm_fwd(st, X1, U, slot, L, L, Y32, Y16, R, s));  // Eq. 15
     // LTE up .. head .. coder .. adjoint back to dY, one workgroup per 16 rows
