@@ -11,6 +11,7 @@
 #pragma once
 #include "common.h"
 #include "kernels.h"
+#include "adam.h"
 
 namespace edpc {
 
@@ -32,24 +33,6 @@ struct FragJob {
 };
 void k_build_frags(const FragJob* jobs, int n_jobs, int total_frags, hipStream_t s);
 
-// Adam over the shared parameters fused with the fragment-copy refresh:
-// matrix jobs are walked in 32 x 64 tiles (rows a multiple of 32, columns a
-// multiple of 64), the other tensors in items of 256 elements; one
-// workgroup per item.  The gradient of an element-range job may be formed
-// here from per-row-block partials (bias, LayerNorm and embedding
-// gradients): the sum over the step's row blocks in block order.
-constexpr int kAdamTileRows = 32;
-constexpr int kAdamTileCols = 64;
-constexpr int kAdamVecItem = 256;
-struct AdamJob {
-  size_t off;        // element offset in the flat parameter buffers
-  int rows, cols;    // matrix (cols > 0) or element range (cols == 0, rows = count)
-  uint4* nt;         // fragment copies (matrix jobs)
-  uint4* nn;
-  const float* red;  // element-range jobs: partials of element 0 of row block 0, or null
-  int red_ld;        // stride between row blocks in red
-  int item_begin;    // first work item of this job
-};
 void k_adam_frags(const StepState* st, const AdamJob* jobs, int n_jobs, int total_items,
                   float* p, float* g, float* m, float* v, AdamCfg ac, hipStream_t s);
 

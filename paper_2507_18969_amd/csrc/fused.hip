@@ -67,44 +67,6 @@ __device__ __forceinline__ void transpose8x8(const uint4* in, uint4* out) {
   }
 }
 
-// Adam (Kingma & Ba 2015, bias-corrected) on 8 consecutive parameters with
-// gradients gv; the updated values are returned in out.
-__device__ __forceinline__ void adam8(float* pp, const float gv[8], float* mp, float* vp, float lr_bc,
-                                      float inv_bc2, const AdamCfg& ac, float out[8]) {
-  typedef float f4 __attribute__((ext_vector_type(4)));
-  float4 p4[2], m4[2], v4[2];
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    p4[h] = ((const float4*)pp)[h];
-    const f4 mv = __builtin_nontemporal_load((const f4*)mp + h);  // moments: once per step
-    const f4 vv = __builtin_nontemporal_load((const f4*)vp + h);
-    m4[h] = make_float4(mv.x, mv.y, mv.z, mv.w);
-    v4[h] = make_float4(vv.x, vv.y, vv.z, vv.w);
-  }
-  float* P = (float*)p4;
-  float* M = (float*)m4;
-  float* V = (float*)v4;
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    M[k] = ac.beta1 * M[k] + (1.0f - ac.beta1) * gv[k];
-    V[k] = ac.beta2 * V[k] + (1.0f - ac.beta2) * gv[k] * gv[k];
-    P[k] = P[k] - lr_bc * M[k] / (sqrtf(V[k] * inv_bc2) + ac.eps);
-    out[k] = P[k];
-  }
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    ((float4*)pp)[h] = p4[h];
-    __builtin_nontemporal_store(f4{m4[h].x, m4[h].y, m4[h].z, m4[h].w}, (f4*)mp + h);
-    __builtin_nontemporal_store(f4{v4[h].x, v4[h].y, v4[h].z, v4[h].w}, (f4*)vp + h);
-  }
-}
-
-__device__ __forceinline__ void load8(const float* q, float out[8]) {
-  const float4 a = ((const float4*)q)[0], b = ((const float4*)q)[1];
-  out[0] = a.x; out[1] = a.y; out[2] = a.z; out[3] = a.w;
-  out[4] = b.x; out[5] = b.y; out[6] = b.z; out[7] = b.w;
-}
-
 // One workgroup per work item: a 32 x 64 tile of a matrix (one thread per
 // row chunk of 8; the nt copy is written straight from registers, the nn copy
 // after a transpose through LDS) or 256 elements of another tensor.
@@ -125,21 +87,7 @@ __global__ void __launch_bounds__(256) adam_frags_kernel(const StepState* __rest
   const int t = threadIdx.x;
   float gv[8], nv[8];
   if (jb.cols == 0) {  // element range, one element a thread
-    const int e = local * kAdamVecItem + t;
-    if (e >= jb.rows) return;
-    const size_t o = jb.off + e;
-    float gr;
-    if (jb.red) {
-      gr = ordered_sum(jb.red + e, (size_t)jb.red_ld, (st->rows + kFusedRows - 1) / kFusedRows);
-      g[o] = gr;
-    } else {
-      gr = g[o];
-    }
-    const float mm = ac.beta1 * m[o] + (1.0f - ac.beta1) * gr;
-    const float vv = ac.beta2 * v[o] + (1.0f - ac.beta2) * gr * gr;
-    p[o] -= lr_bc * mm / (sqrtf(vv * inv_bc2) + ac.eps);
-    m[o] = mm;
-    v[o] = vv;
+    adam_elements(st, jb, local, p, g, m, v, ac, lr_bc, inv_bc2);
     return;
   }
   const int tiles_c = jb.cols / kAdamTileCols;
@@ -149,10 +97,7 @@ __global__ void __launch_bounds__(256) adam_frags_kernel(const StepState* __rest
   const size_t o = jb.off + (size_t)row * jb.cols + col;
   load8(g + o, gv);
   adam8(p + o, gv, m + o, v + o, lr_bc, inv_bc2, ac, nv);
-  const uint4 pk = make_uint4((uint32_t)f2bf(nv[0]) | ((uint32_t)f2bf(nv[1]) << 16),
-                              (uint32_t)f2bf(nv[2]) | ((uint32_t)f2bf(nv[3]) << 16),
-                              (uint32_t)f2bf(nv[4]) | ((uint32_t)f2bf(nv[5]) << 16),
-                              (uint32_t)f2bf(nv[6]) | ((uint32_t)f2bf(nv[7]) << 16));
+  const uint4 pk = pack_bf16x8(nv);
   // nt fragment (nb = row/16, kb = col/32), lane = row%16 + 16*((col%32)/8)
   st_global16(jb.nt + ((size_t)(row >> 4) * (jb.cols / 32) + (col >> 5)) * 64 + (row & 15) +
                   16 * ((col & 31) >> 3), pk);

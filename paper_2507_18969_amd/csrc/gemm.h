@@ -14,6 +14,7 @@
 // atomics: results are identical run to run for a given configuration.
 #pragma once
 #include "common.h"
+#include "adam.h"
 
 namespace edpc {
 
@@ -52,6 +53,23 @@ struct WgradProblem {
   float* dw;         // [M, N]
   int M, N;
   int tiles_n, tile_begin;  // tiles of this problem start at tile_begin
+  // Adam launch only: the BF16 fragment copies of the weight, nt (16-row
+  // blocks, 32 columns deep) and nn (16-column blocks, 32 rows deep)
+  uint4* nt;
+  uint4* nn;
+};
+
+// Adam applied by the weight-gradient launch itself (the row-block step's
+// update): each tile, once its sum over rows is complete, writes its
+// gradient to dw, updates the parameters at the same offset of p (dw - g),
+// their moments m and v, and rewrites both fragment copies.
+struct WgradAdam {
+  float* g;  // base of the gradient buffer that every dw points into
+  float *p, *m, *v;
+  AdamCfg ac;
+  int tiles;  // work-groups past the tiles run element-range Adam items:
+  const AdamJob* ejobs;  // jobs with cols == 0 (biases, LayerNorm, embedding)
+  int n_ejobs;
 };
 
 // Work-group -> tile order for a launch of `total` tiles numbered row-major
@@ -111,6 +129,13 @@ hipError_t launch_gemm(int tile, bool bf16, bool a_kmajor, bool b_kmajor, EpiKin
 // one work-group per tile.
 hipError_t launch_wgrad(int tile, bool bf16, const WgradProblem* d_probs, int n_probs,
                         int total_tiles, const StepState* st, float* part, hipStream_t s);
+// The same weight gradients with Adam in the epilogue (4-wave tiles only;
+// M and N multiples of 32, the shared weights of the row-block step), plus
+// elem_items work-groups of element-range Adam (ad.ejobs).  Returns
+// hipErrorInvalidValue for other tiles.
+hipError_t launch_wgrad_adam(int tile, const WgradProblem* d_probs, int n_probs, int total_tiles,
+                             int elem_items, const StepState* st, const WgradAdam& ad,
+                             hipStream_t s);
 // Wide tiles (gemm_wide.hip), reached through the two launchers above.
 hipError_t launch_gemm_wide(int tile, bool a_kmajor, bool b_kmajor, EpiKind epi, int nb,
                             const GemmArgs& g, int grid_m_max, hipStream_t s);

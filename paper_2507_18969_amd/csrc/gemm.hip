@@ -361,12 +361,31 @@ __global__ void __launch_bounds__(kThreads) gemm_kernel(GemmArgs g) {
       }
 }
 
-template <bool BF, class T>
+// LDS of the Adam epilogue: the FP32 gradient tile, then its BF16 copy.
+template <class T>
+struct WgradAdamLds {
+  static constexpr int LDG = T::BN + 4, LDT = T::BN + 8;
+  static constexpr int BYTES = T::BM * LDG * 4 + T::BM * LDT * 2;
+};
+
+template <bool BF, class T, bool ADAM>
 __global__ void __launch_bounds__(kThreads) wgrad_kernel(const WgradProblem* __restrict__ probs,
-                                                         int n_probs, const StepState* st) {
+                                                         int n_probs, const StepState* st,
+                                                         WgradAdam ad) {
   typedef TileCompute<BF, T, false, false, 1> TC;
   extern __shared__ __align__(16) char smem[];
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  if constexpr (ADAM) {
+    if ((int)blockIdx.x >= ad.tiles) {  // an element-range Adam item
+      const int it = blockIdx.x - ad.tiles;
+      int j = 0;
+      while (j + 1 < ad.n_ejobs && it >= ad.ejobs[j + 1].item_begin) ++j;
+      const AdamJob jb = ad.ejobs[j];
+      adam_elements(st, jb, it - jb.item_begin, ad.p, ad.g, ad.m, ad.v, ad.ac, ad.ac.lr / st->bc1,
+                    1.0f / st->bc2);
+      return;
+    }
+  }
+  const int tile = xcd_tile(blockIdx.x, ADAM ? ad.tiles : (int)gridDim.x);
   int p = 0;
   while (p + 1 < n_probs && tile >= probs[p + 1].tile_begin) ++p;
   const WgradProblem pr = probs[p];
@@ -377,16 +396,102 @@ __global__ void __launch_bounds__(kThreads) wgrad_kernel(const WgradProblem* __r
   tc.run(pr.dout, pr.M, pr.in, pr.N, 0, pr.M, pr.N, K, m0, n0, smem);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave >> 1, wn = wave & 1;
+  if constexpr (!ADAM) {
 #pragma unroll
-  for (int i = 0; i < T::TM; ++i)
+    for (int i = 0; i < T::TM; ++i)
 #pragma unroll
-    for (int j = 0; j < T::TN; ++j)
+      for (int j = 0; j < T::TN; ++j)
 #pragma unroll
-      for (int r = 0; r < TC::Op::NACC; ++r) {
-        const int m = m0 + (wm * T::TM + i) * T::MB + acc_row<T::MB>(r, lane);
-        const int n = n0 + (wn * T::TN + j) * T::MB + acc_col<T::MB>(lane);
-        if (m < pr.M && n < pr.N) gl(pr.dw)[(long long)m * pr.N + n] = tc.acc[0][i][j][r];
+        for (int r = 0; r < TC::Op::NACC; ++r) {
+          const int m = m0 + (wm * T::TM + i) * T::MB + acc_row<T::MB>(r, lane);
+          const int n = n0 + (wn * T::TN + j) * T::MB + acc_col<T::MB>(lane);
+          if (m < pr.M && n < pr.N) gl(pr.dw)[(long long)m * pr.N + n] = tc.acc[0][i][j][r];
+        }
+  } else {
+    // The tile's sum over rows is complete: Adam on its parameters.  Each
+    // thread takes items of 8 consecutive columns of a row (16-byte
+    // accesses; the nt fragment copy straight from registers).  The loads of
+    // up to 4 items are issued together, the first group before the gradient
+    // is staged through LDS; the nn copy is read back transposed from a BF16
+    // tile.
+    typedef WgradAdamLds<T> LD;
+    constexpr int CH = T::BN / 8;
+    constexpr int ITEMS = T::BM * CH;
+    constexpr int PER = (ITEMS + kThreads - 1) / kThreads;
+    constexpr int GR = PER < 4 ? PER : 4;
+    static_assert(PER % GR == 0, "item groups");
+    float* sG = (float*)smem;
+    bf16_t* sT = (bf16_t*)(smem + T::BM * LD::LDG * 4);
+    const float lr_bc = ad.ac.lr / st->bc1;
+    const float inv_bc2 = 1.0f / st->bc2;
+    const size_t base = (size_t)(pr.dw - ad.g);  // element offset of the matrix
+#pragma unroll
+    for (int q0 = 0; q0 < PER; q0 += GR) {
+      float P[GR][8], Mo[GR][8], V[GR][8];
+      size_t o[GR];
+      bool ok[GR];
+      int rl[GR], cl[GR];
+#pragma unroll
+      for (int k = 0; k < GR; ++k) {
+        const int idx = (int)threadIdx.x + (q0 + k) * kThreads;
+        rl[k] = idx / CH;
+        cl[k] = 8 * (idx - rl[k] * CH);
+        ok[k] = idx < ITEMS && m0 + rl[k] < pr.M && n0 + cl[k] < pr.N;
+        // an item outside the matrix loads its element 0 and stores nothing
+        o[k] = ok[k] ? (size_t)(m0 + rl[k]) * pr.N + n0 + cl[k] : 0;
+        adam8_load(ad.p + base + o[k], ad.m + base + o[k], ad.v + base + o[k], P[k], Mo[k], V[k]);
       }
+      if (q0 == 0) {
+        __syncthreads();  // every wave's last operand reads are done
+#pragma unroll
+        for (int i = 0; i < T::TM; ++i)
+#pragma unroll
+          for (int j = 0; j < T::TN; ++j)
+#pragma unroll
+            for (int r = 0; r < TC::Op::NACC; ++r) {
+              const int ml = (wm * T::TM + i) * T::MB + acc_row<T::MB>(r, lane);
+              const int nl = (wn * T::TN + j) * T::MB + acc_col<T::MB>(lane);
+              sG[ml * LD::LDG + nl] = tc.acc[0][i][j][r];
+            }
+        __syncthreads();
+      }
+#pragma unroll
+      for (int k = 0; k < GR; ++k) {
+        if (!ok[k]) continue;
+        float gv[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) gv[e] = sG[rl[k] * LD::LDG + cl[k] + e];
+        float4* gp = (float4*)(pr.dw + o[k]);
+        gp[0] = make_float4(gv[0], gv[1], gv[2], gv[3]);
+        gp[1] = make_float4(gv[4], gv[5], gv[6], gv[7]);
+        adam8_math(P[k], Mo[k], V[k], gv, lr_bc, inv_bc2, ad.ac);
+        adam8_store(ad.p + base + o[k], ad.m + base + o[k], ad.v + base + o[k], P[k], Mo[k], V[k]);
+        const uint4 pk = pack_bf16x8(P[k]);
+        const int row = m0 + rl[k], col = n0 + cl[k];
+        // nt fragment (nb = row/16, kb = col/32), lane = row%16 + 16*((col%32)/8)
+        st_global16(pr.nt + ((size_t)(row >> 4) * (pr.N / 32) + (col >> 5)) * 64 + (row & 15) +
+                        16 * ((col & 31) >> 3),
+                    pk);
+        *(uint4*)&sT[rl[k] * LD::LDT + cl[k]] = pk;
+      }
+    }
+    __syncthreads();
+    // nn fragment (nb = col/16, kb = row/32), lane = col%16 + 16*((row%32)/8):
+    // 8 consecutive rows of one column
+    for (int idx = threadIdx.x; idx < (T::BM / 8) * T::BN; idx += kThreads) {
+      const int rb = idx / T::BN, cl = idx - rb * T::BN;
+      const int row = m0 + 8 * rb, col = n0 + cl;
+      if (row >= pr.M || col >= pr.N) continue;
+      uint32_t w[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        w[k] = (uint32_t)sT[(8 * rb + 2 * k) * LD::LDT + cl] |
+               ((uint32_t)sT[(8 * rb + 2 * k + 1) * LD::LDT + cl] << 16);
+      st_global16(pr.nn + ((size_t)(col >> 4) * (pr.M / 32) + (row >> 5)) * 64 + (col & 15) +
+                      16 * ((row & 31) >> 3),
+                  make_uint4(w[0], w[1], w[2], w[3]));
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -467,9 +572,49 @@ static hipError_t launch_w(const WgradProblem* d_probs, int n_probs, int total_t
                            const StepState* st, hipStream_t s) {
   typedef TileCompute<BF, T, false, false, 1> TC;
   if (total_tiles == 0) return hipSuccess;
-  hipLaunchKernelGGL((wgrad_kernel<BF, T>), dim3(total_tiles), dim3(kThreads), TC::smem_bytes(), s,
-                     d_probs, n_probs, st);
+  hipLaunchKernelGGL((wgrad_kernel<BF, T, false>), dim3(total_tiles), dim3(kThreads),
+                     TC::smem_bytes(), s, d_probs, n_probs, st, WgradAdam{});
   return hipGetLastError();
+}
+
+template <class T>
+static hipError_t launch_wa(const WgradProblem* d_probs, int n_probs, int wgs,
+                            const StepState* st, const WgradAdam& ad, hipStream_t s) {
+  typedef TileCompute<true, T, false, false, 1> TC;
+  if (wgs == 0) return hipSuccess;
+  constexpr int smem = TC::smem_bytes() > WgradAdamLds<T>::BYTES ? TC::smem_bytes()
+                                                                  : WgradAdamLds<T>::BYTES;
+  static_assert(smem <= 160 * 1024, "tile does not fit in LDS");
+  static_assert(T::BM % 32 == 0 && T::BN % 8 == 0, "Adam epilogue tile shape");
+  if constexpr (smem > 64 * 1024) {
+    static bool done = false;
+    if (!done) {
+      hipError_t e = hipFuncSetAttribute((const void*)wgrad_kernel<true, T, true>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, smem);
+      if (e != hipSuccess) return e;
+      done = true;
+    }
+  }
+  hipLaunchKernelGGL((wgrad_kernel<true, T, true>), dim3(wgs), dim3(kThreads), smem, s, d_probs,
+                     n_probs, st, ad);
+  return hipGetLastError();
+}
+
+hipError_t launch_wgrad_adam(int tile, const WgradProblem* p, int n, int tt, int elem_items,
+                             const StepState* st, const WgradAdam& ad_in, hipStream_t s) {
+  WgradAdam ad = ad_in;
+  ad.tiles = tt;
+  const int wgs = tt + elem_items;
+  switch (tile) {
+    case TILE_32x32: return launch_wa<T32x32>(p, n, wgs, st, ad, s);
+    case TILE_64x32: return launch_wa<T64x32>(p, n, wgs, st, ad, s);
+    case TILE_32x64: return launch_wa<T32x64>(p, n, wgs, st, ad, s);
+    case TILE_64x64: return launch_wa<T64x64>(p, n, wgs, st, ad, s);
+    case TILE_128x64: return launch_wa<T128x64>(p, n, wgs, st, ad, s);
+    case TILE_64x128: return launch_wa<T64x128>(p, n, wgs, st, ad, s);
+    case TILE_128x128: return launch_wa<T128x128>(p, n, wgs, st, ad, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 template <bool BF>

@@ -151,6 +151,8 @@ struct Model {
   struct WgTable {
     WgradProblem* d = nullptr;
     int n = 0, tiles = 0;
+    std::vector<WgradProblem> host;
+    WgradProblem* d_adam = nullptr;  // row-block step: the same with fragment copies (Adam launch)
   } wg_tab[TILE_COUNT];
   float* wg_part = nullptr;  // scratch of the balanced wide-tile weight-gradient launch
   size_t wg_part_floats = 0;
@@ -171,6 +173,9 @@ struct Model {
   float* fused_emb_partial = nullptr;
   AdamJob* d_adam_jobs = nullptr;
   int n_adam_jobs = 0, adam_items = 0;
+  // the element-range jobs alone (the matrices take Adam in the weight-gradient launch)
+  AdamJob* d_adam_elem_jobs = nullptr;
+  int n_adam_elem_jobs = 0, adam_elem_items = 0;
   float* fused_colpart = nullptr;
   ColsumJob* d_fcs = nullptr;
   int n_fcs = 0, fcs_cols = 0;

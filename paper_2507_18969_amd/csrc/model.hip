@@ -366,7 +366,7 @@ void Model::build_tables(hipStream_t s) {
     const TileShape ts = tile_shape(tile);
     int tiles = 0;
     auto addw = [&](const void* dout, const void* in, float* dw, int Mo, int Ni) {
-      WgradProblem p;
+      WgradProblem p{};
       p.dout = dout;
       p.in = in;
       p.dw = dw;
@@ -394,6 +394,7 @@ void Model::build_tables(hipStream_t s) {
     WgTable& t = wg_tab[tile];
     t.n = (int)wg.size();
     t.tiles = tiles;
+    t.host = wg;
     t.d = dalloc<WgradProblem>(wg.size());
     hip_check(hipMemcpyAsync(t.d, wg.data(), wg.size() * sizeof(WgradProblem),
                              hipMemcpyHostToDevice, s), "copy");
@@ -509,6 +510,7 @@ void Model::setup_fused(hipStream_t s) {
       a.nn = fj.nn;
       a.red = nullptr;
       a.red_ld = 0;
+      a.red_block = kFusedRows;
       a.item_begin = items;
       if (fj.rows % kAdamTileRows || fj.cols % kAdamTileCols)
         fail(EDPC_E_UNSUPPORTED, "matrix shape of the fused step's Adam tiles");
@@ -527,6 +529,7 @@ void Model::setup_fused(hipStream_t s) {
       a.nt = a.nn = nullptr;
       a.red = nullptr;
       a.red_ld = 0;
+      a.red_block = kFusedRows;
       a.item_begin = items;
       items += (a.rows + kAdamVecItem - 1) / kAdamVecItem;
       aj.push_back(a);
@@ -653,6 +656,38 @@ void Model::setup_fused(hipStream_t s) {
   d_adam_jobs = dalloc<AdamJob>(aj.size());
   hip_check(hipMemcpyAsync(d_adam_jobs, aj.data(), aj.size() * sizeof(AdamJob),
                            hipMemcpyHostToDevice, s), "copy");
+  {  // the element-range jobs alone, and weight-gradient tables that apply Adam
+    std::vector<AdamJob> ae;
+    int items = 0;
+    for (AdamJob a : aj) {
+      if (a.cols != 0) continue;
+      a.item_begin = items;
+      items += (a.rows + kAdamVecItem - 1) / kAdamVecItem;
+      ae.push_back(a);
+    }
+    n_adam_elem_jobs = (int)ae.size();
+    adam_elem_items = items;
+    d_adam_elem_jobs = dalloc<AdamJob>(ae.size());
+    hip_check(hipMemcpyAsync(d_adam_elem_jobs, ae.data(), ae.size() * sizeof(AdamJob),
+                             hipMemcpyHostToDevice, s), "copy");
+    for (int tile = 0; tile < TILE_W128x128; ++tile) {
+      std::vector<WgradProblem> wp = wg_tab[tile].host;
+      bool ok = !wp.empty();
+      for (WgradProblem& p : wp) {
+        p.nt = p.nn = nullptr;
+        for (const FragMat& fm : frag_mats)
+          if (p.dw == grad + fm.off && fm.rows == p.M && fm.cols == p.N) {
+            p.nt = const_cast<uint4*>(fm.nt);
+            p.nn = const_cast<uint4*>(fm.nn);
+          }
+        if (!p.nt || p.M % 32 || p.N % 32) ok = false;
+      }
+      if (!ok) continue;
+      wg_tab[tile].d_adam = dalloc<WgradProblem>(wp.size());
+      hip_check(hipMemcpyAsync(wg_tab[tile].d_adam, wp.data(), wp.size() * sizeof(WgradProblem),
+                               hipMemcpyHostToDevice, s), "copy");
+    }
+  }
   fout.colpart_cols = cols;
   fout.off_b1 = off_b1;
   build_frags(s);
@@ -793,6 +828,18 @@ void Model::step(StepMode mode, const StreamIO& io, const StepOutputs& out, int 
     TIMED(KC_FDM_BWD, k_fdm_bwd(st, X1, dY, U, mU, vU, out.keep_fdm_grad ? dUkeep : nullptr, slot,
                                 L, L, ac, out.update, dX1_32, dX1_16, R, s));
     TIMED(KC_EMB_GRAD, hip_check(launch_fused_out(F, L, fout, R, s), "fused out launch"));
+    const int wt = kc.tile[PS_WGRAD];
+    if (out.update && wt < TILE_W128x128 && wg_tab[wt].d_adam) {
+      // each weight tile takes Adam and its fragment rewrite as soon as its
+      // gradient is summed; work-groups past the tiles take the biases,
+      // LayerNorm and embedding (their partials are complete by now)
+      const WgTable& t = wg_tab[wt];
+      const WgradAdam ad{grad, param, m, v, ac, 0, d_adam_elem_jobs, n_adam_elem_jobs};
+      TIMED(PS_WGRAD, hip_check(launch_wgrad_adam(wt, t.d_adam, t.n, t.tiles, adam_elem_items, st,
+                                                  ad, s),
+                                "wgrad launch"));
+      return;
+    }
     product(PS_WGRAD, 0, R, s);
     if (out.update) {
       // Adam fused with the refresh of the fragment copies and with the sums

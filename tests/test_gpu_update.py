@@ -253,6 +253,23 @@ def test_bf16_update_small_tiles(E, tile):
                  sample_rows=range(0, 100, 13), kernel_id=kid)
 
 
+PS_WGRAD = 10  # product slot of the weight gradients
+
+
+@pytest.mark.parametrize("tile", sorted(SMALL_TILES) + ["w128x128"])
+def test_bf16_fused_update_wgrad_tiles(E, tile):
+    # the row-block step with its weight-gradient launch on one tile shape.
+    # On a 4-wave tile that launch also takes Adam and the rewrite of both
+    # fragment copies in its epilogue; on a wide tile the matrices take Adam
+    # in the pass over all parameters instead.  40 rows: two full row blocks
+    # and a ragged one.
+    t = SMALL_TILES.get(tile, WIDE_TILES.get(tile))
+    kid = E.Model(lib_cfg(E, MID, "bf16"), 40, 40).edpc_model_kernel_id()
+    assert (kid >> 47) & 1, "the 1024-stream model's BF16 default is the row-block step"
+    kid = (kid & ~(0xF << (4 * PS_WGRAD))) | (t << (4 * PS_WGRAD))
+    _update_case(E, MID, rows=40, om_steps=8, wl="mid_bf16", kernel_id=kid)
+
+
 PS_GATE_BWD = 6  # product slot of the gated adjoint (dP and the branch adjoints)
 
 
