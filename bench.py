@@ -41,7 +41,7 @@ MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3}  # dense MFMA peaks of MI355X
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_mid_1024x64KiB.txt")
 KERNEL_TIMING_STEPS = 64
 KERNEL_SOURCES = ["fused.hip", "fused.h", "kernels.hip", "kernels.h", "common.h", "head_row.h",
-                  "rangecoder.h"]
+                  "rangecoder.h", "adam.h", "gemm.h", "gemm.hip"]
 
 
 def log(msg):
