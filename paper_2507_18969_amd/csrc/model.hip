@@ -172,6 +172,9 @@ KernelConfig Model::default_config(const edpc_config& c, size_t rows) {
   k.fused = !(c.flags & EDPC_CFG_LAYERWISE) && c.precision == EDPC_BF16 && rows <= (1u << 20) &&
             !(c.flags & (EDPC_CFG_NO_LTE | EDPC_CFG_LOW_RANK)) &&
             fused_supported(F, L, H, (int)c.branches, (int)c.blocks);
+  // the row-block step's update applies Adam in the epilogue of a 4-wave
+  // weight-gradient tile; a wide tile would need a separate Adam pass
+  if (k.fused && k.tile[PS_WGRAD] >= TILE_W128x128) k.tile[PS_WGRAD] = TILE_64x128;
   return k;
 }
 
@@ -948,6 +951,9 @@ void Model::autotune(hipStream_t s) {
       const TileShape sh = tile_shape(t);
       if (!wide_tile_supported(t, bf16, epi, nb)) continue;
       if (ps != PS_WGRAD && sh.bm > 2 * R && t != TILE_32x32) continue;
+      // row-block step: only the 4-wave tiles take Adam in their epilogue (the
+      // trials time the products alone, which cannot show that saving)
+      if (ps == PS_WGRAD && kc.fused && t >= TILE_W128x128) continue;
       kc.tile[ps] = t;
       product(ps, 0, R, s);  // warm-up (first launch may set attributes)
       hip_check(hipEventRecord(e0, s), "event");
