@@ -33,6 +33,9 @@ struct FragJob {
 };
 void k_build_frags(const FragJob* jobs, int n_jobs, int total_frags, hipStream_t s);
 
+// Adam over the jobs' parameters in one launch (adam.h).  The row-block
+// step's update takes this pass only when its weight gradients run on a wide
+// tile; on a 4-wave tile the weight-gradient launch applies Adam itself.
 void k_adam_frags(const StepState* st, const AdamJob* jobs, int n_jobs, int total_items,
                   float* p, float* g, float* m, float* v, AdamCfg ac, hipStream_t s);
 
