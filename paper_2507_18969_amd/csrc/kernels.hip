@@ -600,9 +600,15 @@ __global__ void __launch_bounds__(256) emb_grad_partial_kernel(
     const StepState* __restrict__ st, const uint8_t* __restrict__ ctx, const float* __restrict__ dx,
     int C, int chunk_rows, int sub_rows, float* __restrict__ partial) {
   // dEmb_chunk[v][e] = sum over the chunk's (row, position) pairs of
-  // [ctx = v] * dX[row][position*E + e]: an FP32 MFMA product whose A operand
-  // (the one-hot of the context bytes) is formed in registers.  Wave w owns
-  // byte values 64w .. 64w+63; pairs are visited in row-major order.
+  // [ctx = v] * dX[row][position*E + e]: a matrix product on the BF16 MFMA
+  // whose A operand, the one-hot of the context bytes, is formed in registers
+  // (exact in BF16).  An FP32 value x is the exact sum of three BF16 values
+  // (x rounded to 8 significant bits, then the rounding errors of what is
+  // left), so dX enters as three BF16 operands accumulated in FP32: an FP32
+  // sum of the same terms, 3 MFMA instructions per 32 pairs where the FP32
+  // MFMA (K = 4) takes 8.
+  // Wave w owns byte values 64w .. 64w+63; pairs are visited in row-major
+  // order, 32 per step.
   extern __shared__ float smem_f[];
   float* lds_dx = smem_f;                                            // [sub_rows][F]
   uint8_t* lds_ctx = (uint8_t*)(smem_f + (size_t)sub_rows * C * E);  // [sub_rows][C]
@@ -624,28 +630,69 @@ __global__ void __launch_bounds__(256) emb_grad_partial_kernel(
     for (int k = threadIdx.x; k < nr * F / 4; k += 256) ((float4*)lds_dx)[k] = src[k];
     for (int k = threadIdx.x; k < nr * C; k += 256) lds_ctx[k] = ctx[(size_t)rs * C + k];
     __syncthreads();
-    // pairs p = i C + c in row-major order, 4 per MFMA step; C is a multiple
-    // of 4, so a step stays inside row i and p / C, p % C follow incrementally
+    // lane group g = lane / 16 takes pairs p0 .. p0 + 7 of each 32-pair step;
+    // pairs past the chunk's end take no byte value and a zero dX
     const int np = nr * C;
-    int pi = 0, pc = 0;
-    for (int k0 = 0; k0 < np; k0 += 4) {
-      const int p = k0 + (lane >> 4);
-      const int v = (int)lds_ctx[p];
-      const float* d = lds_dx + (size_t)pi * F + (pc + (lane >> 4)) * E + (lane & 15);
-      pc += 4;
-      if (pc == C) {
-        pc = 0;
-        ++pi;
+    for (int k0 = 0; k0 < np; k0 += 32) {
+      const int p0 = k0 + 8 * (lane >> 4);
+      int off[8];  // LDS offset of each pair's dX, or -1
+      uint32_t bytes[8];
+      if (C % 8 == 0) {  // the 8 pairs lie in one row: all valid or none
+        const bool live = p0 < np;
+        const int pr = live ? p0 / C : 0, pc = live ? p0 - pr * C : 0;
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+          off[v] = live ? pr * F + (pc + v) * E : -1;
+          bytes[v] = live ? (uint32_t)lds_ctx[p0 + v] : 0xFFFFu;
+        }
+      } else {
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+          const int p = p0 + v;
+          const int pr = p / C;
+          off[v] = p < np ? pr * F + (p - pr * C) * E : -1;
+          bytes[v] = p < np ? (uint32_t)lds_ctx[p] : 0xFFFFu;
+        }
       }
-      float b[NE];
 #pragma unroll
-      for (int nb = 0; nb < NE; ++nb) b[nb] = d[16 * nb];
+      for (int nb = 0; nb < NE; ++nb) {
+        const float* d = lds_dx + 16 * nb + (lane & 15);
+        uint32_t hi[4], mid[4], lo[4];
 #pragma unroll
-      for (int vb = 0; vb < 4; ++vb) {
-        const float a = (v == 64 * w + 16 * vb + (lane & 15)) ? 1.0f : 0.0f;
+        for (int h = 0; h < 4; ++h) {
+          uint32_t ph = 0, pm = 0, pl = 0;
 #pragma unroll
-        for (int nb = 0; nb < NE; ++nb)
-          acc[vb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[nb], acc[vb][nb], 0, 0, 0);
+          for (int u = 0; u < 2; ++u) {
+            const int o = off[2 * h + u];
+            const float x = o >= 0 ? d[o] : 0.0f;
+            const bf16_t b0 = f2bf(x);
+            const float r1 = x - bf2f(b0);
+            const bf16_t b1 = f2bf(r1);
+            const bf16_t b2 = f2bf(r1 - bf2f(b1));
+            ph |= (uint32_t)b0 << (16 * u);
+            pm |= (uint32_t)b1 << (16 * u);
+            pl |= (uint32_t)b2 << (16 * u);
+          }
+          hi[h] = ph;
+          mid[h] = pm;
+          lo[h] = pl;
+        }
+        const bf16x8 bh = __builtin_bit_cast(bf16x8, make_uint4(hi[0], hi[1], hi[2], hi[3]));
+        const bf16x8 bm = __builtin_bit_cast(bf16x8, make_uint4(mid[0], mid[1], mid[2], mid[3]));
+        const bf16x8 bl = __builtin_bit_cast(bf16x8, make_uint4(lo[0], lo[1], lo[2], lo[3]));
+#pragma unroll
+        for (int vb = 0; vb < 4; ++vb) {
+          const uint32_t me = (uint32_t)(64 * w + 16 * vb + (lane & 15));
+          uint32_t q[4];
+#pragma unroll
+          for (int h = 0; h < 4; ++h)
+            q[h] = (bytes[2 * h] == me ? 0x3F80u : 0u) |
+                   ((bytes[2 * h + 1] == me ? 0x3F80u : 0u) << 16);
+          const bf16x8 a = __builtin_bit_cast(bf16x8, make_uint4(q[0], q[1], q[2], q[3]));
+          acc[vb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bh, acc[vb][nb], 0, 0, 0);
+          acc[vb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bm, acc[vb][nb], 0, 0, 0);
+          acc[vb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bl, acc[vb][nb], 0, 0, 0);
+        }
       }
     }
   }

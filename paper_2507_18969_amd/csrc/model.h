@@ -41,7 +41,7 @@ enum ProductSlot : int {
 
 // Kernel configuration: one tile id per product slot, plus the numerics
 // revision of the kernels.  Encoded into 64 bits for the container.
-constexpr uint32_t kNumericsRevision = 5;
+constexpr uint32_t kNumericsRevision = 6;
 struct KernelConfig {
   int tile[PS_COUNT];
   bool fused = false;  // BF16 row-block fused step (bit 47 of the id)
