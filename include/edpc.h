@@ -239,8 +239,9 @@ void edpc_model_destroy(edpc_model* m);
 
 /* The same with an explicit kernel configuration: `kernel_id` is the 64-bit
  * id a container records (tile shape per matrix product, 4 bits per product
- * slot; bit 47 the BF16 row-block fused step; bits 48.. the numerics
- * revision), so that a model can run the summation orders of a given
+ * slot; bit 47 the BF16 row-block fused step; bit 46 the layer-by-layer
+ * step's LayerNorm adjoint with its column sums folded in; bits 48.. the
+ * numerics revision), so that a model can run the summation orders of a given
  * container, or a chosen tile everywhere.  0 picks the default.  An id of
  * another numerics revision, an unknown tile, or a tile or fused step the
  * model's shape and precision cannot run is EDPC_E_UNSUPPORTED. */

@@ -20,7 +20,9 @@ namespace edpc {
 //   52  f32 lr, beta1, beta2, eps
 //   68  u64 seed
 //   76  u64 kernel configuration id: 4 bits of tile choice per product slot,
-//           bit 47 the BF16 row-block fused step, bits 48.. the numerics revision
+//           bit 47 the BF16 row-block fused step, bit 46 the LayerNorm adjoint
+//           with its column sums (layer-by-layer step), bits 48.. the numerics
+//           revision
 //   84  u32 device architecture (950 for gfx950)
 //   88  u32 reserved (0)
 //   92  per stream: u64 length, u64 payload length, u32 CRC-32 of the bytes

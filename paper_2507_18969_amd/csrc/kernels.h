@@ -98,9 +98,17 @@ void k_fdm_bwd(const StepState* st, const float* x1, const float* dy, float* U, 
                bool update, float* dx1_32, bf16_t* dx1_16, int max_rows, hipStream_t s);
 void k_ln_fwd(const StepState* st, const float* h, const float* gamma, const float* beta, int F,
               float* z32, bf16_t* z16, float* mean, float* rstd, int max_rows, hipStream_t s);
+// LayerNorm adjoint (Eq. 9) plus the residual adjoint dh_next.  With `part`
+// (only where ln_bwd_folds(F)) it also forms, per group of kLnFoldRows rows in
+// row order, the column sums of the block's LayerNorm affine gradients and of
+// dh_next (the gradient of the output bias of the block before): part[group]
+// holds [beta | gamma | dh_next] sums, 3F floats.
+constexpr int kLnFoldRows = 16;
+bool ln_bwd_folds(int F);
+size_t ln_fold_part_elems(int max_rows, int F);
 void k_ln_bwd(const StepState* st, const float* h, const float* mean, const float* rstd,
               const float* gamma, const float* dz, const float* dh_next, int F, float* dh32,
-              bf16_t* dh16, int max_rows, hipStream_t s);
+              bf16_t* dh16, float* part, int max_rows, hipStream_t s);
 void k_head(const StepState* st, HeadArgs a, StreamIO io, int max_rows, hipStream_t s);
 
 // Column sums over the active rows (bias and LayerNorm gradients, loss).
@@ -114,6 +122,12 @@ struct ColsumJob {
   int col_block_begin; // first 64-column block of this job
   int col_offset;      // first column of this job in the partial buffer
   float scale;         // 0: scale by 1/rows
+  // sums formed elsewhere (the LayerNorm adjoint's row groups): the job's
+  // column c is the in-order sum of part[k * part_ld + c] over the
+  // ceil(rows / part_rows) groups, and the first pass skips the job (such
+  // jobs follow the others, with col_block_begin past the first pass's grid)
+  const float* part;
+  int part_ld, part_rows;
 };
 size_t colsum_partial_elems(int max_rows, int total_cols);
 void k_colsum(const StepState* st, const ColsumJob* jobs, int n_jobs, int total_blocks,

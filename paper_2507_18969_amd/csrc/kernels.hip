@@ -460,9 +460,95 @@ __global__ void __launch_bounds__(256) ln_bwd_reg_kernel(
   }
 }
 
+// The LayerNorm adjoint with the column sums folded in.  The 4 waves of a
+// workgroup share each row (thread t takes columns t, t + 256, ...), so a
+// thread's share of the column sums over the group's rows stays in CPT x 3
+// registers; the row statistics of the adjoint are summed over the 4 waves
+// through LDS, in wave order.  Rows r0 .. r0 + kLnFoldRows - 1 in order.
+template <int CPT>
+__global__ void __launch_bounds__(256) ln_bwd_fold_kernel(
+    const StepState* __restrict__ st, const float* __restrict__ h, const float* __restrict__ mean,
+    const float* __restrict__ rstd, const float* __restrict__ gamma, const float* __restrict__ dz,
+    const float* __restrict__ dh_next, float* __restrict__ dh32, bf16_t* __restrict__ dh16,
+    float* __restrict__ part) {
+  constexpr int F = 256 * CPT;
+  __shared__ float red[2][4][2];  // per-row wave partials, alternating by row
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int rows = st->rows;
+  const int r0 = blockIdx.x * kLnFoldRows;
+  if (r0 >= rows) return;
+  const int r1 = min(rows, r0 + kLnFoldRows);
+  float gm[CPT], sb[CPT], sg[CPT], so[CPT];
+#pragma unroll
+  for (int u = 0; u < CPT; ++u) {
+    gm[u] = gamma[t + 256 * u];
+    sb[u] = sg[u] = so[u] = 0.f;
+  }
+  for (int r = r0; r < r1; ++r) {
+    const int buf = (r - r0) & 1;
+    const float mu = mean[r], rs = rstd[r];
+    float xh[CPT], d[CPT], dn[CPT];
+    float s1 = 0.f, s2 = 0.f;
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+      const size_t o = (size_t)r * F + t + 256 * u;
+      xh[u] = (h[o] - mu) * rs;
+      d[u] = dz[o];
+      dn[u] = dh_next[o];
+      const float dx = d[u] * gm[u];
+      s1 += dx;
+      s2 += dx * xh[u];
+    }
+    s1 = wave_sum(s1);
+    s2 = wave_sum(s2);
+    if (lane == 0) {
+      red[buf][w][0] = s1;
+      red[buf][w][1] = s2;
+    }
+    // (the next row's barrier keeps the row after next from rewriting
+    // red[buf] before every thread has read it)
+    __syncthreads();
+    const float m1 = ((red[buf][0][0] + red[buf][1][0]) + (red[buf][2][0] + red[buf][3][0])) / (float)F;
+    const float m2 = ((red[buf][0][1] + red[buf][1][1]) + (red[buf][2][1] + red[buf][3][1])) / (float)F;
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+      const size_t o = (size_t)r * F + t + 256 * u;
+      const float dx = d[u] * gm[u];
+      const float v = dn[u] + rs * (dx - m1 - xh[u] * m2);
+      dh32[o] = v;
+      if (dh16) dh16[o] = f2bf(v);
+      sb[u] += d[u];
+      sg[u] += d[u] * xh[u];
+      so[u] += dn[u];
+    }
+  }
+  float* pg = part + (size_t)blockIdx.x * 3 * F;
+#pragma unroll
+  for (int u = 0; u < CPT; ++u) {
+    pg[t + 256 * u] = sb[u];
+    pg[F + t + 256 * u] = sg[u];
+    pg[2 * F + t + 256 * u] = so[u];
+  }
+}
+
+bool ln_bwd_folds(int F) { return F == 256 || F == 512 || F == 1024 || F == 2048; }
+
+size_t ln_fold_part_elems(int max_rows, int F) {
+  return (size_t)((max_rows + kLnFoldRows - 1) / kLnFoldRows) * 3 * (size_t)F;
+}
+
 void k_ln_bwd(const StepState* st, const float* h, const float* mean, const float* rstd,
               const float* gamma, const float* dz, const float* dh_next, int F, float* dh32,
-              bf16_t* dh16, int max_rows, hipStream_t s) {
+              bf16_t* dh16, float* part, int max_rows, hipStream_t s) {
+  if (part && ln_bwd_folds(F)) {
+    const dim3 g(blocks_for(max_rows, kLnFoldRows)), b(256);
+    switch (F / 256) {
+      case 1: hipLaunchKernelGGL(ln_bwd_fold_kernel<1>, g, b, 0, s, st, h, mean, rstd, gamma, dz, dh_next, dh32, dh16, part); return;
+      case 2: hipLaunchKernelGGL(ln_bwd_fold_kernel<2>, g, b, 0, s, st, h, mean, rstd, gamma, dz, dh_next, dh32, dh16, part); return;
+      case 4: hipLaunchKernelGGL(ln_bwd_fold_kernel<4>, g, b, 0, s, st, h, mean, rstd, gamma, dz, dh_next, dh32, dh16, part); return;
+      case 8: hipLaunchKernelGGL(ln_bwd_fold_kernel<8>, g, b, 0, s, st, h, mean, rstd, gamma, dz, dh_next, dh32, dh16, part); return;
+    }
+  }
   const dim3 g(blocks_for(max_rows, 4)), b(256);
   switch (F % 256 == 0 ? F / 256 : 0) {
     case 1: hipLaunchKernelGGL(ln_bwd_reg_kernel<1>, g, b, 0, s, st, h, mean, rstd, gamma, dz, dh_next, dh32, dh16); return;
@@ -562,8 +648,14 @@ __global__ void colsum_reduce_kernel(const StepState* __restrict__ st,
   int j = 0;
   while (j + 1 < n_jobs && c >= jobs[j + 1].col_offset) ++j;
   const ColsumJob& jb = jobs[j];
-  const int nch = (st->rows + chunk - 1) / chunk;
-  const float s = ordered_sum(partial + c, (size_t)total_cols, nch);
+  float s;
+  if (jb.part) {
+    const int ng = (st->rows + jb.part_rows - 1) / jb.part_rows;
+    s = ordered_sum(jb.part + (c - jb.col_offset), (size_t)jb.part_ld, ng);
+  } else {
+    const int nch = (st->rows + chunk - 1) / chunk;
+    s = ordered_sum(partial + c, (size_t)total_cols, nch);
+  }
   gl(jb.dst)[c - jb.col_offset] = s * (jb.scale == 0.0f ? st->inv_rows : jb.scale);
 }
 

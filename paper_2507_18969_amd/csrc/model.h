@@ -41,10 +41,11 @@ enum ProductSlot : int {
 
 // Kernel configuration: one tile id per product slot, plus the numerics
 // revision of the kernels.  Encoded into 64 bits for the container.
-constexpr uint32_t kNumericsRevision = 6;
+constexpr uint32_t kNumericsRevision = 7;
 struct KernelConfig {
   int tile[PS_COUNT];
   bool fused = false;  // BF16 row-block fused step (bit 47 of the id)
+  bool ln_fold = false;  // layer-by-layer step: LayerNorm adjoint with its column sums (bit 46)
   uint64_t encode() const;
   static bool decode(uint64_t id, KernelConfig* out);
 };
@@ -159,6 +160,7 @@ struct Model {
   ColsumJob* d_cs = nullptr;
   int n_cs = 0, cs_blocks = 0, cs_cols = 0;
   float* cs_partial = nullptr;
+  std::vector<float*> ln_part;  // LayerNorm adjoint's row-group column sums, per block (or empty)
   ColsumJob* d_loss_job = nullptr;
   float* loss_partial = nullptr;
   int emb_chunk = 16, emb_sub = 16;

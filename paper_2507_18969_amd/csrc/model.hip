@@ -22,14 +22,16 @@ uint64_t KernelConfig::encode() const {
   uint64_t id = (uint64_t)kNumericsRevision << 48;
   for (int i = 0; i < PS_COUNT; ++i) id |= (uint64_t)(tile[i] & 15) << (4 * i);
   if (fused) id |= 1ull << 47;
+  if (ln_fold) id |= 1ull << 46;
   return id;
 }
 
 bool KernelConfig::decode(uint64_t id, KernelConfig* out) {
-  static_assert(4 * PS_COUNT <= 47, "tile ids overlap the fused bit");
+  static_assert(4 * PS_COUNT <= 46, "tile ids overlap the flag bits");
   if ((id >> 48) != kNumericsRevision) return false;
-  if ((id >> (4 * PS_COUNT)) & ((1ull << (47 - 4 * PS_COUNT)) - 1)) return false;
+  if ((id >> (4 * PS_COUNT)) & ((1ull << (46 - 4 * PS_COUNT)) - 1)) return false;
   out->fused = ((id >> 47) & 1) != 0;
+  out->ln_fold = ((id >> 46) & 1) != 0;
   for (int i = 0; i < PS_COUNT; ++i) {
     const int t = (int)((id >> (4 * i)) & 15);
     if (t >= TILE_COUNT) return false;
@@ -175,6 +177,9 @@ KernelConfig Model::default_config(const edpc_config& c, size_t rows) {
   // the row-block step's update applies Adam in the epilogue of a 4-wave
   // weight-gradient tile; a wide tile would need a separate Adam pass
   if (k.fused && k.tile[PS_WGRAD] >= TILE_W128x128) k.tile[PS_WGRAD] = TILE_64x128;
+  // from 4096 rows the LayerNorm adjoint forms its block's column sums itself
+  // (16 rows a workgroup in turn); below that its workgroups would be too few
+  k.ln_fold = !k.fused && c.blocks > 0 && ln_bwd_folds(F) && rows >= 4096;
   return k;
 }
 
@@ -207,6 +212,8 @@ Model::Model(const edpc_config& c, size_t nslots, size_t rows, const KernelConfi
   lte = !(c.flags & EDPC_CFG_NO_LTE) && !low_rank;
   if (kc.fused && !(bf16 && lte && fused_supported(F, L, H, K, N) && rows <= (1u << 20)))
     fail(EDPC_E_UNSUPPORTED, "fused step requested for an unsupported shape");
+  if (kc.ln_fold && (kc.fused || N == 0 || !ln_bwd_folds(F)))
+    fail(EDPC_E_UNSUPPORTED, "LayerNorm adjoint with column sums requested for an unsupported shape");
 
   // Flat layout of the shared parameters; each tensor starts 64-aligned.
   auto add = [&](const std::string& n, size_t numel, uint32_t tid, double bound) {
@@ -410,11 +417,15 @@ void Model::build_tables(hipStream_t s) {
     wg_part = dalloc<float>(wg_part_floats);
   }
 
-  // column sums: bias gradients, LayerNorm affine gradients
+  // column sums: bias gradients, LayerNorm affine gradients.  Where the
+  // LayerNorm adjoint folds them in (kernel configuration bit 46), each block's beta, gamma
+  // and output-bias sums come from its row-group partials; those jobs follow
+  // the others, past the first pass's grid.
   std::vector<ColsumJob> cs;
+  const bool fold = kc.ln_fold;
   auto addc = [&](const float* src, int cols, int ld, float* dst, const float* h,
                   const float* mu, const float* rs) {
-    ColsumJob j;
+    ColsumJob j{};
     j.src = src;
     j.h = h;
     j.mean = mu;
@@ -432,21 +443,44 @@ void Model::build_tables(hipStream_t s) {
   addc(dz32, 256, 256, G_("bh"), nullptr, nullptr, nullptr);
   for (int j = 0; j < N; ++j) {
     const std::string b = "blk" + std::to_string(j);
-    addc(dH32[j + 1], F, F, G_(b + ".bo"), nullptr, nullptr, nullptr);
+    if (!fold) addc(dH32[j + 1], F, F, G_(b + ".bo"), nullptr, nullptr, nullptr);
     addc(dA32[j], K * H, K * H, G_(b + ".b0"), nullptr, nullptr, nullptr);
-    addc(dZ[j], F, F, G_("ln" + std::to_string(j) + ".beta"), nullptr, nullptr, nullptr);
-    addc(dZ[j], F, F, G_("ln" + std::to_string(j) + ".gamma"), Hs[j], mean[j], rstd[j]);
+    if (!fold) {
+      addc(dZ[j], F, F, G_("ln" + std::to_string(j) + ".beta"), nullptr, nullptr, nullptr);
+      addc(dZ[j], F, F, G_("ln" + std::to_string(j) + ".gamma"), Hs[j], mean[j], rstd[j]);
+    }
   }
   if (lte) {
     addc(dH32[0], F, F, G_("b2"), nullptr, nullptr, nullptr);
     addc(dX1_32, L, L, G_("b1"), nullptr, nullptr, nullptr);
+  }
+  ln_part.assign(fold ? N : 0, nullptr);
+  if (fold) {
+    for (int j = 0; j < N; ++j) {
+      ln_part[j] = dalloc<float>(ln_fold_part_elems((int)max_rows, F));
+      const std::string b = "blk" + std::to_string(j), ln = "ln" + std::to_string(j);
+      float* dsts[3] = {G_(ln + ".beta"), G_(ln + ".gamma"), G_(b + ".bo")};
+      for (int q = 0; q < 3; ++q) {
+        ColsumJob jb{};
+        jb.dst = dsts[q];
+        jb.cols = F;
+        jb.col_block_begin = cs_blocks;  // past the first pass's grid
+        jb.col_offset = cs_cols;
+        cs_cols += F;
+        jb.scale = 1.0f;
+        jb.part = ln_part[j] + (size_t)q * F;
+        jb.part_ld = 3 * F;
+        jb.part_rows = kLnFoldRows;
+        cs.push_back(jb);
+      }
+    }
   }
   n_cs = (int)cs.size();
   d_cs = dalloc<ColsumJob>(cs.size());
   cs_partial = dalloc<float>(colsum_partial_elems((int)max_rows, cs_cols));
   hip_check(hipMemcpyAsync(d_cs, cs.data(), cs.size() * sizeof(ColsumJob), hipMemcpyHostToDevice, s),
             "copy");
-  ColsumJob lj;
+  ColsumJob lj{};
   lj.src = loss_rows;
   lj.h = nullptr;
   lj.mean = lj.rstd = nullptr;
@@ -884,7 +918,8 @@ void Model::step(StepMode mode, const StreamIO& io, const StepOutputs& out, int 
     product(PS_GATE_BWD, j, R, s);
     product(PS_DZ, j, R, s);
     TIMED(KC_LN_BWD, k_ln_bwd(st, Hs[j], mean[j], rstd[j], P_(ln + ".gamma"), dZ[j],
-                              dH32[j + 1], F, dH32[j], bf16 ? dH16[j] : nullptr, R, s));
+                              dH32[j + 1], F, dH32[j], bf16 ? dH16[j] : nullptr,
+                              ln_part.empty() ? nullptr : ln_part[j], R, s));
   }
   if (lte) product(PS_LTE_UP_BWD, 0, R, s);
   // low rank: dy = B_s dx'', dB_s = y (x) dx'' (B before its update), Adam on B_s

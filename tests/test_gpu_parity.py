@@ -87,7 +87,7 @@ def test_initial_parameters_bit_identical(E):
 
 
 def _step_case(E, model, precision, rows, pos, om_steps=0, n_slots=None, prefix=None, wl="small",
-               **over):
+               kernel_id=0, **over):
     data, lens = gen.make_streams(wl, prefix=prefix or (pos + 1), n_streams=rows)
     st = np.frombuffer(data.tobytes(), dtype=np.uint8).reshape(rows, -1)
     C = model["context"]
@@ -98,7 +98,7 @@ def _step_case(E, model, precision, rows, pos, om_steps=0, n_slots=None, prefix=
         om.step(st[:, i - C:i].astype(np.int64), st[:, i].astype(np.int64), np.arange(rows))
     om.round_to_f32()
     cfg = lib_cfg(E, model, precision, **over)
-    m = E.Model(cfg, n_slots or rows, rows)
+    m = E.Model(cfg, n_slots or rows, rows, kernel_id)
     if om_steps:
         load_oracle_state(m, om)
     ctx = st[:, pos - C:pos]
@@ -342,7 +342,7 @@ def test_autotuned_encode_roundtrip(E):
     cfg = lib_cfg(E, SMALL, autotune=True)
     cont = _encode(E, cfg, data, lens)
     kid = int.from_bytes(cont[76:84].cpu().numpy().tobytes(), "little")
-    assert kid >> 48 == 6  # numerics revision
+    assert kid >> 48 == 7  # numerics revision
     out, _ = E.edpc_decode(cont)
     assert out.cpu().numpy().tobytes() == data.tobytes()
 
@@ -431,6 +431,29 @@ def test_extreme_shapes_one_step_and_roundtrip(E, shape, precision):
     cont = _encode(E, lib_cfg(E, model, precision), flat, lens)
     out, _ = E.edpc_decode(cont)
     assert out.cpu().numpy().tobytes() == flat.tobytes()
+
+
+LN_FOLD = 1 << 46  # kernel configuration bit: LayerNorm adjoint with its column sums
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_layernorm_adjoint_with_column_sums(E, precision):
+    # the layer-by-layer LayerNorm adjoint that also forms its block's beta,
+    # gamma and output-bias column sums over groups of 16 rows (the default
+    # from 4096 rows), forced on 40 rows: two full groups and a ragged one
+    cfg = lib_cfg(E, MID, precision, layerwise=True)
+    kid = E.Model(cfg, 40, 40).edpc_model_kernel_id()
+    assert not (kid >> 47) & 1 and not (kid >> 46) & 1
+    assert (E.Model(cfg, 4096, 4096).edpc_model_kernel_id() >> 46) & 1
+    om, m, ctx, tgt = _step_case(E, MID, precision, rows=40, pos=MID["context"] + 4, om_steps=4,
+                                 prefix=MID["context"] + 5, wl="mid_bf16", kernel_id=kid | LN_FOLD,
+                                 layerwise=True)
+    assert m.edpc_model_kernel_id() == kid | LN_FOLD
+    if precision == "fp32":
+        _, g_o, dU_o = _compare_step(E, om, m, ctx, tgt, p_tol=1e-5, g_rtol=1e-4)
+        _compare_update(E, om, m, ctx, tgt, g_o, dU_o, tol=1e-6)
+    else:
+        _compare_step(E, om, m, ctx, tgt, p_tol=2e-3, g_rtol=3e-2)
 
 
 @pytest.mark.parametrize("branches", [1, 3])
