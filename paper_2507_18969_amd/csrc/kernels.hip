@@ -715,13 +715,50 @@ __global__ void __launch_bounds__(256) emb_grad_partial_kernel(
 #pragma unroll
     for (int nb = 0; nb < NE; ++nb) acc[vb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
   const int r_end = min(rows, r0 + chunk_rows);
+  // The next sub-batch of rows is loaded into registers while the current
+  // one feeds the MFMAs from LDS: up to 8192 floats of dX (8 float4 a
+  // thread) and 512 context bytes (sub_rows * C <= 8192 / E).  Wider rows
+  // (F > 8192, one row a sub-batch) are copied straight to LDS instead.
+  constexpr int kStage = 8;
+  const bool staged = sub_rows * F <= 4 * kStage * 256;
+  float4 nx[kStage];
+  uint32_t nc[2] = {0u, 0u};
+  auto fetch = [&](int rs) {
+    const int nr = min(sub_rows, r_end - rs);
+    const float4* src = (const float4*)(dx + (size_t)rs * F);
+#pragma unroll
+    for (int q = 0; q < kStage; ++q) {
+      const int k = (int)threadIdx.x + 256 * q;
+      nx[q] = k < nr * F / 4 ? src[k] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int k = (int)threadIdx.x + 256 * q;
+      nc[q] = k < nr * C ? (uint32_t)ctx[(size_t)rs * C + k] : 0u;
+    }
+  };
+  if (staged && r0 < r_end) fetch(r0);
   for (int rs = r0; rs < r_end; rs += sub_rows) {
     const int nr = min(sub_rows, r_end - rs);
+    __syncthreads();  // the previous sub-batch's LDS reads are done
+    if (staged) {
+#pragma unroll
+      for (int q = 0; q < kStage; ++q) {
+        const int k = (int)threadIdx.x + 256 * q;
+        if (k < nr * F / 4) ((float4*)lds_dx)[k] = nx[q];
+      }
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int k = (int)threadIdx.x + 256 * q;
+        if (k < nr * C) lds_ctx[k] = (uint8_t)nc[q];
+      }
+    } else {
+      const float4* src = (const float4*)(dx + (size_t)rs * F);
+      for (int k = threadIdx.x; k < nr * F / 4; k += 256) ((float4*)lds_dx)[k] = src[k];
+      for (int k = threadIdx.x; k < nr * C; k += 256) lds_ctx[k] = ctx[(size_t)rs * C + k];
+    }
     __syncthreads();
-    const float4* src = (const float4*)(dx + (size_t)rs * F);
-    for (int k = threadIdx.x; k < nr * F / 4; k += 256) ((float4*)lds_dx)[k] = src[k];
-    for (int k = threadIdx.x; k < nr * C; k += 256) lds_ctx[k] = ctx[(size_t)rs * C + k];
-    __syncthreads();
+    if (staged && rs + sub_rows < r_end) fetch(rs + sub_rows);
     // lane group g = lane / 16 takes pairs p0 .. p0 + 7 of each 32-pair step;
     // pairs past the chunk's end take no byte value and a zero dX
     const int np = nr * C;
