@@ -4,6 +4,7 @@
 namespace edpc {
 
 constexpr int kThreads = 256;  // 4 waves of 64, arranged 2 x 2 over the tile
+static_assert(kThreads == kAdamVecItem, "element-range Adam items take one thread an element");
 
 template <bool BF, int MB>
 struct Mfma;
