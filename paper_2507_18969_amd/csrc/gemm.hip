@@ -3,8 +3,9 @@
 
 namespace edpc {
 
-constexpr int kThreads = 256;  // 4 waves of 64, arranged 2 x 2 over the tile
-static_assert(kThreads == kAdamVecItem, "element-range Adam items take one thread an element");
+// 4 waves of 64, arranged 2 x 2 over the tile; also the element count of an
+// element-range Adam item (kAdamVecItem), which takes one thread an element
+constexpr int kThreads = 256;
 
 template <bool BF, int MB>
 struct Mfma;
