@@ -858,6 +858,14 @@ __global__ void __launch_bounds__(256) fused_in_kernel(FusedInArgs a) {
   const int nr = min(BM, rows - r0);
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index (uniform)
+  // the product's first batch of W1 fragments goes out before the gather, so
+  // its latency overlaps the dependent loads of the context bytes
+  constexpr int NT = L / 64;
+  int cb[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) cb[t] = w + 4 * t;
+  uint4 first[8];
+  mm_first<F, NT, 8>(a.w1_nt, cb, first);
   for (int idx = tid; idx < BM * C; idx += 256) {
     const int i = idx / C, c = idx % C;
     uint8_t v = 0;
@@ -887,15 +895,11 @@ __global__ void __launch_bounds__(256) fused_in_kernel(FusedInArgs a) {
     if (i < nr) *(ushort4*)(a.x16 + (size_t)(r0 + i) * F + f) = h;
   }
   __syncthreads();
-  constexpr int NT = L / 64;
-  int cb[NT];
   f32x4 acc[NT];
-#pragma unroll
-  for (int t = 0; t < NT; ++t) cb[t] = w + 4 * t;
   float bias[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) bias[t] = a.b1[cb[t] * 16 + (lane & 15)];
-  mm<F, NT, 8>(&sA[0][0], LDA, a.w1_nt, cb, acc);
+  mm_rest<F, NT, 8>(&sA[0][0], LDA, a.w1_nt, cb, acc, first, [] {});
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const int c = cb[t] * 16 + (lane & 15);
@@ -924,6 +928,14 @@ __global__ void __launch_bounds__(256) fused_out_kernel(FusedOutArgs a) {
   const int nr = min(BM, rows - r0);
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index (uniform)
+  // the product's first batch of W1 fragments goes out before the loads of
+  // dX' and the b1 partial, so their latencies overlap
+  constexpr int NTO = F / 64;
+  int cbo[NTO];
+#pragma unroll
+  for (int t = 0; t < NTO; ++t) cbo[t] = w + 4 * t;
+  uint4 first[8];
+  mm_first<L, NTO, 8>(a.w1_nn, cbo, first);
   for (int idx = tid; idx < BM * (L / 8); idx += 256) {
     const int i = idx / (L / 8), q = idx % (L / 8);
     uint4 v = make_uint4(0, 0, 0, 0);
@@ -944,15 +956,11 @@ __global__ void __launch_bounds__(256) fused_out_kernel(FusedOutArgs a) {
   }
   __syncthreads();
   {
-    constexpr int NT = F / 64;
-    int cb[NT];
-    f32x4 acc[NT];
+    f32x4 acc[NTO];
+    mm_rest<L, NTO, 8>(&sA[0][0], LDA, a.w1_nn, cbo, acc, first, [] {});
 #pragma unroll
-    for (int t = 0; t < NT; ++t) cb[t] = w + 4 * t;
-    mm<L, NT, 8>(&sA[0][0], LDA, a.w1_nn, cb, acc);
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const int c = cb[t] * 16 + (lane & 15);
+    for (int t = 0; t < NTO; ++t) {
+      const int c = cbo[t] * 16 + (lane & 15);
 #pragma unroll
       for (int r = 0; r < 4; ++r) sX[4 * (lane >> 4) + r][c] = acc[t][r];
     }
