@@ -174,9 +174,16 @@ KernelConfig Model::default_config(const edpc_config& c, size_t rows) {
   k.fused = !(c.flags & EDPC_CFG_LAYERWISE) && c.precision == EDPC_BF16 && rows <= (1u << 20) &&
             !(c.flags & (EDPC_CFG_NO_LTE | EDPC_CFG_LOW_RANK)) &&
             fused_supported(F, L, H, (int)c.branches, (int)c.blocks);
-  // the row-block step's update applies Adam in the epilogue of a 4-wave
-  // weight-gradient tile; a wide tile would need a separate Adam pass
-  if (k.fused && k.tile[PS_WGRAD] >= TILE_W128x128) k.tile[PS_WGRAD] = TILE_64x128;
+  // The row-block step's update applies Adam in the epilogue of a 4-wave
+  // weight-gradient tile (a wide tile would need a separate Adam pass).  That
+  // epilogue favours larger tiles over more of them: at 1024 rows of the
+  // 1024-stream model an update step took 248 us on 64 x 128 or 128 x 64
+  // tiles (224 of them) against 284 us on the 64 x 32 ones the general rule
+  // picks (896), so the rule asks for 192 tiles here.
+  if (k.fused) {
+    k.tile[PS_WGRAD] = pick_tile(rows, wg, 192, bf);
+    if (k.tile[PS_WGRAD] >= TILE_W128x128) k.tile[PS_WGRAD] = TILE_64x128;
+  }
   // from 4096 rows the LayerNorm adjoint forms its block's column sums itself
   // (16 rows a workgroup in turn); below that its workgroups would be too few
   k.ln_fold = !k.fused && c.blocks > 0 && ln_bwd_folds(F) && rows >= 4096;
