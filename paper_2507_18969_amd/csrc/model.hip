@@ -167,6 +167,36 @@ KernelConfig Model::default_config(const edpc_config& c, size_t rows) {
     wg.push_back({KH, F});
   }
   k.tile[PS_WGRAD] = pick_tile(rows, wg, 512, bf);
+  if (rows >= 4096) {
+    // Many rows: the autotuner's choices at 16384 rows of the large model,
+    // as rules of the product's shape.
+    if (bf) {
+      // weight gradients: the balanced launch of 256 x 256 tiles once that
+      // table covers every CU (0.85 against 1.21 ms per step); the output
+      // product, short in K with a residual epilogue, on more and smaller
+      // tiles (0.57 against 0.62 ms)
+      const TileShape ts = tile_shape(TILE_W256x256);
+      size_t n = 0;
+      for (auto& mn : wg) n += ((mn.first + ts.bm - 1) / ts.bm) * ((mn.second + ts.bn - 1) / ts.bn);
+      if (n >= (size_t)kWgradRanges) k.tile[PS_WGRAD] = TILE_W256x256;
+      if (H <= 512) k.tile[PS_OUT] = TILE_W128x128;
+    } else {
+      // FP32 (35.5 against 30.0 ms per step with the general rule): forward
+      // products on 128 x 128 tiles for at most 256 outputs, 64 x 64 when
+      // K <= 512, else 128 x 64; every input adjoint on 64 x 128; the
+      // weight gradients on 64 x 64
+      auto fwd = [&](int n, int kk) {
+        return n <= 256 ? TILE_128x128 : kk <= 512 ? TILE_64x64 : TILE_128x64;
+      };
+      k.tile[PS_LTE_DOWN] = fwd(L, F);
+      k.tile[PS_LTE_UP] = fwd(F, L);
+      k.tile[PS_OUT] = fwd(F, H);
+      k.tile[PS_HEAD] = fwd(256, F);
+      for (int ps : {PS_HEAD_BWD, PS_GATE_BWD, PS_DZ, PS_LTE_UP_BWD, PS_LTE_DOWN_BWD})
+        k.tile[ps] = TILE_64x128;
+      k.tile[PS_WGRAD] = TILE_64x64;
+    }
+  }
   // BF16 shapes with a row-block kernel take the fused step (one workgroup per
   // 16 rows runs LTE up .. head .. coder .. adjoint) unless EDPC_CFG_LAYERWISE
   // asks for the layer-by-layer products.  The row-block kernels index
