@@ -149,11 +149,15 @@ KernelConfig Model::default_config(const edpc_config& c, size_t rows) {
   const int F = c.context * c.embed, L = c.latent, H = c.hidden;
   const int KH = c.branches * H;
   const bool bf = c.precision == EDPC_BF16;
-  auto one = [&](int n) { return pick_tile(rows, {{0, n}}, 256, bf); };
+  // tiles wanted per product: the FP32 autotuner took 32 x 32 tiles for every
+  // product at 1024 rows of the 1024-stream model (512 of them for 512
+  // outputs), where 256 tiles would give 64 x 32 (515 against 495 us a step)
+  const size_t want = bf ? 256 : 512;
+  auto one = [&](int n) { return pick_tile(rows, {{0, n}}, want, bf); };
   k.tile[PS_LTE_DOWN] = one(L);
   k.tile[PS_LTE_UP] = one(F);
   // gated products: a wide tile's columns hold both branches of H / 2 outputs
-  k.tile[PS_GATE] = pick_tile(rows, {{0, H}}, 256, bf, EPI_GATE_FWD, (int)c.branches);
+  k.tile[PS_GATE] = pick_tile(rows, {{0, H}}, want, bf, EPI_GATE_FWD, (int)c.branches);
   k.tile[PS_OUT] = one(F);
   k.tile[PS_HEAD] = one(256);
   k.tile[PS_HEAD_BWD] = one(F);
@@ -166,7 +170,20 @@ KernelConfig Model::default_config(const edpc_config& c, size_t rows) {
     wg.push_back({F, H});
     wg.push_back({KH, F});
   }
-  k.tile[PS_WGRAD] = pick_tile(rows, wg, 512, bf);
+  // Weight gradients: fewer, larger tiles than the other products.  At 1024
+  // rows of the 1024-stream model the general rule's 512 tiles took 62 us
+  // per BF16 step against 25 us on the autotuner's choice, and 55 against 50
+  // us in FP32, whose autotuner takes 64 x 64 tiles at every size measured.
+  auto wg_tiles = [&](int t) {
+    const TileShape ts = tile_shape(t);
+    size_t n = 0;
+    for (auto& mn : wg) n += ((mn.first + ts.bm - 1) / ts.bm) * ((mn.second + ts.bn - 1) / ts.bn);
+    return n;
+  };
+  if (bf)
+    k.tile[PS_WGRAD] = pick_tile(rows, wg, 192, bf);
+  else
+    k.tile[PS_WGRAD] = wg_tiles(TILE_64x64) >= 192 ? TILE_64x64 : pick_tile(rows, wg, 512, bf);
   if (rows >= 4096) {
     // Many rows: the autotuner's choices at 16384 rows of the large model,
     // as rules of the product's shape.
@@ -175,10 +192,7 @@ KernelConfig Model::default_config(const edpc_config& c, size_t rows) {
       // table covers every CU (0.85 against 1.21 ms per step); the output
       // product, short in K with a residual epilogue, on more and smaller
       // tiles (0.57 against 0.62 ms)
-      const TileShape ts = tile_shape(TILE_W256x256);
-      size_t n = 0;
-      for (auto& mn : wg) n += ((mn.first + ts.bm - 1) / ts.bm) * ((mn.second + ts.bn - 1) / ts.bn);
-      if (n >= (size_t)kWgradRanges) k.tile[PS_WGRAD] = TILE_W256x256;
+      if (wg_tiles(TILE_W256x256) >= (size_t)kWgradRanges) k.tile[PS_WGRAD] = TILE_W256x256;
       if (H <= 512) k.tile[PS_OUT] = TILE_W128x128;
     } else {
       // FP32 (35.5 against 30.0 ms per step with the general rule): forward
@@ -194,7 +208,6 @@ KernelConfig Model::default_config(const edpc_config& c, size_t rows) {
       k.tile[PS_HEAD] = fwd(256, F);
       for (int ps : {PS_HEAD_BWD, PS_GATE_BWD, PS_DZ, PS_LTE_UP_BWD, PS_LTE_DOWN_BWD})
         k.tile[ps] = TILE_64x128;
-      k.tile[PS_WGRAD] = TILE_64x64;
     }
   }
   // BF16 shapes with a row-block kernel take the fused step (one workgroup per
@@ -209,11 +222,8 @@ KernelConfig Model::default_config(const edpc_config& c, size_t rows) {
   // epilogue favours larger tiles over more of them: at 1024 rows of the
   // 1024-stream model an update step took 248 us on 64 x 128 or 128 x 64
   // tiles (224 of them) against 284 us on the 64 x 32 ones the general rule
-  // picks (896), so the rule asks for 192 tiles here.
-  if (k.fused) {
-    k.tile[PS_WGRAD] = pick_tile(rows, wg, 192, bf);
-    if (k.tile[PS_WGRAD] >= TILE_W128x128) k.tile[PS_WGRAD] = TILE_64x128;
-  }
+  // picks for 512 tiles (896); the 192-tile rule above gives 128 x 64.
+  if (k.fused && k.tile[PS_WGRAD] >= TILE_W128x128) k.tile[PS_WGRAD] = TILE_64x128;
   // from 4096 rows the LayerNorm adjoint forms its block's column sums itself
   // (16 rows a workgroup in turn); below that its workgroups would be too few
   k.ln_fold = !k.fused && c.blocks > 0 && ln_bwd_folds(F) && rows >= 4096;
