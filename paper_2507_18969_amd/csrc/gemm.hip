@@ -100,7 +100,19 @@ __device__ __forceinline__ void blk_of(int b, int& rb, int& kb) {
   kb = 8 * v + (b & 7);
 }
 
-template <bool BF, int ROWS, int BK>
+// FP32 tiles hold an operand k-major in LDS, [BK][ROWS + PAD].  An MFMA
+// operand read takes MB consecutive rows at each of 64 / MB k values, and
+// gfx950's LDS has 64 four-byte banks, so the read is conflict-free when the
+// row stride is MB (mod 64): the k groups land on disjoint banks.  Operands
+// staged from the row-contiguous layout are stored as 16-byte row chunks,
+// conflict-free at any stride, and take that stride.  K-major operands are
+// transposed into LDS by 4-byte stores, for which a stride of 4 (mod 64)
+// spreads a wave's stores best; they keep PAD = 4.
+constexpr int fp32_lds_pad(bool kmajor, int rows, int mb) {
+  return kmajor ? 4 : ((mb - rows % 64) % 64 + 64) % 64;
+}
+
+template <bool BF, int ROWS, int BK, int PAD = 4>
 struct Stage {
   static constexpr int VEC = BF ? 8 : 4;                 // elements per 16-byte vector
   static constexpr int NVEC = ROWS * BK / VEC;           // vectors per tile
@@ -109,8 +121,9 @@ struct Stage {
   static_assert(!BF || (BK == 128 && ROWS % 16 == 0), "blk_of: 16 chunks, row blocks in pairs");
   static constexpr int BLK_PER_THREAD = (NBLK + kThreads - 1) / kThreads;
   static constexpr int NREG = PER_THREAD > 8 * BLK_PER_THREAD ? PER_THREAD : 8 * BLK_PER_THREAD;
-  static constexpr int STRIDE = BF ? (BK + 8) : (ROWS + 4);  // LDS row stride (elements)
-  static constexpr int LDS_ELEMS = BF ? ROWS * (BK + 8) : BK * (ROWS + 4);
+  static constexpr int STRIDE = BF ? (BK + 8) : (ROWS + PAD);  // LDS row stride (elements)
+  static constexpr int LDS_ELEMS = BF ? ROWS * (BK + 8) : BK * (ROWS + PAD);
+  static_assert(BF || (ROWS + PAD) % 4 == 0, "16-byte aligned FP32 rows");
   uint4 reg[NREG];
 
   // Global -> registers.  kmajor: src[row * ld + k]; else src[k * ld + row].
@@ -219,10 +232,10 @@ struct TileCompute {
   static constexpr int BK = BF ? 128 : 64;
   static constexpr int MB = T::MB, TM = T::TM, TN = T::TN;
   typedef Mfma<BF, MB> Op;
-  typedef Stage<BF, T::BM, BK> SA;
-  typedef Stage<BF, T::BN, BK> SB;
+  typedef Stage<BF, T::BM, BK, fp32_lds_pad(AK, T::BM, T::MB)> SA;
+  typedef Stage<BF, T::BN, BK, fp32_lds_pad(BKM, T::BN, T::MB)> SB;
   // two register stages unless that would hold more than 16 vectors a thread
-  static constexpr int ST = (Stage<BF, T::BM, BK>::NREG + NB * Stage<BF, T::BN, BK>::NREG) <= 16 ? 2 : 1;
+  static constexpr int ST = (SA::NREG + NB * SB::NREG) <= 16 ? 2 : 1;
   typename Op::Acc acc[NB][TM][TN];
 
   __device__ __forceinline__ void run(const void* A, int lda, const void* B, int ldb,
@@ -574,8 +587,19 @@ static hipError_t launch_w(const WgradProblem* d_probs, int n_probs, int total_t
                            const StepState* st, hipStream_t s) {
   typedef TileCompute<BF, T, false, false, 1> TC;
   if (total_tiles == 0) return hipSuccess;
-  hipLaunchKernelGGL((wgrad_kernel<BF, T, false>), dim3(total_tiles), dim3(kThreads),
-                     TC::smem_bytes(), s, d_probs, n_probs, st, WgradAdam{});
+  constexpr int smem = TC::smem_bytes();
+  static_assert(smem <= 160 * 1024, "tile does not fit in LDS");
+  if constexpr (smem > 64 * 1024) {
+    static bool done = false;
+    if (!done) {
+      hipError_t e = hipFuncSetAttribute((const void*)wgrad_kernel<BF, T, false>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, smem);
+      if (e != hipSuccess) return e;
+      done = true;
+    }
+  }
+  hipLaunchKernelGGL((wgrad_kernel<BF, T, false>), dim3(total_tiles), dim3(kThreads), smem, s,
+                     d_probs, n_probs, st, WgradAdam{});
   return hipGetLastError();
 }
 
