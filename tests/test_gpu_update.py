@@ -270,6 +270,19 @@ def test_bf16_fused_update_wgrad_tiles(E, tile):
     _update_case(E, MID, rows=40, om_steps=8, wl="mid_bf16", kernel_id=kid)
 
 
+def test_autotuner_keeps_the_row_block_weight_gradient_tile(E):
+    # the autotuner's trials time the products without the Adam epilogue the
+    # row-block step's weight-gradient tile carries, so it leaves that tile at
+    # its default (a 4-wave tile); it still tunes nothing else there
+    d = lib_cfg(E, MID, "bf16")
+    kd = E.Model(d, 1024, 1024).edpc_model_kernel_id()
+    t = lib_cfg(E, dict(MID, autotune=True), "bf16")
+    kt = E.Model(t, 1024, 1024).edpc_model_kernel_id()
+    assert (kd >> 47) & 1 and (kt >> 47) & 1
+    slot = lambda k: (k >> (4 * PS_WGRAD)) & 0xF
+    assert slot(kt) == slot(kd) and slot(kd) in SMALL_TILES.values()
+
+
 PS_GATE_BWD = 6  # product slot of the gated adjoint (dP and the branch adjoints)
 
 
